@@ -1,0 +1,171 @@
+/*
+ * hp2sph.h -- C ABI of libhp2sph: HP2SPH spherical-harmonic analysis of
+ * HEALPix maps on AMD Instinct MI355X (gfx950).
+ *
+ * The method is Algorithm 1 (HP2SPH) of Drake & Wright, "A Fast and Accurate
+ * Algorithm for Spherical Harmonic Analysis on HEALPix Grids with
+ * Applications to the Cosmic Microwave Background Radiation"
+ * (arXiv:1904.10514):
+ *   Step 1 (Sec. 3.1, eqs. upsamp, trig_expansion, interp_cond): per-ring
+ *          trigonometric interpolation by FFT;
+ *   Step 2 (Sec. 3.2, eqs. DFS, nufft2, normal_eq): double Fourier sphere and
+ *          the least-squares fit in colatitude truncated to 4 Nside + 1 modes,
+ *          with pole values from a quadratic least-squares fit to the three
+ *          rings nearest each pole;
+ *   Step 3 (Sec. 3.3): Slevinsky's conversion of the bivariate Fourier
+ *          coefficients to spherical-harmonic coefficients, order by order,
+ *          as products of Givens rotations;
+ * followed by the angular power spectrum, eq. (APS) (Sec. 1).  Conventions
+ * are those of Appendix A (eqs. ssph, sphip) with the Condon-Shortley phase
+ * and Y_l^{-m} = (-1)^m conj(Y_l^m).
+ *
+ * Band: HP2SPH yields degrees l <= p = 2 Nside (the 4 Nside + 1 colatitude
+ * modes of Sec. 3.2.2).  A plan asks for lmax <= 2 Nside per map; a smaller
+ * lmax truncates the p-band result (values for l <= lmax are unchanged).
+ *
+ * Precision modes:
+ *   HP2SPH_F64         every stage in FP64.
+ *   HP2SPH_F32_REFINE  the analysis stages run in FP32 (FP32 arithmetic and
+ *                      accumulation, FP64-built tables rounded once); then one
+ *                      step of eq. (uzawa) (Sec. 2.2) with A := HP2SPH:
+ *                      a0 = A32 f, r = f - S64 a0 (exact synthesis and the
+ *                      residual map in FP64), a1 = a0 + A32 r (FP64 add).
+ *   HP2SPH_F32         one FP32 analysis, no refinement (diagnostic).
+ *
+ * Conventions of every call:
+ *   - All functions return an int status: HP2SPH_OK (0) or a negative code;
+ *     none throws or aborts.  hp2sph_last_error() returns a thread-local
+ *     message for the last failing call on that thread.
+ *   - Device pointers are HIP device memory on the device that was current
+ *     when the plan was created; the caller owns them.  `stream` is a
+ *     hipStream_t (NULL = the default stream); work is enqueued
+ *     asynchronously on it.
+ *   - Maps: FP64, RING order (rings north to south, points of a ring with
+ *     longitude ascending from the ring's first point, eq. healpts), the maps
+ *     of a batch back to back: map b starts at sum_{b'<b} 12 nside[b']^2.
+ *   - a_lm: complex128 as interleaved (re, im) doubles, per map packed
+ *     m-major for m >= 0: index(l, m) = m (2 lmax + 1 - m) / 2 + l,
+ *     0 <= m <= l <= lmax; a_l^{-m} = (-1)^m conj(a_l^m) is implied.  The
+ *     maps of a batch back to back: map b starts at
+ *     sum_{b'<b} (lmax[b']+1)(lmax[b']+2)/2 complex entries.  16-byte aligned.
+ *   - C_l: FP64, lmax[b]+1 values per map, back to back.
+ *   - A plan is not re-entrant: two calls that share one workspace must not
+ *     overlap in time (serialise them on one stream).
+ */
+#ifndef HP2SPH_H
+#define HP2SPH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hp2sph_plan_s* hp2sph_plan_t;
+
+enum {
+    HP2SPH_F64 = 0,
+    HP2SPH_F32_REFINE = 1,
+    HP2SPH_F32 = 2
+};
+
+enum {
+    HP2SPH_OK = 0,
+    HP2SPH_EINVAL = -1,      /* bad argument (size, mode, null/misaligned pointer) */
+    HP2SPH_ENOMEM = -2,      /* host or device allocation of plan tables failed  */
+    HP2SPH_EDEVICE = -3,     /* a HIP call failed; see hp2sph_last_error()       */
+    HP2SPH_EWORKSPACE = -4,  /* workspace pointer null or misaligned             */
+    HP2SPH_ESTATE = -5       /* plan handle is null or already destroyed         */
+};
+
+/* Largest nside a plan accepts (FFT lengths and LDS budgets are sized for it). */
+#define HP2SPH_MAX_NSIDE 2048
+
+/*
+ * Create a plan for `batch` maps.  nside[b] is a power of two in
+ * [2, HP2SPH_MAX_NSIDE]; 0 <= lmax[b] <= 2 nside[b].  Maps with equal nside
+ * form one group that every stage processes in one launch.  The set-up
+ * (geometry, the colatitude least-squares solve fused with the Legendre
+ * connection, Givens angles, FFT twiddles) is built here on the host in FP64
+ * and copied to the device once; nothing of it is rebuilt per call.
+ * On success *out receives the plan (owned by the caller; free it with
+ * hp2sph_plan_destroy).  Errors: EINVAL, ENOMEM, EDEVICE.
+ */
+int hp2sph_plan_create(const int32_t* nside, const int32_t* lmax, int32_t batch,
+                       int32_t mode, hp2sph_plan_t* out);
+
+/* Device workspace (bytes) hp2sph_analyze / hp2sph_synthesize need. */
+int hp2sph_workspace_size(hp2sph_plan_t plan, size_t* bytes);
+
+/*
+ * Analysis, Algorithm 1: maps (device, FP64, read only) -> alm (device,
+ * complex128, written).  workspace: device, >= hp2sph_workspace_size bytes,
+ * 256-byte aligned, contents need not be initialised and are clobbered.
+ * Errors: EINVAL (null/misaligned maps or alm), EWORKSPACE, ESTATE, EDEVICE.
+ */
+int hp2sph_analyze(hp2sph_plan_t plan, const double* maps, double* alm,
+                   void* workspace, void* stream);
+
+/*
+ * Exact synthesis, eq. (synthesis) (Sec. 2.2): alm (device, complex128,
+ * layout as above, read only) -> maps (device, FP64, written), always in
+ * FP64, through the same stages transposed (reverse Givens sweeps,
+ * evaluation of the order-0/1 Legendre series at the ring colatitudes,
+ * inverse per-ring FFT with aliasing of |m| >= n/2 onto the ring's modes).
+ * This is the S of the refinement round; it is exposed as the next step the
+ * paper names in Sec. 5.  Errors as for hp2sph_analyze.
+ */
+int hp2sph_synthesize(hp2sph_plan_t plan, const double* alm, double* maps,
+                      void* workspace, void* stream);
+
+/*
+ * Angular power spectrum, eq. (APS): C_l = (|a_l^0|^2 + 2 sum_{m=1}^{l}
+ * |a_l^m|^2) / (2l+1) per map, FP64 accumulation in a fixed order (results
+ * are bitwise reproducible).  alm device (read), cl device (written).
+ * Errors: EINVAL, ESTATE, EDEVICE.
+ */
+int hp2sph_power_spectrum(hp2sph_plan_t plan, const double* alm, double* cl,
+                          void* stream);
+
+/* Free the plan's device tables and host state.  ESTATE for a null plan. */
+int hp2sph_plan_destroy(hp2sph_plan_t plan);
+
+/* Thread-local text of the last error on the calling thread ("" if none). */
+const char* hp2sph_last_error(void);
+
+/*
+ * Host-only inspection of the set-up tables (no GPU needed; used by tests).
+ * Writes up to `capacity` doubles of table `table` for `nside` into `out`
+ * and the full element count into *count (out may be NULL to query the
+ * count).  Tables:
+ *   HP2SPH_TABLE_RINGS    per ring r = 1..4nside-1: z, n, phi0, start (4 doubles each)
+ *   HP2SPH_TABLE_POLE     the three pole weights (quadratic extrapolation in z
+ *                         of the three nearest ring means to the pole)
+ *   HP2SPH_TABLE_ANALYSIS block `block` (0..3 = (k even, +), (k even, -),
+ *                         (k odd, +), (k odd, -)): the matrix mapping the
+ *                         half-ring data h = 0..2nside to the order-0/1
+ *                         Legendre coefficients, stored [h][l'] (row-major,
+ *                         2nside+1 rows, (number of l of the block) columns)
+ *   HP2SPH_TABLE_SYNTHESIS block `block`: the evaluation matrix, stored
+ *                         [l'][h]
+ *   HP2SPH_TABLE_GIVENS   block `block`: (c, s) for sweep t = 1.. and chain
+ *                         position l' >= t, stored as rows t = 1..T of
+ *                         (ntop+1) pairs (entries l' < t are zero)
+ * Errors: EINVAL (bad nside/table/block), ENOMEM.
+ */
+enum {
+    HP2SPH_TABLE_RINGS = 0,
+    HP2SPH_TABLE_POLE = 1,
+    HP2SPH_TABLE_ANALYSIS = 2,
+    HP2SPH_TABLE_SYNTHESIS = 3,
+    HP2SPH_TABLE_GIVENS = 4
+};
+int hp2sph_host_table(int32_t nside, int32_t table, int32_t block, double* out,
+                      int64_t capacity, int64_t* count);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HP2SPH_H */

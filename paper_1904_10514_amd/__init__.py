@@ -1,0 +1,187 @@
+"""Python binding of libhp2sph (HP2SPH spherical-harmonic analysis on MI355X).
+
+Argument marshalling only: every stage runs in the HIP kernels of
+libhp2sph.so (built in-tree by paper_1904_10514_amd.build).  PyTorch supplies
+device memory and the current stream.  There is no CPU fallback: importing
+this package fails if the library has not been built, and every call that
+needs a GPU fails if none is visible.
+
+    plan = Plan(nside=1024, lmax=2048, batch=64, mode="f32_refine")
+    alm = plan.analyze(maps)            # (sum of alm sizes,) complex128
+    cl = plan.power_spectrum(alm)       # (sum of lmax+1,) float64
+    maps2 = plan.synthesize(alm)        # (sum of npix,) float64
+
+Conventions (see include/hp2sph.h): maps are float64 in HEALPix RING order,
+maps of a batch back to back; a_lm are complex128 packed m-major for m >= 0,
+index m (2 lmax + 1 - m)/2 + l, maps back to back.
+"""
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhp2sph.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        "libhp2sph.so is not built; run `python -m paper_1904_10514_amd.build` "
+        "(hipcc, gfx950) before importing paper_1904_10514_amd")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+HP2SPH_F64, HP2SPH_F32_REFINE, HP2SPH_F32 = 0, 1, 2
+MODES = {"f64": HP2SPH_F64, "f32_refine": HP2SPH_F32_REFINE, "f32": HP2SPH_F32}
+ERRORS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "EWORKSPACE", -5: "ESTATE"}
+TABLE_RINGS, TABLE_POLE, TABLE_ANALYSIS, TABLE_SYNTHESIS, TABLE_GIVENS = 0, 1, 2, 3, 4
+MAX_NSIDE = 2048
+
+EXPORTED = [
+    "hp2sph_plan_create", "hp2sph_workspace_size", "hp2sph_analyze", "hp2sph_synthesize",
+    "hp2sph_power_spectrum", "hp2sph_plan_destroy", "hp2sph_last_error", "hp2sph_host_table",
+]
+
+_vp = ctypes.c_void_p
+_i32 = ctypes.c_int32
+_lib.hp2sph_plan_create.argtypes = [ctypes.POINTER(_i32), ctypes.POINTER(_i32), _i32, _i32, ctypes.POINTER(_vp)]
+_lib.hp2sph_workspace_size.argtypes = [_vp, ctypes.POINTER(ctypes.c_size_t)]
+_lib.hp2sph_analyze.argtypes = [_vp, _vp, _vp, _vp, _vp]
+_lib.hp2sph_synthesize.argtypes = [_vp, _vp, _vp, _vp, _vp]
+_lib.hp2sph_power_spectrum.argtypes = [_vp, _vp, _vp, _vp]
+_lib.hp2sph_plan_destroy.argtypes = [_vp]
+_lib.hp2sph_last_error.restype = ctypes.c_char_p
+_lib.hp2sph_host_table.argtypes = [_i32, _i32, _i32, _vp, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
+for _f in EXPORTED:
+    if _f not in ("hp2sph_last_error",):
+        getattr(_lib, _f).restype = ctypes.c_int
+
+
+class HP2SPHError(RuntimeError):
+    def __init__(self, code, where):
+        self.code = code
+        msg = _lib.hp2sph_last_error().decode(errors="replace")
+        super().__init__(f"{where}: {ERRORS.get(code, code)}: {msg}")
+
+
+def _check(code, where):
+    if code != 0:
+        raise HP2SPHError(code, where)
+
+
+def lib():
+    """The loaded ctypes library (for tests of the raw C ABI)."""
+    return _lib
+
+
+def npix(nside):
+    return 12 * int(nside) * int(nside)
+
+
+def alm_size(lmax):
+    return (int(lmax) + 1) * (int(lmax) + 2) // 2
+
+
+def host_table(nside, table, block=0):
+    """A set-up table computed on the host (no GPU), as float64 numpy."""
+    cnt = ctypes.c_int64(0)
+    _check(_lib.hp2sph_host_table(int(nside), int(table), int(block), None, 0, ctypes.byref(cnt)), "host_table")
+    out = np.empty(cnt.value, dtype=np.float64)
+    _check(_lib.hp2sph_host_table(int(nside), int(table), int(block), out.ctypes.data, cnt.value,
+                                  ctypes.byref(cnt)), "host_table")
+    return out
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("no GPU visible: libhp2sph runs on MI355X only (no CPU fallback)")
+    return torch
+
+
+class Plan:
+    """A plan for a batch of maps (uniform or uneven nside)."""
+
+    def __init__(self, nside, lmax=None, batch=None, mode="f64"):
+        torch = _torch()
+        if np.isscalar(nside):
+            if batch is None:
+                batch = 1
+            nside = [int(nside)] * int(batch)
+        nside = [int(v) for v in nside]
+        batch = len(nside)
+        if lmax is None:
+            lmax = [2 * v for v in nside]
+        elif np.isscalar(lmax):
+            lmax = [int(lmax)] * batch
+        lmax = [int(v) for v in lmax]
+        if len(lmax) != batch:
+            raise ValueError("lmax must match nside")
+        self.nside, self.lmax, self.batch = nside, lmax, batch
+        self.mode = MODES[mode] if isinstance(mode, str) else int(mode)
+        arr_n = (_i32 * batch)(*nside)
+        arr_l = (_i32 * batch)(*lmax)
+        h = _vp()
+        _check(_lib.hp2sph_plan_create(arr_n, arr_l, batch, self.mode, ctypes.byref(h)), "plan_create")
+        self._h = h
+        ws = ctypes.c_size_t(0)
+        _check(_lib.hp2sph_workspace_size(self._h, ctypes.byref(ws)), "workspace_size")
+        self.workspace_bytes = ws.value
+        self._ws = torch.empty(max(ws.value, 1) + 256, dtype=torch.uint8, device="cuda")
+        base = self._ws.data_ptr()
+        self._ws_ptr = (base + 255) // 256 * 256
+        self.npix_total = sum(npix(v) for v in nside)
+        self.alm_total = sum(alm_size(v) for v in lmax)
+        self.cl_total = sum(v + 1 for v in lmax)
+        self.map_offsets = np.concatenate([[0], np.cumsum([npix(v) for v in nside])])
+        self.alm_offsets = np.concatenate([[0], np.cumsum([alm_size(v) for v in lmax])])
+        self.cl_offsets = np.concatenate([[0], np.cumsum([v + 1 for v in lmax])])
+
+    def _stream(self):
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+    def analyze(self, maps, out=None):
+        torch = _torch()
+        if maps.dtype != torch.float64 or not maps.is_cuda or not maps.is_contiguous():
+            raise ValueError("maps must be a contiguous float64 CUDA tensor")
+        if maps.numel() != self.npix_total:
+            raise ValueError(f"maps has {maps.numel()} values, plan expects {self.npix_total}")
+        if out is None:
+            out = torch.empty(self.alm_total, dtype=torch.complex128, device=maps.device)
+        _check(_lib.hp2sph_analyze(self._h, maps.data_ptr(), out.data_ptr(), self._ws_ptr, self._stream()),
+               "analyze")
+        return out
+
+    def synthesize(self, alm, out=None):
+        torch = _torch()
+        if alm.dtype != torch.complex128 or not alm.is_cuda or not alm.is_contiguous():
+            raise ValueError("alm must be a contiguous complex128 CUDA tensor")
+        if alm.numel() != self.alm_total:
+            raise ValueError("alm has the wrong size for this plan")
+        if out is None:
+            out = torch.empty(self.npix_total, dtype=torch.float64, device=alm.device)
+        _check(_lib.hp2sph_synthesize(self._h, alm.data_ptr(), out.data_ptr(), self._ws_ptr, self._stream()),
+               "synthesize")
+        return out
+
+    def power_spectrum(self, alm, out=None):
+        torch = _torch()
+        if alm.dtype != torch.complex128 or not alm.is_cuda or not alm.is_contiguous():
+            raise ValueError("alm must be a contiguous complex128 CUDA tensor")
+        if out is None:
+            out = torch.empty(self.cl_total, dtype=torch.float64, device=alm.device)
+        _check(_lib.hp2sph_power_spectrum(self._h, alm.data_ptr(), out.data_ptr(), self._stream()),
+               "power_spectrum")
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.hp2sph_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,494 @@
+// C ABI of libhp2sph: plans, workspace, stage sequencing.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <new>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/hp2sph.h"
+#include "kernels.h"
+#include "tables.h"
+
+namespace hp2sph {
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+    g_last_error = msg;
+    return code;
+}
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    ~DevBuf() {
+        if (p) (void)hipFree(p);
+    }
+};
+
+// Device copy of one nside's tables in precision T.
+template <class T>
+struct DevTables {
+    std::vector<std::unique_ptr<DevBuf>> owned;
+    T* ana[4] = {};
+    T* givens[4] = {};
+    FftTab<T> fft{};
+
+    T* upload(const std::vector<double>& v) {
+        std::vector<T> tmp(v.begin(), v.end());
+        auto b = std::make_unique<DevBuf>();
+        b->bytes = std::max<size_t>(tmp.size(), 1) * sizeof(T);
+        if (hipMalloc(&b->p, b->bytes) != hipSuccess) throw std::bad_alloc();
+        if (!tmp.empty() && hipMemcpy(b->p, tmp.data(), tmp.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess)
+            throw std::runtime_error("hipMemcpy failed");
+        T* out = static_cast<T*>(b->p);
+        owned.push_back(std::move(b));
+        return out;
+    }
+};
+
+template <class I>
+I* upload_int(std::vector<std::unique_ptr<DevBuf>>& owned, const std::vector<I>& v) {
+    auto b = std::make_unique<DevBuf>();
+    b->bytes = std::max<size_t>(v.size(), 1) * sizeof(I);
+    if (hipMalloc(&b->p, b->bytes) != hipSuccess) throw std::bad_alloc();
+    if (!v.empty() && hipMemcpy(b->p, v.data(), v.size() * sizeof(I), hipMemcpyHostToDevice) != hipSuccess)
+        throw std::runtime_error("hipMemcpy failed");
+    I* out = static_cast<I*>(b->p);
+    owned.push_back(std::move(b));
+    return out;
+}
+
+struct Group {
+    int nside = 0;
+    std::vector<int> members;         // batch indices
+    GroupDims dims{};
+    double pole_w[3] = {0, 0, 0};
+    std::vector<std::unique_ptr<DevBuf>> owned;
+    RingTab rings{};
+    DevTables<double> t64;
+    DevTables<float> t32;
+    double* syn[4] = {};              // synthesis matrices (FP64)
+    int64_t* d_map_off = nullptr;     // per member: offset of its map (doubles)
+    int64_t* d_alm_off = nullptr;     // per member: offset of its alm (complex)
+    int64_t* d_cl_off = nullptr;
+    int32_t* d_lmax = nullptr;
+    int lmax_max = 0;
+    // workspace offsets (bytes, relative to the plan's workspace)
+    size_t off_D = 0, off_U = 0;
+    size_t bytes_D = 0, bytes_U = 0;
+    int64_t rows_D[4] = {}, rows_U[4] = {};
+};
+
+}  // namespace
+}  // namespace hp2sph
+
+struct hp2sph_plan_s {
+    int batch = 0;
+    int mode = 0;
+    int device = 0;
+    std::vector<int32_t> nside, lmax;
+    std::vector<int64_t> map_off, alm_off, cl_off;
+    int64_t total_pix = 0, total_alm = 0, total_cl = 0;
+    std::vector<std::unique_ptr<hp2sph::Group>> groups;
+    size_t ws_bytes = 0;
+    size_t off_R = 0;                 // residual map (refinement)
+    uint32_t magic = 0x48503253u;
+};
+
+using namespace hp2sph;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+template <class T>
+void fill_fft(DevTables<T>& d, const HostTables& h, std::vector<std::unique_ptr<DevBuf>>& owned) {
+    d.fft.twiddle = d.upload(h.twiddle);
+    d.fft.roots = d.upload(h.roots);
+    d.fft.chirp = d.upload(h.chirp);
+    d.fft.chirpfft = d.upload(h.chirpfft);
+    d.fft.rootoff = upload_int(owned, h.rootoff);
+    d.fft.chirpoff = upload_int(owned, h.chirpoff);
+    d.fft.chirpfftoff = upload_int(owned, h.chirpfftoff);
+    d.fft.chirpm = upload_int(owned, h.chirpm);
+    d.fft.fft_max = h.fft_max;
+}
+
+// Givens tables padded in t to a multiple of the sweep pass length
+std::vector<double> pad_givens(const std::vector<double>& g, int nl, int T, int tpad) {
+    std::vector<double> out(size_t(nl) * tpad * 2, 0.0);
+    for (int lp = 0; lp < nl; ++lp)
+        for (int t = 0; t < T; ++t) {
+            out[(size_t(lp) * tpad + t) * 2] = g[(size_t(lp) * T + t) * 2];
+            out[(size_t(lp) * tpad + t) * 2 + 1] = g[(size_t(lp) * T + t) * 2 + 1];
+        }
+    return out;
+}
+
+void build_group(hp2sph_plan_t plan, Group& G) {
+    HostTables h;
+    build_tables(G.nside, h, true);
+    const int p = h.p;
+    GroupDims& d = G.dims;
+    d.nside = G.nside;
+    d.p = p;
+    d.nmaps = int(G.members.size());
+    for (int b = 0; b < 4; ++b) {
+        BlockShape bs = block_shape(G.nside, b);
+        d.nl[b] = bs.nl;
+        d.nk[b] = bs.nk;
+        d.lmin[b] = bs.lmin;
+        const int T = std::max(bs.nsweep, 1);
+        d.tpad[b] = (T + 7) / 8 * 8;
+    }
+    d.Npm[0] = 2 * d.nk[0];
+    d.Npm[1] = 2 * d.nk[2];
+    d.N[0] = int64_t(d.nmaps) * d.Npm[0];
+    d.N[1] = int64_t(d.nmaps) * d.Npm[1];
+    for (int i = 0; i < 3; ++i) G.pole_w[i] = h.pole_w[i];
+
+    // rings
+    std::vector<int64_t> st;
+    std::vector<int32_t> nn;
+    std::vector<int8_t> sh;
+    for (auto& r : h.rings) {
+        st.push_back(r.start);
+        nn.push_back(int32_t(r.n));
+        sh.push_back(r.phi0 != 0.0 ? 1 : 0);
+    }
+    G.rings.start = upload_int(G.owned, st);
+    G.rings.n = upload_int(G.owned, nn);
+    G.rings.shifted = upload_int(G.owned, sh);
+
+    const bool need64 = true;   // FP64 tables: analysis in F64 mode, always for synthesis
+    const bool need32 = (plan->mode != HP2SPH_F64);
+    for (int b = 0; b < 4; ++b) {
+        const int T = std::max(block_shape(G.nside, b).nsweep, 1);
+        std::vector<double> gp = pad_givens(h.givens[b], d.nl[b], T, d.tpad[b]);
+        if (need64) {
+            G.t64.ana[b] = G.t64.upload(h.ana[b]);
+            G.t64.givens[b] = G.t64.upload(gp);
+        }
+        if (need32) {
+            G.t32.ana[b] = G.t32.upload(h.ana[b]);
+            G.t32.givens[b] = G.t32.upload(gp);
+        }
+        G.syn[b] = G.t64.upload(h.syn[b]);
+    }
+    fill_fft(G.t64, h, G.owned);
+    if (need32) fill_fft(G.t32, h, G.owned);
+
+    // per-member offsets
+    std::vector<int64_t> mo, ao, co;
+    std::vector<int32_t> lm;
+    G.lmax_max = 0;
+    for (int i : G.members) {
+        mo.push_back(plan->map_off[i]);
+        ao.push_back(plan->alm_off[i]);
+        co.push_back(plan->cl_off[i]);
+        lm.push_back(plan->lmax[i]);
+        G.lmax_max = std::max(G.lmax_max, int(plan->lmax[i]));
+    }
+    G.d_map_off = upload_int(G.owned, mo);
+    G.d_alm_off = upload_int(G.owned, ao);
+    G.d_cl_off = upload_int(G.owned, co);
+    G.d_lmax = upload_int(G.owned, lm);
+
+    // workspace sizes (FP64 elements; FP32 stages alias the same bytes)
+    const int K = 2 * G.nside + 1;
+    G.bytes_D = 0;
+    G.bytes_U = 0;
+    for (int b = 0; b < 4; ++b) {
+        const int kpar = b >> 1;
+        G.rows_D[b] = K;
+        G.rows_U[b] = d.nl[b];
+        G.bytes_D += align_up(size_t(K) * d.N[kpar] * sizeof(double));
+        G.bytes_U += align_up(size_t(d.nl[b]) * d.N[kpar] * sizeof(double));
+    }
+}
+
+template <class T>
+Blocks4<T> blocks_at(void* ws, size_t off, const Group& G, const int64_t* rows) {
+    Blocks4<T> out;
+    char* base = static_cast<char*>(ws) + off;
+    size_t o = 0;
+    for (int b = 0; b < 4; ++b) {
+        out.p[b] = reinterpret_cast<T*>(base + o);
+        o += align_up(size_t(rows[b]) * G.dims.N[b >> 1] * sizeof(double));
+    }
+    return out;
+}
+
+template <class T>
+Blocks4<const T> cblocks(Blocks4<T> b) {
+    Blocks4<const T> o;
+    for (int i = 0; i < 4; ++i) o.p[i] = b.p[i];
+    return o;
+}
+
+#define HIPCHK(expr)                                                                          \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            return fail(HP2SPH_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));  \
+    } while (0)
+
+template <class T>
+DevTables<T>& tabs(Group& G);
+template <>
+DevTables<double>& tabs<double>(Group& G) { return G.t64; }
+template <>
+DevTables<float>& tabs<float>(Group& G) { return G.t32; }
+
+// One analysis pass of one group in precision T: maps_in -> alm (write or add).
+template <class T>
+int analysis_pass(Group& G, const double* maps_in, double* alm, void* ws, bool accumulate, hipStream_t s) {
+    DevTables<T>& t = tabs<T>(G);
+    Blocks4<T> D = blocks_at<T>(ws, G.off_D, G, G.rows_D);
+    Blocks4<T> U = blocks_at<T>(ws, G.off_U, G, G.rows_U);
+    HIPCHK(launch_ring_forward<T>(maps_in, G.d_map_off, G.rings, t.fft, D, G.dims, s));
+    HIPCHK(launch_pole<T>(D, G.dims, G.pole_w[0], G.pole_w[1], G.pole_w[2], s));
+    GemmBatch<T> gb{};
+    gb.nprob = 4;
+    for (int b = 0; b < 4; ++b) {
+        const int kpar = b >> 1;
+        GemmProblem<T>& P = gb.pr[b];
+        P.A = t.ana[b];
+        P.B = D.p[b];
+        P.C = U.p[b];
+        P.M = G.dims.nl[b];
+        P.N = int(G.dims.N[kpar]);
+        P.K = 2 * G.nside + 1;
+        P.lda = G.dims.nl[b];
+        P.ldb = G.dims.N[kpar];
+        P.ldc = G.dims.N[kpar];
+    }
+    HIPCHK(launch_gemm<T>(gb, s));
+    Blocks4<const T> Gv;
+    for (int b = 0; b < 4; ++b) Gv.p[b] = t.givens[b];
+    HIPCHK(launch_sweep_fwd<T>(U, Gv, G.dims, s));
+    HIPCHK(launch_pack<T>(cblocks(U), alm, G.d_alm_off, G.d_lmax, G.dims, accumulate, s));
+    return HP2SPH_OK;
+}
+
+// FP64 synthesis of one group: alm -> out (or minus_from - synthesis).
+int synthesis_pass(Group& G, const double* alm, double* out, const double* minus_from, void* ws, hipStream_t s) {
+    Blocks4<double> D = blocks_at<double>(ws, G.off_D, G, G.rows_D);
+    Blocks4<double> U = blocks_at<double>(ws, G.off_U, G, G.rows_U);
+    HIPCHK(launch_unpack(alm, G.d_alm_off, G.d_lmax, U, G.dims, s));
+    Blocks4<const double> Gv;
+    for (int b = 0; b < 4; ++b) Gv.p[b] = G.t64.givens[b];
+    HIPCHK(launch_sweep_bwd<double>(U, Gv, G.dims, s));
+    GemmBatch<double> gb{};
+    gb.nprob = 4;
+    for (int b = 0; b < 4; ++b) {
+        const int kpar = b >> 1;
+        GemmProblem<double>& P = gb.pr[b];
+        P.A = G.syn[b];
+        P.B = U.p[b];
+        P.C = D.p[b];
+        P.M = 2 * G.nside + 1;
+        P.N = int(G.dims.N[kpar]);
+        P.K = G.dims.nl[b];
+        P.lda = 2 * G.nside + 1;
+        P.ldb = G.dims.N[kpar];
+        P.ldc = G.dims.N[kpar];
+    }
+    HIPCHK(launch_gemm<double>(gb, s));
+    HIPCHK(launch_ring_inverse(cblocks(D), G.rings, G.t64.fft, out, minus_from, G.d_map_off, G.dims, s));
+    return HP2SPH_OK;
+}
+
+bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+int check_plan(hp2sph_plan_t plan) {
+    if (!plan || plan->magic != 0x48503253u) return fail(HP2SPH_ESTATE, "invalid plan handle");
+    return HP2SPH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* hp2sph_last_error(void) { return g_last_error.c_str(); }
+
+int hp2sph_plan_create(const int32_t* nside, const int32_t* lmax, int32_t batch, int32_t mode,
+                       hp2sph_plan_t* out) {
+    if (!out) return fail(HP2SPH_EINVAL, "out is null");
+    *out = nullptr;
+    if (!nside || !lmax) return fail(HP2SPH_EINVAL, "nside/lmax is null");
+    if (batch <= 0) return fail(HP2SPH_EINVAL, "batch must be positive");
+    if (mode != HP2SPH_F64 && mode != HP2SPH_F32_REFINE && mode != HP2SPH_F32)
+        return fail(HP2SPH_EINVAL, "unknown precision mode");
+    for (int b = 0; b < batch; ++b) {
+        if (nside[b] < 2 || nside[b] > HP2SPH_MAX_NSIDE || !is_pow2(nside[b]))
+            return fail(HP2SPH_EINVAL, "nside must be a power of two in [2, " + std::to_string(HP2SPH_MAX_NSIDE) + "]");
+        if (lmax[b] < 0 || lmax[b] > 2 * nside[b]) return fail(HP2SPH_EINVAL, "need 0 <= lmax <= 2 nside");
+    }
+    std::unique_ptr<hp2sph_plan_s> plan;
+    try {
+        plan.reset(new hp2sph_plan_s());
+        plan->batch = batch;
+        plan->mode = mode;
+        if (hipGetDevice(&plan->device) != hipSuccess) return fail(HP2SPH_EDEVICE, "hipGetDevice failed");
+        plan->nside.assign(nside, nside + batch);
+        plan->lmax.assign(lmax, lmax + batch);
+        int64_t mo = 0, ao = 0, co = 0;
+        for (int b = 0; b < batch; ++b) {
+            plan->map_off.push_back(mo);
+            plan->alm_off.push_back(ao);
+            plan->cl_off.push_back(co);
+            mo += 12LL * nside[b] * nside[b];
+            ao += int64_t(lmax[b] + 1) * (lmax[b] + 2) / 2;
+            co += lmax[b] + 1;
+        }
+        plan->total_pix = mo;
+        plan->total_alm = ao;
+        plan->total_cl = co;
+        std::map<int, std::vector<int>> bys;
+        for (int b = 0; b < batch; ++b) bys[nside[b]].push_back(b);
+        size_t ws = 0;
+        size_t max_group = 0;
+        for (auto it = bys.rbegin(); it != bys.rend(); ++it) {
+            auto G = std::make_unique<Group>();
+            G->nside = it->first;
+            G->members = it->second;
+            build_group(plan.get(), *G);
+            G->off_D = 0;
+            G->off_U = align_up(G->bytes_D);
+            max_group = std::max(max_group, G->off_U + align_up(G->bytes_U));
+            plan->groups.push_back(std::move(G));
+        }
+        ws = max_group;   // groups run one after another and share the buffers
+        if (mode == HP2SPH_F32_REFINE) {
+            plan->off_R = ws;
+            ws += align_up(size_t(plan->total_pix) * sizeof(double));
+        }
+        plan->ws_bytes = ws;
+        // kernels with more than 64 KB of dynamic LDS
+        if (configure_kernels() != hipSuccess) return fail(HP2SPH_EDEVICE, "hipFuncSetAttribute failed");
+    } catch (const std::bad_alloc&) {
+        return fail(HP2SPH_ENOMEM, "allocation of plan tables failed");
+    } catch (const std::exception& e) {
+        return fail(HP2SPH_EDEVICE, e.what());
+    }
+    *out = plan.release();
+    return HP2SPH_OK;
+}
+
+int hp2sph_workspace_size(hp2sph_plan_t plan, size_t* bytes) {
+    if (int e = check_plan(plan)) return e;
+    if (!bytes) return fail(HP2SPH_EINVAL, "bytes is null");
+    *bytes = plan->ws_bytes;
+    return HP2SPH_OK;
+}
+
+int hp2sph_analyze(hp2sph_plan_t plan, const double* maps, double* alm, void* workspace, void* stream) {
+    if (int e = check_plan(plan)) return e;
+    if (!maps || !alm) return fail(HP2SPH_EINVAL, "maps/alm is null");
+    if (!aligned(maps, 8) || !aligned(alm, 16)) return fail(HP2SPH_EINVAL, "maps/alm misaligned");
+    if (!workspace || !aligned(workspace, kAlign)) return fail(HP2SPH_EWORKSPACE, "workspace null or not 256-byte aligned");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    for (auto& gp : plan->groups) {
+        Group& G = *gp;
+        if (plan->mode == HP2SPH_F64) {
+            if (int e = analysis_pass<double>(G, maps, alm, workspace, false, s)) return e;
+        } else if (plan->mode == HP2SPH_F32) {
+            if (int e = analysis_pass<float>(G, maps, alm, workspace, false, s)) return e;
+        } else {
+            double* R = reinterpret_cast<double*>(static_cast<char*>(workspace) + plan->off_R);
+            if (int e = analysis_pass<float>(G, maps, alm, workspace, false, s)) return e;
+            if (int e = synthesis_pass(G, alm, R, maps, workspace, s)) return e;
+            if (int e = analysis_pass<float>(G, R, alm, workspace, true, s)) return e;
+        }
+    }
+    return HP2SPH_OK;
+}
+
+int hp2sph_synthesize(hp2sph_plan_t plan, const double* alm, double* maps, void* workspace, void* stream) {
+    if (int e = check_plan(plan)) return e;
+    if (!maps || !alm) return fail(HP2SPH_EINVAL, "maps/alm is null");
+    if (!aligned(maps, 8) || !aligned(alm, 16)) return fail(HP2SPH_EINVAL, "maps/alm misaligned");
+    if (!workspace || !aligned(workspace, kAlign)) return fail(HP2SPH_EWORKSPACE, "workspace null or not 256-byte aligned");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    for (auto& gp : plan->groups)
+        if (int e = synthesis_pass(*gp, alm, maps, nullptr, workspace, s)) return e;
+    return HP2SPH_OK;
+}
+
+int hp2sph_power_spectrum(hp2sph_plan_t plan, const double* alm, double* cl, void* stream) {
+    if (int e = check_plan(plan)) return e;
+    if (!alm || !cl) return fail(HP2SPH_EINVAL, "alm/cl is null");
+    if (!aligned(alm, 16) || !aligned(cl, 8)) return fail(HP2SPH_EINVAL, "alm/cl misaligned");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    for (auto& gp : plan->groups) {
+        Group& G = *gp;
+        HIPCHK(launch_cl(alm, G.d_alm_off, G.d_lmax, cl, G.d_cl_off, G.dims.nmaps, G.lmax_max, s));
+    }
+    return HP2SPH_OK;
+}
+
+int hp2sph_plan_destroy(hp2sph_plan_t plan) {
+    if (int e = check_plan(plan)) return e;
+    plan->magic = 0;
+    delete plan;
+    return HP2SPH_OK;
+}
+
+int hp2sph_host_table(int32_t nside, int32_t table, int32_t block, double* out, int64_t capacity, int64_t* count) {
+    if (!count) return fail(HP2SPH_EINVAL, "count is null");
+    if (nside < 2 || nside > HP2SPH_MAX_NSIDE || !is_pow2(nside)) return fail(HP2SPH_EINVAL, "bad nside");
+    if (table < HP2SPH_TABLE_RINGS || table > HP2SPH_TABLE_GIVENS) return fail(HP2SPH_EINVAL, "bad table");
+    if ((table >= HP2SPH_TABLE_ANALYSIS) && (block < 0 || block > 3)) return fail(HP2SPH_EINVAL, "bad block");
+    std::vector<double> v;
+    try {
+        HostTables h;
+        if (table == HP2SPH_TABLE_RINGS) {
+            const int nr = 4 * nside - 1;
+            int64_t st = 0;
+            for (int r = 1; r <= nr; ++r) {
+                RingGeom g = ring_geom(nside, r);
+                v.push_back(g.z);
+                v.push_back(double(g.n));
+                v.push_back(g.phi0);
+                v.push_back(double(st));
+                st += g.n;
+            }
+        } else {
+            build_tables(nside, h, false);
+            if (table == HP2SPH_TABLE_POLE) v.assign(h.pole_w, h.pole_w + 3);
+            else if (table == HP2SPH_TABLE_ANALYSIS) v = h.ana[block];
+            else if (table == HP2SPH_TABLE_SYNTHESIS) v = h.syn[block];
+            else {
+                BlockShape bs = block_shape(nside, block);
+                const int T = bs.nsweep, nl = bs.nl;
+                v.assign(size_t(std::max(T, 0)) * nl * 2, 0.0);
+                for (int t = 0; t < T; ++t)
+                    for (int lp = 0; lp < nl; ++lp) {
+                        v[(size_t(t) * nl + lp) * 2] = h.givens[block][(size_t(lp) * T + t) * 2];
+                        v[(size_t(t) * nl + lp) * 2 + 1] = h.givens[block][(size_t(lp) * T + t) * 2 + 1];
+                    }
+            }
+        }
+    } catch (const std::bad_alloc&) {
+        return fail(HP2SPH_ENOMEM, "host allocation failed");
+    } catch (const std::exception& e) {
+        return fail(HP2SPH_EINVAL, e.what());
+    }
+    *count = int64_t(v.size());
+    if (out) std::memcpy(out, v.data(), sizeof(double) * size_t(std::min<int64_t>(capacity, int64_t(v.size()))));
+    return HP2SPH_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,114 @@
+// Device kernels of libhp2sph and their launch wrappers (gfx950, wave64).
+//
+// Data layout shared by the stages (one nside group of `nmaps` maps):
+//   Dsym_b [h][n]   block b = 0..3 (see tables.h), h = 0 .. 2 nside (the pole
+//                   row, the ring pairs, the equator), n = map * Npm + 2 k' + c
+//                   with k' = k / 2 the index of the longitude mode k of the
+//                   block's parity and c = 0 (real), 1 (imaginary).
+//   U_b    [l'][n]  order-0/1 Legendre coefficients of block b (after the
+//                   fused colatitude fit), then, in place, a_l^m after the
+//                   Givens sweeps: column k' holds order m = 2k' + kpar at
+//                   degrees l = lmin + 2 l' >= m.
+// Every array is row-major with the row stride N_kpar = nmaps * Npm_kpar,
+// Npm_kpar = 2 * (number of modes of parity kpar).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace hp2sph {
+
+template <class T>
+struct FftTab {
+    const T* twiddle;         // e^{-2 pi i t / fft_max}, t < fft_max / 2 (complex)
+    const T* roots;           // per ring size: e^{-i pi k / n}, k = 0 .. n
+    const T* chirp;           // per ring size (Bluestein): w_k = e^{-i pi k^2 / L}
+    const T* chirpfft;        // per ring size (Bluestein): FFT_M(conj chirp)
+    const int64_t* rootoff;   // [j], j = 1 .. nside (complex offsets)
+    const int64_t* chirpoff;
+    const int64_t* chirpfftoff;
+    const int32_t* chirpm;    // Bluestein length per j, 0 if L = 2j is a power of two
+    int fft_max;
+};
+
+struct RingTab {
+    const int64_t* start;     // first pixel of ring r (index r - 1)
+    const int32_t* n;         // pixels on ring r
+    const int8_t* shifted;    // 1 if the first point is at pi / n, 0 if at 0
+};
+
+template <class T>
+struct Blocks4 {
+    T* p[4];
+};
+
+struct GroupDims {
+    int nside, p, nmaps;
+    int Npm[2];               // columns per map for k parity 0 / 1
+    int64_t N[2];             // row strides nmaps * Npm
+    int nl[4], nk[4], lmin[4], tpad[4];
+};
+
+template <class T>
+struct GemmProblem {
+    const T* A;               // [K][M], row stride lda
+    const T* B;               // [K][N], row stride ldb
+    T* C;                     // [M][N], row stride ldc
+    int M, N, K;
+    int64_t lda, ldb, ldc;
+    int tiles_n, tile_begin;
+};
+
+template <class T>
+struct GemmBatch {
+    GemmProblem<T> pr[4];
+    int nprob;
+    int total_tiles;
+};
+
+// S1: per-ring real DFT, shift to unshifted longitudes, Nyquist rule and the
+// north/south combination, written into Dsym rows 1 .. 2 nside.
+template <class T>
+hipError_t launch_ring_forward(const double* maps, const int64_t* map_off, RingTab rt, FftTab<T> ft,
+                               Blocks4<T> D, const GroupDims& g, hipStream_t s);
+
+// S2: pole row h = 0 (quadratic extrapolation of the three nearest ring
+// means); zeroes every other entry of the pole row.
+template <class T>
+hipError_t launch_pole(Blocks4<T> D, const GroupDims& g, double w0, double w1, double w2, hipStream_t s);
+
+// C[m][n] = sum_k A[k][m] B[k][n] for up to four problems, one launch.
+template <class T>
+hipError_t launch_gemm(GemmBatch<T> gb, hipStream_t s);
+
+// S4 analysis sweeps (Givens, order 0/1 -> order m), in place on U.
+template <class T>
+hipError_t launch_sweep_fwd(Blocks4<T> U, Blocks4<const T> G, const GroupDims& g, hipStream_t s);
+
+// Synthesis sweeps (transposed, order m -> order 0/1), in place on U.
+template <class T>
+hipError_t launch_sweep_bwd(Blocks4<T> U, Blocks4<const T> G, const GroupDims& g, hipStream_t s);
+
+// U (a_l^m after the sweeps) -> packed complex128 alm; accumulate adds.
+template <class T>
+hipError_t launch_pack(Blocks4<const T> U, double* alm, const int64_t* alm_off, const int32_t* lmax,
+                       const GroupDims& g, bool accumulate, hipStream_t s);
+
+// packed complex128 alm -> U (zeros outside 0 <= m <= l <= lmax).
+hipError_t launch_unpack(const double* alm, const int64_t* alm_off, const int32_t* lmax, Blocks4<double> U,
+                         const GroupDims& g, hipStream_t s);
+
+// Synthesis: Dsym (FP64, from the evaluation GEMM) -> ring values; if
+// `minus_from` is non-null writes minus_from - synthesis (the residual).
+hipError_t launch_ring_inverse(Blocks4<const double> D, RingTab rt, FftTab<double> ft, double* out,
+                               const double* minus_from, const int64_t* map_off, const GroupDims& g,
+                               hipStream_t s);
+
+// Raise the dynamic-LDS limit of the ring kernels (up to 128 KB at nside 2048).
+hipError_t configure_kernels();
+
+// C_l per map from packed alm.
+hipError_t launch_cl(const double* alm, const int64_t* alm_off, const int32_t* lmax, double* cl,
+                     const int64_t* cl_off, int nmaps, int lmax_max, hipStream_t s);
+
+}  // namespace hp2sph

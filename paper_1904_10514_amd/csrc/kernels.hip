@@ -1,0 +1,727 @@
+// Device kernels of libhp2sph (gfx950).  See kernels.h for the data layout.
+#include "kernels.h"
+
+#include <hip/hip_runtime.h>
+
+namespace hp2sph {
+
+// ---------------------------------------------------------------------------
+// complex helpers
+// ---------------------------------------------------------------------------
+
+template <class T>
+struct C2 {
+    T x, y;
+};
+
+template <class T>
+__device__ __forceinline__ C2<T> cadd(C2<T> a, C2<T> b) { return {a.x + b.x, a.y + b.y}; }
+template <class T>
+__device__ __forceinline__ C2<T> csub(C2<T> a, C2<T> b) { return {a.x - b.x, a.y - b.y}; }
+template <class T>
+__device__ __forceinline__ C2<T> cmul(C2<T> a, C2<T> b) {
+    return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <class T>
+__device__ __forceinline__ C2<T> cconj(C2<T> a) { return {a.x, -a.y}; }
+template <class T>
+__device__ __forceinline__ C2<T> cscale(C2<T> a, T s) { return {a.x * s, a.y * s}; }
+template <class T>
+__device__ __forceinline__ C2<T> ldc(const T* p, int64_t i) { return {p[2 * i], p[2 * i + 1]}; }
+
+__device__ __forceinline__ int ilog2(int v) { return 31 - __clz(v); }
+__device__ __forceinline__ int bitrev(int v, int lg) { return lg == 0 ? 0 : int(__brev(unsigned(v)) >> (32 - lg)); }
+
+// In-place radix-2 FFT in LDS, e^{-2 pi i jk / M}.  DIT: input in
+// bit-reversed order, output natural.  DIF: input natural, output
+// bit-reversed.  Caller synchronises before (data written) and the routine
+// ends with a barrier.
+template <class T>
+__device__ void lds_fft_dit(C2<T>* buf, int M, const T* tw, int fft_max) {
+    const int nt = blockDim.x;
+    for (int len = 2; len <= M; len <<= 1) {
+        const int half = len >> 1, lh = ilog2(half);
+        const int stride = fft_max / len;
+        for (int b = threadIdx.x; b < (M >> 1); b += nt) {
+            const int grp = b >> lh, pos = b & (half - 1);
+            const int i = grp * len + pos, j = i + half;
+            const C2<T> w = ldc(tw, int64_t(pos) * stride);
+            const C2<T> u = buf[i], v = cmul(w, buf[j]);
+            buf[i] = cadd(u, v);
+            buf[j] = csub(u, v);
+        }
+        __syncthreads();
+    }
+}
+
+template <class T>
+__device__ void lds_fft_dif(C2<T>* buf, int M, const T* tw, int fft_max) {
+    const int nt = blockDim.x;
+    for (int len = M; len >= 2; len >>= 1) {
+        const int half = len >> 1, lh = ilog2(half);
+        const int stride = fft_max / len;
+        for (int b = threadIdx.x; b < (M >> 1); b += nt) {
+            const int grp = b >> lh, pos = b & (half - 1);
+            const int i = grp * len + pos, j = i + half;
+            const C2<T> w = ldc(tw, int64_t(pos) * stride);
+            const C2<T> u = buf[i], v = buf[j];
+            buf[i] = cadd(u, v);
+            buf[j] = cmul(csub(u, v), w);
+        }
+        __syncthreads();
+    }
+}
+
+// Forward DFT of length L (a power of two, or any L through Bluestein's
+// chirp-z with M = chirpm) of the complex sequence produced by `src(q)`,
+// q < L.  On return Z(k) gives the k-th output (valid until the next
+// barrier that rewrites buf).
+template <class T>
+struct DftResult {
+    C2<T>* buf;
+    const T* w;      // chirp (Bluestein) or null
+    int M, lg;
+    bool blue;
+    T invM;
+    __device__ C2<T> Z(int k) const {
+        if (!blue) return buf[k];
+        C2<T> c = cconj(buf[bitrev(k, lg)]);
+        c = cscale(c, invM);
+        return cmul(ldc(w, k), c);
+    }
+};
+
+template <class T, class Src>
+__device__ DftResult<T> lds_dft(C2<T>* buf, int L, int M_blue, const T* chirp, const T* chirpfft,
+                                const T* tw, int fft_max, Src src) {
+    DftResult<T> r;
+    r.buf = buf;
+    if (M_blue == 0) {
+        r.blue = false;
+        r.M = L;
+        r.lg = ilog2(L);
+        r.w = nullptr;
+        r.invM = T(1);
+        for (int q = threadIdx.x; q < L; q += blockDim.x) buf[bitrev(q, r.lg)] = src(q);
+        __syncthreads();
+        lds_fft_dit(buf, L, tw, fft_max);
+        return r;
+    }
+    r.blue = true;
+    r.M = M_blue;
+    r.lg = ilog2(M_blue);
+    r.w = chirp;
+    r.invM = T(1) / T(M_blue);
+    for (int q = threadIdx.x; q < M_blue; q += blockDim.x) {
+        C2<T> v = {T(0), T(0)};
+        if (q < L) v = cmul(src(q), ldc(chirp, q));
+        buf[bitrev(q, r.lg)] = v;
+    }
+    __syncthreads();
+    lds_fft_dit(buf, M_blue, tw, fft_max);
+    // pointwise product with the chirp spectrum, conjugated for the inverse
+    for (int k = threadIdx.x; k < M_blue; k += blockDim.x) buf[k] = cconj(cmul(buf[k], ldc(chirpfft, k)));
+    __syncthreads();
+    lds_fft_dif(buf, M_blue, tw, fft_max);
+    return r;
+}
+
+// ---------------------------------------------------------------------------
+// S1: forward ring transform
+// ---------------------------------------------------------------------------
+
+constexpr int kRingThreads = 512;
+constexpr int kRingKPT = 9;   // (HP2SPH_MAX_NSIDE * 2 + 1) / kRingThreads, rounded up
+
+template <class T>
+__device__ void ring_spectrum(const double* x, int n, bool shifted, int p, FftTab<T> ft, C2<T>* buf,
+                              C2<T> (&D)[kRingKPT]) {
+    const int L = n >> 1, j = n >> 2;
+    const int Mb = ft.chirpm[j];
+    const T* chirp = ft.chirp + 2 * ft.chirpoff[j];
+    const T* chirpfft = ft.chirpfft + 2 * ft.chirpfftoff[j];
+    const T* roots = ft.roots + 2 * ft.rootoff[j];
+    auto src = [&](int q) -> C2<T> { return {T(x[2 * q]), T(x[2 * q + 1])}; };
+    DftResult<T> R = lds_dft<T>(buf, L, Mb, chirp, chirpfft, ft.twiddle, ft.fft_max, src);
+    const T invn = T(1) / T(n);
+#pragma unroll
+    for (int i = 0; i < kRingKPT; ++i) {
+        const int k = threadIdx.x + i * kRingThreads;
+        C2<T> d = {T(0), T(0)};
+        if (k <= p) {
+            if (k < L) {
+                const C2<T> zk = R.Z(k), zl = R.Z(k == 0 ? 0 : L - k);
+                const C2<T> e = cscale(cadd(zk, cconj(zl)), T(0.5));
+                const C2<T> dlt = csub(zk, cconj(zl));
+                const C2<T> o = {T(0.5) * dlt.y, -T(0.5) * dlt.x};   // (zk - conj zl) / (2i)
+                C2<T> X = cadd(e, cmul(ldc(roots, 2 * k), o));
+                if (shifted) X = cmul(X, ldc(roots, k));
+                d = cscale(X, invn);
+            } else if (k == L) {
+                const C2<T> z0 = R.Z(0);
+                const T alpha = (z0.x - z0.y) * invn;
+                if (L < p) d = {T(0), -T(0.5) * alpha};   // polar ring: alpha sin(L lambda)
+                else d = {shifted ? T(0) : T(0.5) * alpha, T(0)};
+            }
+        }
+        D[i] = d;
+    }
+    __syncthreads();
+}
+
+template <class T>
+__global__ __launch_bounds__(kRingThreads) void k_ring_forward(const double* __restrict__ maps,
+                                                               const int64_t* __restrict__ map_off, RingTab rt,
+                                                               FftTab<T> ft, Blocks4<T> D, GroupDims g) {
+    extern __shared__ unsigned char smem_raw[];
+    C2<T>* buf = reinterpret_cast<C2<T>*>(smem_raw);
+    const int h = blockIdx.x + 1;
+    const int b = blockIdx.y;
+    const int ns = g.nside, p = g.p;
+    const double* m = maps + map_off[b];
+    C2<T> DN[kRingKPT], DS[kRingKPT];
+    {
+        const int r0 = h - 1;
+        ring_spectrum<T>(m + rt.start[r0], rt.n[r0], rt.shifted[r0] != 0, p, ft, buf, DN);
+    }
+    const bool equator = (h == 2 * ns);
+    if (!equator) {
+        const int r0 = 4 * ns - h - 1;
+        ring_spectrum<T>(m + rt.start[r0], rt.n[r0], rt.shifted[r0] != 0, p, ft, buf, DS);
+    }
+#pragma unroll
+    for (int i = 0; i < kRingKPT; ++i) {
+        const int k = threadIdx.x + i * kRingThreads;
+        if (k > p) continue;
+        C2<T> dp, dm;
+        if (equator) {
+            dp = DN[i];
+            dm = {T(0), T(0)};
+        } else {
+            dp = cscale(cadd(DN[i], DS[i]), T(0.5));
+            dm = cscale(csub(DN[i], DS[i]), T(0.5));
+        }
+        const int kpar = k & 1, kk = k >> 1;
+        const int64_t col = int64_t(b) * g.Npm[kpar] + 2 * kk;
+        const int64_t row = int64_t(h) * g.N[kpar];
+        T* bp = D.p[2 * kpar + 0];
+        T* bm = D.p[2 * kpar + 1];
+        bp[row + col] = dp.x;
+        bp[row + col + 1] = dp.y;
+        bm[row + col] = dm.x;
+        bm[row + col + 1] = dm.y;
+    }
+}
+
+template <class T>
+hipError_t launch_ring_forward(const double* maps, const int64_t* map_off, RingTab rt, FftTab<T> ft, Blocks4<T> D,
+                               const GroupDims& g, hipStream_t s) {
+    dim3 grid(2 * g.nside, g.nmaps);
+    size_t shm = size_t(ft.fft_max) * sizeof(C2<T>);
+    hipLaunchKernelGGL(k_ring_forward<T>, grid, dim3(kRingThreads), shm, s, maps, map_off, rt, ft, D, g);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// S2: pole row
+// ---------------------------------------------------------------------------
+
+template <class T>
+__global__ void k_pole(Blocks4<T> D, GroupDims g, double w0, double w1, double w2) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t N0 = g.N[0], N1 = g.N[1];
+    const int64_t total = 2 * N0 + 2 * N1;
+    if (i >= total) return;
+    int blk;
+    int64_t col, N;
+    if (i < N0) { blk = 0; col = i; N = N0; }
+    else if (i < 2 * N0) { blk = 1; col = i - N0; N = N0; }
+    else if (i < 2 * N0 + N1) { blk = 2; col = i - 2 * N0; N = N1; }
+    else { blk = 3; col = i - 2 * N0 - N1; N = N1; }
+    T* P = D.p[blk];
+    T val = T(0);
+    if (blk < 2 && (col % g.Npm[0]) == 0) {
+        // k = 0, real part: the pole value (f_N +- f_S) / 2 from the ring means
+        val = T(w0 * double(P[1 * N + col]) + w1 * double(P[2 * N + col]) + w2 * double(P[3 * N + col]));
+    }
+    P[col] = val;
+}
+
+template <class T>
+hipError_t launch_pole(Blocks4<T> D, const GroupDims& g, double w0, double w1, double w2, hipStream_t s) {
+    const int64_t total = 2 * g.N[0] + 2 * g.N[1];
+    hipLaunchKernelGGL(k_pole<T>, dim3(unsigned((total + 255) / 256)), dim3(256), 0, s, D, g, w0, w1, w2);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Grouped GEMM on MFMA: C[m][n] = sum_k A[k][m] B[k][n]
+// ---------------------------------------------------------------------------
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+template <class T>
+struct MfmaAcc;
+// Operand layout (both precisions, measured on gfx950): lane l supplies
+// A[l % 16][l / 16] and B[l / 16][l % 16] of the 16x4 / 4x16 operands.
+// Accumulator register r of lane l holds D[row][l % 16] with
+// row = 4 r + l / 16 for f64_16x16x4 and row = 4 (l / 16) + r for f32_16x16x4.
+template <>
+struct MfmaAcc<double> {
+    using V = v4d;
+    static __device__ __forceinline__ V mma(double a, double b, V c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int lane, int r) { return 4 * r + (lane >> 4); }
+};
+template <>
+struct MfmaAcc<float> {
+    using V = v4f;
+    static __device__ __forceinline__ V mma(float a, float b, V c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+};
+
+constexpr int GBM = 128, GBN = 128, GBK = 16, GPAD = 4;
+
+template <class T>
+__global__ __launch_bounds__(256) void k_gemm(GemmBatch<T> gb) {
+    __shared__ T As[GBK][GBM + GPAD];
+    __shared__ T Bs[GBK][GBN + GPAD];
+    int tile = blockIdx.x;
+    int pi = 0;
+    while (pi + 1 < gb.nprob && tile >= gb.pr[pi + 1].tile_begin) ++pi;
+    const GemmProblem<T> P = gb.pr[pi];
+    tile -= P.tile_begin;
+    const int tm = tile / P.tiles_n, tn = tile % P.tiles_n;
+    const int m0 = tm * GBM, n0 = tn * GBN;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    using Acc = MfmaAcc<T>;
+    typename Acc::V acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = typename Acc::V{0, 0, 0, 0};
+
+    const int lr = tid >> 4;          // 0..15: k row of the tile this thread loads
+    const int lc = (tid & 15) * 8;    // 8 consecutive columns
+    T ra[8], rb[8];
+    auto gload = [&](int k0) {
+        const int k = k0 + lr;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int mm = m0 + lc + e, nn = n0 + lc + e;
+            ra[e] = (k < P.K && mm < P.M) ? P.A[int64_t(k) * P.lda + mm] : T(0);
+            rb[e] = (k < P.K && nn < P.N) ? P.B[int64_t(k) * P.ldb + nn] : T(0);
+        }
+    };
+    gload(0);
+    for (int k0 = 0; k0 < P.K; k0 += GBK) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            As[lr][lc + e] = ra[e];
+            Bs[lr][lc + e] = rb[e];
+        }
+        __syncthreads();
+        if (k0 + GBK < P.K) gload(k0 + GBK);
+#pragma unroll
+        for (int kk = 0; kk < GBK / 4; ++kk) {
+            const int kr = kk * 4 + (lane >> 4);
+            T a[4], b[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) a[i] = As[kr][wm * 64 + i * 16 + (lane & 15)];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) b[j] = Bs[kr][wn * 64 + j * 16 + (lane & 15)];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] = Acc::mma(a[i], b[j], acc[i][j]);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int nn = n0 + wn * 64 + j * 16 + (lane & 15);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int mm = m0 + wm * 64 + i * 16 + Acc::row(lane, r);
+                if (mm < P.M && nn < P.N) P.C[int64_t(mm) * P.ldc + nn] = acc[i][j][r];
+            }
+        }
+    }
+}
+
+template <class T>
+hipError_t launch_gemm(GemmBatch<T> gb, hipStream_t s) {
+    int t = 0;
+    for (int i = 0; i < gb.nprob; ++i) {
+        auto& P = gb.pr[i];
+        const int tm = (P.M + GBM - 1) / GBM;
+        P.tiles_n = (P.N + GBN - 1) / GBN;
+        P.tile_begin = t;
+        t += tm * P.tiles_n;
+    }
+    gb.total_tiles = t;
+    if (t == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gemm<T>, dim3(t), dim3(256), 0, s, gb);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// S4: Givens sweeps.  One wave per (map, block, group of 32 columns k');
+// lane = (k', re/im).  Sweeps are applied in passes of SW consecutive
+// sweeps: values are streamed along the chain (l' ascending for analysis,
+// descending for synthesis) and every sweep of the pass keeps its carry in
+// registers; the rotation angles are the same for all lanes.
+// ---------------------------------------------------------------------------
+
+constexpr int SW = 8;
+constexpr int kSweepCols = 32;
+
+__device__ __forceinline__ void sweep_locate(const GroupDims& g, int& blk, int& grp, int& map) {
+    int w = blockIdx.x;
+    map = w % g.nmaps;
+    w /= g.nmaps;
+    blk = 0;
+    for (; blk < 4; ++blk) {
+        const int ng = (g.nk[blk] + kSweepCols - 1) / kSweepCols;
+        if (w < ng) break;
+        w -= ng;
+    }
+    grp = w;
+}
+
+template <class T>
+__global__ __launch_bounds__(64) void k_sweep_fwd(Blocks4<T> U, Blocks4<const T> G, GroupDims g) {
+    int blk, grp, map;
+    sweep_locate(g, blk, grp, map);
+    const int kpar = blk >> 1;
+    const int lane = threadIdx.x;
+    const int kk = grp * kSweepCols + (lane >> 1);
+    const int nk = g.nk[blk], nl = g.nl[blk], tpad = g.tpad[blk];
+    const int64_t N = g.N[kpar];
+    const bool valid = kk < nk;
+    const int kcol = valid ? kk : nk - 1;
+    T* col = U.p[blk] + int64_t(map) * g.Npm[kpar] + 2 * kcol + (lane & 1);
+    const T* Gt = G.p[blk];
+    const int tg = min(grp * kSweepCols + kSweepCols - 1, nk - 1);
+    for (int t0 = 1; t0 <= tg; t0 += SW) {
+        T carry[SW];
+#pragma unroll
+        for (int j = 0; j < SW; ++j) carry[j] = T(0);
+        for (int lp = t0 - 1; lp < nl; ++lp) {
+            T v = col[int64_t(lp) * N];
+            T vf = v;
+            const T* cs = Gt + (int64_t(lp) * tpad + (t0 - 1)) * 2;
+#pragma unroll
+            for (int j = 0; j < SW; ++j) {
+                const int t = t0 + j;
+                if (lp < t - 1) break;
+                if (lp == t - 1) {
+                    carry[j] = v;
+                    break;
+                }
+                const T c = cs[2 * j], s = cs[2 * j + 1];
+                const T nv = c * carry[j] + s * v;
+                carry[j] = c * v - s * carry[j];
+                v = nv;
+                if (t <= kk) vf = v;
+            }
+            if (valid) col[int64_t(lp) * N] = vf;
+        }
+    }
+}
+
+template <class T>
+__global__ __launch_bounds__(64) void k_sweep_bwd(Blocks4<T> U, Blocks4<const T> G, GroupDims g) {
+    int blk, grp, map;
+    sweep_locate(g, blk, grp, map);
+    const int kpar = blk >> 1;
+    const int lane = threadIdx.x;
+    const int kk = grp * kSweepCols + (lane >> 1);
+    const int nk = g.nk[blk], nl = g.nl[blk], tpad = g.tpad[blk];
+    const int64_t N = g.N[kpar];
+    const bool valid = kk < nk;
+    const int kcol = valid ? kk : nk - 1;
+    T* col = U.p[blk] + int64_t(map) * g.Npm[kpar] + 2 * kcol + (lane & 1);
+    const T* Gt = G.p[blk];
+    const int tg = min(grp * kSweepCols + kSweepCols - 1, nk - 1);
+    // passes from the highest sweep down; pass covers sweeps t1 .. t1 - SW + 1
+    for (int t1 = tg; t1 >= 1; t1 -= SW) {
+        const int t0 = t1 - SW + 1;   // may be < 1: those sweeps are skipped
+        T carry[SW];
+#pragma unroll
+        for (int j = 0; j < SW; ++j) carry[j] = T(0);
+        const int lo = max(t0 - 1, 0);
+        for (int lp = nl - 1; lp >= lo; --lp) {
+            T v = col[int64_t(lp) * N];
+            // sweep t = t1 - j, applied in order j = 0 .. SW-1
+#pragma unroll
+            for (int j = 0; j < SW; ++j) {
+                const int t = t1 - j;
+                if (t < 1) break;
+                const bool act = (t <= kk);
+                if (lp >= t) {
+                    const T* cs = Gt + (int64_t(lp) * tpad + (t - 1)) * 2;
+                    const T c = cs[0], s = cs[1];
+                    const T nv = s * v + c * carry[j];
+                    const T nc = c * v - s * carry[j];
+                    if (act) {
+                        v = nv;
+                        carry[j] = nc;
+                    }
+                } else if (lp == t - 1) {
+                    if (act) v = carry[j];
+                }
+            }
+            if (valid) col[int64_t(lp) * N] = v;
+        }
+    }
+}
+
+template <class T>
+static int sweep_waves(const GroupDims& g) {
+    int w = 0;
+    for (int b = 0; b < 4; ++b) w += (g.nk[b] + kSweepCols - 1) / kSweepCols;
+    return w * g.nmaps;
+}
+
+template <class T>
+hipError_t launch_sweep_fwd(Blocks4<T> U, Blocks4<const T> G, const GroupDims& g, hipStream_t s) {
+    hipLaunchKernelGGL(k_sweep_fwd<T>, dim3(sweep_waves<T>(g)), dim3(64), 0, s, U, G, g);
+    return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_sweep_bwd(Blocks4<T> U, Blocks4<const T> G, const GroupDims& g, hipStream_t s) {
+    hipLaunchKernelGGL(k_sweep_bwd<T>, dim3(sweep_waves<T>(g)), dim3(64), 0, s, U, G, g);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// pack / unpack between U and the packed complex128 alm
+// ---------------------------------------------------------------------------
+
+// one thread per (map, block, l', k') complex entry
+template <class T>
+__global__ void k_pack(Blocks4<const T> U, double* __restrict__ alm, const int64_t* __restrict__ alm_off,
+                       const int32_t* __restrict__ lmaxv, GroupDims g, int accumulate) {
+    const int blk = blockIdx.z;
+    const int map = blockIdx.y;
+    const int kpar = blk >> 1;
+    const int nk = g.nk[blk], nl = g.nl[blk];
+    const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (idx >= int64_t(nk) * nl) return;
+    const int lp = int(idx / nk), kk = int(idx % nk);
+    const int l = g.lmin[blk] + 2 * lp, m = 2 * kk + kpar;
+    const int L = lmaxv[map];
+    if (l < m || l > L) return;
+    const T* src = U.p[blk] + int64_t(lp) * g.N[kpar] + int64_t(map) * g.Npm[kpar] + 2 * kk;
+    const int64_t o = 2 * (alm_off[map] + int64_t(m) * (2 * L + 1 - m) / 2 + l);
+    const double re = double(src[0]), im = double(src[1]);
+    if (accumulate) {
+        alm[o] += re;
+        alm[o + 1] += im;
+    } else {
+        alm[o] = re;
+        alm[o + 1] = im;
+    }
+}
+
+template <class T>
+hipError_t launch_pack(Blocks4<const T> U, double* alm, const int64_t* alm_off, const int32_t* lmax,
+                       const GroupDims& g, bool accumulate, hipStream_t s) {
+    int64_t most = 0;
+    for (int b = 0; b < 4; ++b) most = std::max<int64_t>(most, int64_t(g.nk[b]) * g.nl[b]);
+    dim3 grid(unsigned((most + 255) / 256), g.nmaps, 4);
+    hipLaunchKernelGGL(k_pack<T>, grid, dim3(256), 0, s, U, alm, alm_off, lmax, g, accumulate ? 1 : 0);
+    return hipGetLastError();
+}
+
+__global__ void k_unpack(const double* __restrict__ alm, const int64_t* __restrict__ alm_off,
+                         const int32_t* __restrict__ lmaxv, Blocks4<double> U, GroupDims g) {
+    const int blk = blockIdx.z;
+    const int map = blockIdx.y;
+    const int kpar = blk >> 1;
+    const int nk = g.nk[blk], nl = g.nl[blk];
+    const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (idx >= int64_t(nk) * nl) return;
+    const int lp = int(idx / nk), kk = int(idx % nk);
+    const int l = g.lmin[blk] + 2 * lp, m = 2 * kk + kpar;
+    const int L = lmaxv[map];
+    double re = 0.0, im = 0.0;
+    if (l >= m && l <= L) {
+        const int64_t o = 2 * (alm_off[map] + int64_t(m) * (2 * L + 1 - m) / 2 + l);
+        re = alm[o];
+        im = alm[o + 1];
+    }
+    double* dst = U.p[blk] + int64_t(lp) * g.N[kpar] + int64_t(map) * g.Npm[kpar] + 2 * kk;
+    dst[0] = re;
+    dst[1] = im;
+}
+
+hipError_t launch_unpack(const double* alm, const int64_t* alm_off, const int32_t* lmax, Blocks4<double> U,
+                         const GroupDims& g, hipStream_t s) {
+    int64_t most = 0;
+    for (int b = 0; b < 4; ++b) most = std::max<int64_t>(most, int64_t(g.nk[b]) * g.nl[b]);
+    dim3 grid(unsigned((most + 255) / 256), g.nmaps, 4);
+    hipLaunchKernelGGL(k_unpack, grid, dim3(256), 0, s, alm, alm_off, lmax, U, g);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Synthesis: inverse ring transform (+ residual)
+// ---------------------------------------------------------------------------
+
+// e^{+i pi k / n} for any k >= 0 from the table e^{-i pi k'/n}, k' = 0..n
+__device__ __forceinline__ C2<double> eplus(const double* roots, int64_t k, int n) {
+    const int64_t kk = k % (2 * int64_t(n));
+    if (kk <= n) return cconj(ldc(roots, kk));
+    const C2<double> r = ldc(roots, kk - n);
+    return {-r.x, r.y};   // -conj(r)
+}
+
+__device__ void ring_synth(const Blocks4<const double>& D, int h, int sgn, int n, bool shifted, int p,
+                           const GroupDims& g, int map, FftTab<double> ft, C2<double>* buf, double* out,
+                           const double* minus_from) {
+    const int L = n >> 1, j = n >> 2;
+    const int Mb = ft.chirpm[j];
+    const double* roots = ft.roots + 2 * ft.rootoff[j];
+    // G_k = D_k e^{i k phi0}, D_k = D+_k + sgn D-_k
+    auto Gk = [&](int k) -> C2<double> {
+        const int kpar = k & 1, kk = k >> 1;
+        const int64_t o = int64_t(h) * g.N[kpar] + int64_t(map) * g.Npm[kpar] + 2 * kk;
+        const double* bp = D.p[2 * kpar];
+        const double* bm = D.p[2 * kpar + 1];
+        C2<double> d = {bp[o] + sgn * bm[o], bp[o + 1] + sgn * bm[o + 1]};
+        if (shifted) d = cmul(d, eplus(roots, k, n));
+        return d;
+    };
+    // H_t = sum_{k = t mod n} G_k + conj(sum_{k>0, k = -t mod n} G_k)
+    auto Ht = [&](int t) -> C2<double> {
+        C2<double> a = {0.0, 0.0}, bsum = {0.0, 0.0};
+        for (int k = t; k <= p; k += n) a = cadd(a, Gk(k));
+        for (int k = (t == 0 ? n : n - t); k <= p; k += n) bsum = cadd(bsum, Gk(k));
+        return cadd(a, cconj(bsum));
+    };
+    // Z'_t = (H_t + conj H_{L-t}) + i (H_t - conj H_{L-t}) e^{2 pi i t / n};
+    // the inverse DFT of length L is conj(DFT(conj Z')).
+    auto src = [&](int t) -> C2<double> {
+        const C2<double> ht = Ht(t), hl = Ht(L - t);
+        const C2<double> e = cadd(ht, cconj(hl));
+        const C2<double> o = cmul(csub(ht, cconj(hl)), cconj(ldc(roots, 2 * t)));
+        const C2<double> z = {e.x - o.y, e.y + o.x};
+        return cconj(z);
+    };
+    const double* chirp = ft.chirp + 2 * ft.chirpoff[j];
+    const double* chirpfft = ft.chirpfft + 2 * ft.chirpfftoff[j];
+    DftResult<double> R = lds_dft<double>(buf, L, Mb, chirp, chirpfft, ft.twiddle, ft.fft_max, src);
+    for (int q = threadIdx.x; q < L; q += blockDim.x) {
+        const C2<double> z = cconj(R.Z(q));
+        double v0 = z.x, v1 = z.y;
+        if (minus_from) {
+            v0 = minus_from[2 * q] - v0;
+            v1 = minus_from[2 * q + 1] - v1;
+        }
+        out[2 * q] = v0;
+        out[2 * q + 1] = v1;
+    }
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(kRingThreads) void k_ring_inverse(Blocks4<const double> D, RingTab rt,
+                                                               FftTab<double> ft, double* out,
+                                                               const double* minus_from,
+                                                               const int64_t* __restrict__ map_off, GroupDims g) {
+    extern __shared__ unsigned char smem_raw[];
+    C2<double>* buf = reinterpret_cast<C2<double>*>(smem_raw);
+    const int h = blockIdx.x + 1;
+    const int map = blockIdx.y;
+    const int ns = g.nside;
+    const int64_t mo = map_off[map];
+    {
+        const int r0 = h - 1;
+        const int64_t st = mo + rt.start[r0];
+        ring_synth(D, h, +1, rt.n[r0], rt.shifted[r0] != 0, g.p, g, map, ft, buf, out + st,
+                   minus_from ? minus_from + st : nullptr);
+    }
+    if (h < 2 * ns) {
+        const int r0 = 4 * ns - h - 1;
+        const int64_t st = mo + rt.start[r0];
+        ring_synth(D, h, -1, rt.n[r0], rt.shifted[r0] != 0, g.p, g, map, ft, buf, out + st,
+                   minus_from ? minus_from + st : nullptr);
+    }
+}
+
+hipError_t launch_ring_inverse(Blocks4<const double> D, RingTab rt, FftTab<double> ft, double* out,
+                               const double* minus_from, const int64_t* map_off, const GroupDims& g,
+                               hipStream_t s) {
+    dim3 grid(2 * g.nside, g.nmaps);
+    size_t shm = size_t(ft.fft_max) * sizeof(C2<double>);
+    hipLaunchKernelGGL(k_ring_inverse, grid, dim3(kRingThreads), shm, s, D, rt, ft, out, minus_from, map_off, g);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// S5: C_l
+// ---------------------------------------------------------------------------
+
+__global__ void k_cl(const double* __restrict__ alm, const int64_t* __restrict__ alm_off,
+                     const int32_t* __restrict__ lmaxv, double* __restrict__ cl, const int64_t* __restrict__ cl_off) {
+    const int map = blockIdx.y;
+    const int L = lmaxv[map];
+    const int l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l > L) return;
+    const double* a = alm + 2 * alm_off[map];
+    double s = 0.0;
+    for (int m = 0; m <= l; ++m) {
+        const int64_t o = 2 * (int64_t(m) * (2 * L + 1 - m) / 2 + l);
+        const double re = a[o], im = a[o + 1];
+        const double v = re * re + im * im;
+        s += (m == 0) ? v : 2.0 * v;
+    }
+    cl[cl_off[map] + l] = s / (2.0 * l + 1.0);
+}
+
+hipError_t launch_cl(const double* alm, const int64_t* alm_off, const int32_t* lmax, double* cl,
+                     const int64_t* cl_off, int nmaps, int lmax_max, hipStream_t s) {
+    dim3 grid(unsigned((lmax_max + 1 + 127) / 128), nmaps);
+    hipLaunchKernelGGL(k_cl, grid, dim3(128), 0, s, alm, alm_off, lmax, cl, cl_off);
+    return hipGetLastError();
+}
+
+hipError_t configure_kernels() {
+    const int bytes = 160 * 1024;
+    hipError_t e;
+    if ((e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_ring_forward<double>),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, bytes)) != hipSuccess) return e;
+    if ((e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_ring_forward<float>),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, bytes)) != hipSuccess) return e;
+    if ((e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_ring_inverse),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, bytes)) != hipSuccess) return e;
+    return hipSuccess;
+}
+
+// explicit instantiations
+template hipError_t launch_ring_forward<double>(const double*, const int64_t*, RingTab, FftTab<double>,
+                                                Blocks4<double>, const GroupDims&, hipStream_t);
+template hipError_t launch_ring_forward<float>(const double*, const int64_t*, RingTab, FftTab<float>,
+                                               Blocks4<float>, const GroupDims&, hipStream_t);
+template hipError_t launch_pole<double>(Blocks4<double>, const GroupDims&, double, double, double, hipStream_t);
+template hipError_t launch_pole<float>(Blocks4<float>, const GroupDims&, double, double, double, hipStream_t);
+template hipError_t launch_gemm<double>(GemmBatch<double>, hipStream_t);
+template hipError_t launch_gemm<float>(GemmBatch<float>, hipStream_t);
+template hipError_t launch_sweep_fwd<double>(Blocks4<double>, Blocks4<const double>, const GroupDims&, hipStream_t);
+template hipError_t launch_sweep_fwd<float>(Blocks4<float>, Blocks4<const float>, const GroupDims&, hipStream_t);
+template hipError_t launch_sweep_bwd<double>(Blocks4<double>, Blocks4<const double>, const GroupDims&, hipStream_t);
+template hipError_t launch_pack<double>(Blocks4<const double>, double*, const int64_t*, const int32_t*,
+                                        const GroupDims&, bool, hipStream_t);
+template hipError_t launch_pack<float>(Blocks4<const float>, double*, const int64_t*, const int32_t*,
+                                       const GroupDims&, bool, hipStream_t);
+
+}  // namespace hp2sph
