@@ -135,6 +135,22 @@ int hp2sph_plan_destroy(hp2sph_plan_t plan);
 const char* hp2sph_last_error(void);
 
 /*
+ * Per-stage timing with HIP events recorded on the caller's stream around
+ * every kernel launch of the plan (for benchmarks; adds two event records per
+ * launch).  hp2sph_profile(plan, 1) clears the accumulators and starts
+ * recording; hp2sph_profile(plan, 0) stops.  hp2sph_profile_read waits for the
+ * recorded events and returns, per stage, the summed milliseconds and the
+ * number of launches (arrays of length nstages, at most HP2SPH_NSTAGES).
+ * Stages: 0 ring transform (S1), 1 pole values (S2), 2 analysis GEMM (S3),
+ * 3 analysis Givens sweeps (S4), 4 pack a_lm, 5 unpack a_lm, 6 synthesis
+ * sweeps, 7 synthesis GEMM, 8 inverse ring transform and residual, 9 C_l (S5).
+ * Errors: ESTATE, EINVAL, EDEVICE.
+ */
+#define HP2SPH_NSTAGES 10
+int hp2sph_profile(hp2sph_plan_t plan, int32_t enable);
+int hp2sph_profile_read(hp2sph_plan_t plan, double* ms, int32_t* launches, int32_t nstages);
+
+/*
  * Host-only inspection of the set-up tables (no GPU needed; used by tests).
  * Writes up to `capacity` doubles of table `table` for `nside` into `out`
  * and the full element count into *count (out may be NULL to query the

@@ -58,7 +58,7 @@ import numpy as np
 import scipy.linalg
 
 from .geometry import ring_table, pixel_xyz
-from .legendre import gauss_legendre, plm_rows
+from .legendre import gauss_legendre, plm_orthonormal, plm_rows
 
 
 # --------------------------------------------------------------------------
@@ -235,6 +235,15 @@ def _project(G_at_nodes, ks, nodes, weights, lmax):
     sign = np.where(ks < 0, (-1.0) ** am, 1.0)
     wg = G_at_nodes * weights[None, :]
     out = np.zeros((lmax + 1, len(ks)), dtype=np.complex128)
+    if len(ks) <= 8:
+        # few orders: one recurrence per order instead of all orders at once
+        for i, k in enumerate(ks):
+            a = abs(int(k))
+            if a > lmax:
+                continue
+            P = plm_orthonormal(lmax, a, nodes)           # rows l = |k| .. lmax
+            out[a:, i] = np.sqrt(2.0 * np.pi) * sign[i] * (P @ wg[i])
+        return out
     for l, P in plm_rows(lmax, nodes):
         sel = am <= l
         if not np.any(sel):

@@ -26,7 +26,7 @@ LIB_PATH = os.path.join(_HERE, "libhp2sph.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(
-        "libhp2sph.so is not built; run `python -m paper_1904_10514_amd.build` "
+        "libhp2sph.so is not built; run `python paper_1904_10514_amd/build.py` "
         "(hipcc, gfx950) before importing paper_1904_10514_amd")
 
 _lib = ctypes.CDLL(LIB_PATH)
@@ -40,7 +40,11 @@ MAX_NSIDE = 2048
 EXPORTED = [
     "hp2sph_plan_create", "hp2sph_workspace_size", "hp2sph_analyze", "hp2sph_synthesize",
     "hp2sph_power_spectrum", "hp2sph_plan_destroy", "hp2sph_last_error", "hp2sph_host_table",
+    "hp2sph_profile", "hp2sph_profile_read",
 ]
+NSTAGES = 10
+STAGES = ["ring_forward", "pole", "gemm_analysis", "sweep_analysis", "pack", "unpack",
+          "sweep_synthesis", "gemm_synthesis", "ring_inverse_residual", "cl"]
 
 _vp = ctypes.c_void_p
 _i32 = ctypes.c_int32
@@ -51,6 +55,8 @@ _lib.hp2sph_synthesize.argtypes = [_vp, _vp, _vp, _vp, _vp]
 _lib.hp2sph_power_spectrum.argtypes = [_vp, _vp, _vp, _vp]
 _lib.hp2sph_plan_destroy.argtypes = [_vp]
 _lib.hp2sph_last_error.restype = ctypes.c_char_p
+_lib.hp2sph_profile.argtypes = [_vp, _i32]
+_lib.hp2sph_profile_read.argtypes = [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i32), _i32]
 _lib.hp2sph_host_table.argtypes = [_i32, _i32, _i32, _vp, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
 for _f in EXPORTED:
     if _f not in ("hp2sph_last_error",):
@@ -174,6 +180,17 @@ class Plan:
         _check(_lib.hp2sph_power_spectrum(self._h, alm.data_ptr(), out.data_ptr(), self._stream()),
                "power_spectrum")
         return out
+
+    def profile(self, enable):
+        """Start (True, clears the accumulators) or stop per-stage event timing."""
+        _check(_lib.hp2sph_profile(self._h, 1 if enable else 0), "profile")
+
+    def profile_read(self):
+        """{stage: (total ms, launches)} accumulated since profile(True)."""
+        ms = (ctypes.c_double * NSTAGES)()
+        n = (_i32 * NSTAGES)()
+        _check(_lib.hp2sph_profile_read(self._h, ms, n, NSTAGES), "profile_read")
+        return {STAGES[i]: (ms[i], n[i]) for i in range(NSTAGES)}
 
     def close(self):
         if getattr(self, "_h", None):

@@ -1,6 +1,9 @@
 """Build libhp2sph.so (gfx950) in-tree with hipcc.
 
-Usage: python -m paper_1904_10514_amd.build   (or build() from Python)
+Usage: python paper_1904_10514_amd/build.py [-v]
+
+Run by path: it must not import the package, whose __init__ loads the
+library this script produces.
 """
 
 import os

@@ -90,7 +90,58 @@ struct Group {
 }  // namespace
 }  // namespace hp2sph
 
+namespace hp2sph {
+namespace {
+// HIP-event timing of stage launches (see hp2sph_profile in hp2sph.h)
+struct Profiler {
+    bool on = false;
+    struct Rec {
+        int stage;
+        hipEvent_t a, b;
+    };
+    std::vector<Rec> pending;
+    std::vector<hipEvent_t> pool;
+    double ms[HP2SPH_NSTAGES] = {};
+    int launches[HP2SPH_NSTAGES] = {};
+    hipEvent_t get() {
+        if (!pool.empty()) {
+            hipEvent_t e = pool.back();
+            pool.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+    hipError_t drain() {
+        for (auto& r : pending) {
+            hipError_t e = hipEventSynchronize(r.b);
+            if (e != hipSuccess) return e;
+            float t = 0.f;
+            e = hipEventElapsedTime(&t, r.a, r.b);
+            if (e != hipSuccess) return e;
+            ms[r.stage] += t;
+            launches[r.stage] += 1;
+            pool.push_back(r.a);
+            pool.push_back(r.b);
+        }
+        pending.clear();
+        return hipSuccess;
+    }
+    ~Profiler() {
+        for (auto& r : pending) {
+            (void)hipEventDestroy(r.a);
+            (void)hipEventDestroy(r.b);
+        }
+        for (auto e : pool) (void)hipEventDestroy(e);
+    }
+};
+thread_local Profiler* g_prof = nullptr;   // profiler of the plan being executed
+}  // namespace
+}  // namespace hp2sph
+
 struct hp2sph_plan_s {
+    hp2sph::Profiler prof;
     int batch = 0;
     int mode = 0;
     int device = 0;
@@ -237,6 +288,22 @@ Blocks4<const T> cblocks(Blocks4<T> b) {
     return o;
 }
 
+// Launch `expr` as stage `st`, bracketed by events when profiling is on.
+#define STAGE(st, expr)                                                                        \
+    do {                                                                                       \
+        hipEvent_t ea_ = nullptr, eb_ = nullptr;                                               \
+        if (g_prof && g_prof->on) {                                                            \
+            ea_ = g_prof->get();                                                               \
+            eb_ = g_prof->get();                                                               \
+            if (ea_) (void)hipEventRecord(ea_, s);                                             \
+        }                                                                                      \
+        HIPCHK(expr);                                                                          \
+        if (ea_ && eb_) {                                                                      \
+            (void)hipEventRecord(eb_, s);                                                      \
+            g_prof->pending.push_back({st, ea_, eb_});                                         \
+        }                                                                                      \
+    } while (0)
+
 #define HIPCHK(expr)                                                                          \
     do {                                                                                      \
         hipError_t e_ = (expr);                                                               \
@@ -257,8 +324,8 @@ int analysis_pass(Group& G, const double* maps_in, double* alm, void* ws, bool a
     DevTables<T>& t = tabs<T>(G);
     Blocks4<T> D = blocks_at<T>(ws, G.off_D, G, G.rows_D);
     Blocks4<T> U = blocks_at<T>(ws, G.off_U, G, G.rows_U);
-    HIPCHK(launch_ring_forward<T>(maps_in, G.d_map_off, G.rings, t.fft, D, G.dims, s));
-    HIPCHK(launch_pole<T>(D, G.dims, G.pole_w[0], G.pole_w[1], G.pole_w[2], s));
+    STAGE(0, launch_ring_forward<T>(maps_in, G.d_map_off, G.rings, t.fft, D, G.dims, s));
+    STAGE(1, launch_pole<T>(D, G.dims, G.pole_w[0], G.pole_w[1], G.pole_w[2], s));
     GemmBatch<T> gb{};
     gb.nprob = 4;
     for (int b = 0; b < 4; ++b) {
@@ -274,11 +341,11 @@ int analysis_pass(Group& G, const double* maps_in, double* alm, void* ws, bool a
         P.ldb = G.dims.N[kpar];
         P.ldc = G.dims.N[kpar];
     }
-    HIPCHK(launch_gemm<T>(gb, s));
+    STAGE(2, launch_gemm<T>(gb, s));
     Blocks4<const T> Gv;
     for (int b = 0; b < 4; ++b) Gv.p[b] = t.givens[b];
-    HIPCHK(launch_sweep_fwd<T>(U, Gv, G.dims, s));
-    HIPCHK(launch_pack<T>(cblocks(U), alm, G.d_alm_off, G.d_lmax, G.dims, accumulate, s));
+    STAGE(3, launch_sweep_fwd<T>(U, Gv, G.dims, s));
+    STAGE(4, launch_pack<T>(cblocks(U), alm, G.d_alm_off, G.d_lmax, G.dims, accumulate, s));
     return HP2SPH_OK;
 }
 
@@ -286,10 +353,10 @@ int analysis_pass(Group& G, const double* maps_in, double* alm, void* ws, bool a
 int synthesis_pass(Group& G, const double* alm, double* out, const double* minus_from, void* ws, hipStream_t s) {
     Blocks4<double> D = blocks_at<double>(ws, G.off_D, G, G.rows_D);
     Blocks4<double> U = blocks_at<double>(ws, G.off_U, G, G.rows_U);
-    HIPCHK(launch_unpack(alm, G.d_alm_off, G.d_lmax, U, G.dims, s));
+    STAGE(5, launch_unpack(alm, G.d_alm_off, G.d_lmax, U, G.dims, s));
     Blocks4<const double> Gv;
     for (int b = 0; b < 4; ++b) Gv.p[b] = G.t64.givens[b];
-    HIPCHK(launch_sweep_bwd<double>(U, Gv, G.dims, s));
+    STAGE(6, launch_sweep_bwd<double>(U, Gv, G.dims, s));
     GemmBatch<double> gb{};
     gb.nprob = 4;
     for (int b = 0; b < 4; ++b) {
@@ -305,8 +372,8 @@ int synthesis_pass(Group& G, const double* alm, double* out, const double* minus
         P.ldb = G.dims.N[kpar];
         P.ldc = G.dims.N[kpar];
     }
-    HIPCHK(launch_gemm<double>(gb, s));
-    HIPCHK(launch_ring_inverse(cblocks(D), G.rings, G.t64.fft, out, minus_from, G.d_map_off, G.dims, s));
+    STAGE(7, launch_gemm<double>(gb, s));
+    STAGE(8, launch_ring_inverse(cblocks(D), G.rings, G.t64.fft, out, minus_from, G.d_map_off, G.dims, s));
     return HP2SPH_OK;
 }
 
@@ -396,6 +463,7 @@ int hp2sph_workspace_size(hp2sph_plan_t plan, size_t* bytes) {
 
 int hp2sph_analyze(hp2sph_plan_t plan, const double* maps, double* alm, void* workspace, void* stream) {
     if (int e = check_plan(plan)) return e;
+    g_prof = &plan->prof;
     if (!maps || !alm) return fail(HP2SPH_EINVAL, "maps/alm is null");
     if (!aligned(maps, 8) || !aligned(alm, 16)) return fail(HP2SPH_EINVAL, "maps/alm misaligned");
     if (!workspace || !aligned(workspace, kAlign)) return fail(HP2SPH_EWORKSPACE, "workspace null or not 256-byte aligned");
@@ -418,6 +486,7 @@ int hp2sph_analyze(hp2sph_plan_t plan, const double* maps, double* alm, void* wo
 
 int hp2sph_synthesize(hp2sph_plan_t plan, const double* alm, double* maps, void* workspace, void* stream) {
     if (int e = check_plan(plan)) return e;
+    g_prof = &plan->prof;
     if (!maps || !alm) return fail(HP2SPH_EINVAL, "maps/alm is null");
     if (!aligned(maps, 8) || !aligned(alm, 16)) return fail(HP2SPH_EINVAL, "maps/alm misaligned");
     if (!workspace || !aligned(workspace, kAlign)) return fail(HP2SPH_EWORKSPACE, "workspace null or not 256-byte aligned");
@@ -429,12 +498,37 @@ int hp2sph_synthesize(hp2sph_plan_t plan, const double* alm, double* maps, void*
 
 int hp2sph_power_spectrum(hp2sph_plan_t plan, const double* alm, double* cl, void* stream) {
     if (int e = check_plan(plan)) return e;
+    g_prof = &plan->prof;
     if (!alm || !cl) return fail(HP2SPH_EINVAL, "alm/cl is null");
     if (!aligned(alm, 16) || !aligned(cl, 8)) return fail(HP2SPH_EINVAL, "alm/cl misaligned");
     hipStream_t s = static_cast<hipStream_t>(stream);
     for (auto& gp : plan->groups) {
         Group& G = *gp;
-        HIPCHK(launch_cl(alm, G.d_alm_off, G.d_lmax, cl, G.d_cl_off, G.dims.nmaps, G.lmax_max, s));
+        STAGE(9, launch_cl(alm, G.d_alm_off, G.d_lmax, cl, G.d_cl_off, G.dims.nmaps, G.lmax_max, s));
+    }
+    return HP2SPH_OK;
+}
+
+int hp2sph_profile(hp2sph_plan_t plan, int32_t enable) {
+    if (int e = check_plan(plan)) return e;
+    if (hipError_t e = plan->prof.drain(); e != hipSuccess) return fail(HP2SPH_EDEVICE, hipGetErrorString(e));
+    if (enable) {
+        for (int i = 0; i < HP2SPH_NSTAGES; ++i) {
+            plan->prof.ms[i] = 0.0;
+            plan->prof.launches[i] = 0;
+        }
+    }
+    plan->prof.on = enable != 0;
+    return HP2SPH_OK;
+}
+
+int hp2sph_profile_read(hp2sph_plan_t plan, double* ms, int32_t* launches, int32_t nstages) {
+    if (int e = check_plan(plan)) return e;
+    if (!ms || !launches || nstages < 0 || nstages > HP2SPH_NSTAGES) return fail(HP2SPH_EINVAL, "bad arguments");
+    if (hipError_t e = plan->prof.drain(); e != hipSuccess) return fail(HP2SPH_EDEVICE, hipGetErrorString(e));
+    for (int i = 0; i < nstages; ++i) {
+        ms[i] = plan->prof.ms[i];
+        launches[i] = plan->prof.launches[i];
     }
     return HP2SPH_OK;
 }

@@ -373,119 +373,236 @@ hipError_t launch_gemm(GemmBatch<T> gb, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
-// S4: Givens sweeps.  One wave per (map, block, group of 32 columns k');
-// lane = (k', re/im).  Sweeps are applied in passes of SW consecutive
-// sweeps: values are streamed along the chain (l' ascending for analysis,
-// descending for synthesis) and every sweep of the pass keeps its carry in
-// registers; the rotation angles are the same for all lanes.
+// S4: Givens sweeps.
+//
+// Column k' of block b needs sweeps t = 1 .. k' (order m' = 2t + kpar) in
+// that order for analysis (each sweep: a carry runs up the chain l' = t-1 ..
+// nl-1, rotating (carry, x[l']) and dropping the final carry), and t = k' ..
+// 1 with the transposed rotations for synthesis (a zero carry runs down the
+// chain and is deposited at l' = t-1).  The angles depend on (t, l') only.
+//
+// One workgroup = SW_WAVES waves on the same 32 columns k' (lane = (k',
+// re/im)) of one map and block.  Sweeps are grouped in aligned blocks of
+// SW = 8 (t = 8q+1 .. 8q+8); in one pass wave w applies block q0 + w, so a
+// pass applies SW * SW_WAVES sweeps.  Chain values stream through the waves
+// in chunks of SW_CHUNK positions: wave 0 reads from global memory, hands
+// each chunk to wave 1 through LDS, .., the last wave writes back; at step s
+// wave w works on chunk s - w, with a barrier per step.  The carries of a
+// wave's SW sweeps stay in registers for the whole pass; the angles are the
+// same for every lane and come through the scalar cache.  Columns that need
+// fewer sweeps than their neighbours are masked per lane only in the wave
+// blocks that contain their last sweep.
 // ---------------------------------------------------------------------------
 
 constexpr int SW = 8;
+constexpr int SW_WAVES = 16;
+constexpr int SW_CHUNK = 4;
 constexpr int kSweepCols = 32;
 
 __device__ __forceinline__ void sweep_locate(const GroupDims& g, int& blk, int& grp, int& map) {
+    // work items ordered longest first: highest column groups of all blocks first
     int w = blockIdx.x;
     map = w % g.nmaps;
     w /= g.nmaps;
+    int ng[4], gmax = 0;
+    for (int b = 0; b < 4; ++b) {
+        ng[b] = (g.nk[b] + kSweepCols - 1) / kSweepCols;
+        gmax = max(gmax, ng[b]);
+    }
+    for (int r = gmax - 1; r >= 0; --r) {
+        for (int b = 0; b < 4; ++b) {
+            if (r < ng[b]) {
+                if (w == 0) {
+                    blk = b;
+                    grp = r;
+                    return;
+                }
+                --w;
+            }
+        }
+    }
     blk = 0;
-    for (; blk < 4; ++blk) {
-        const int ng = (g.nk[blk] + kSweepCols - 1) / kSweepCols;
-        if (w < ng) break;
-        w -= ng;
-    }
-    grp = w;
+    grp = 0;
 }
 
+// The angle table is read-only while a sweep kernel runs: reading it through
+// the constant address space lets wave-uniform loads use the scalar cache.
 template <class T>
-__global__ __launch_bounds__(64) void k_sweep_fwd(Blocks4<T> U, Blocks4<const T> G, GroupDims g) {
-    int blk, grp, map;
-    sweep_locate(g, blk, grp, map);
-    const int kpar = blk >> 1;
-    const int lane = threadIdx.x;
-    const int kk = grp * kSweepCols + (lane >> 1);
-    const int nk = g.nk[blk], nl = g.nl[blk], tpad = g.tpad[blk];
-    const int64_t N = g.N[kpar];
-    const bool valid = kk < nk;
-    const int kcol = valid ? kk : nk - 1;
-    T* col = U.p[blk] + int64_t(map) * g.Npm[kpar] + 2 * kcol + (lane & 1);
-    const T* Gt = G.p[blk];
-    const int tg = min(grp * kSweepCols + kSweepCols - 1, nk - 1);
-    for (int t0 = 1; t0 <= tg; t0 += SW) {
-        T carry[SW];
+using ConstPtr = const __attribute__((address_space(4))) T*;
+
+template <class T>
+__device__ __forceinline__ ConstPtr<T> as_const(const T* p) {
+    return (ConstPtr<T>)(p);
+}
+
+// forward sweeps of one wave over one position lp
+template <class T, bool MASK>
+__device__ __forceinline__ T fwd_position(T v, int lp, int tb, int tg, int kk, T (&carry)[SW], ConstPtr<T> cs) {
+    T vf = v;
 #pragma unroll
-        for (int j = 0; j < SW; ++j) carry[j] = T(0);
-        for (int lp = t0 - 1; lp < nl; ++lp) {
-            T v = col[int64_t(lp) * N];
-            T vf = v;
-            const T* cs = Gt + (int64_t(lp) * tpad + (t0 - 1)) * 2;
-#pragma unroll
-            for (int j = 0; j < SW; ++j) {
-                const int t = t0 + j;
-                if (lp < t - 1) break;
-                if (lp == t - 1) {
-                    carry[j] = v;
-                    break;
-                }
-                const T c = cs[2 * j], s = cs[2 * j + 1];
-                const T nv = c * carry[j] + s * v;
-                carry[j] = c * v - s * carry[j];
-                v = nv;
-                if (t <= kk) vf = v;
-            }
-            if (valid) col[int64_t(lp) * N] = vf;
+    for (int j = 0; j < SW; ++j) {
+        const int t = tb + j;
+        if (t > tg || lp < t - 1) break;
+        if (lp == t - 1) {
+            carry[j] = v;
+            break;
+        }
+        const T c = cs[2 * j], s = cs[2 * j + 1];
+        const T nv = c * carry[j] + s * v;
+        carry[j] = c * v - s * carry[j];
+        v = nv;
+        if (MASK) {
+            if (t <= kk) vf = v;
+        } else {
+            vf = v;
         }
     }
+    return vf;
 }
 
 template <class T>
-__global__ __launch_bounds__(64) void k_sweep_bwd(Blocks4<T> U, Blocks4<const T> G, GroupDims g) {
+__global__ __launch_bounds__(64 * SW_WAVES) void k_sweep_fwd(Blocks4<T> U, Blocks4<const T> G, GroupDims g) {
+    __shared__ T slots[SW_WAVES][2][SW_CHUNK][64];
     int blk, grp, map;
     sweep_locate(g, blk, grp, map);
     const int kpar = blk >> 1;
-    const int lane = threadIdx.x;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
+    const int lane = threadIdx.x & 63;
     const int kk = grp * kSweepCols + (lane >> 1);
     const int nk = g.nk[blk], nl = g.nl[blk], tpad = g.tpad[blk];
     const int64_t N = g.N[kpar];
     const bool valid = kk < nk;
     const int kcol = valid ? kk : nk - 1;
     T* col = U.p[blk] + int64_t(map) * g.Npm[kpar] + 2 * kcol + (lane & 1);
-    const T* Gt = G.p[blk];
+    const T* __restrict__ Gt = G.p[blk];
     const int tg = min(grp * kSweepCols + kSweepCols - 1, nk - 1);
-    // passes from the highest sweep down; pass covers sweeps t1 .. t1 - SW + 1
-    for (int t1 = tg; t1 >= 1; t1 -= SW) {
-        const int t0 = t1 - SW + 1;   // may be < 1: those sweeps are skipped
+    const int kmin = grp * kSweepCols;
+    for (int t0 = 1; t0 <= tg; t0 += SW * SW_WAVES) {
+        const int tb = t0 + wave * SW;                 // first sweep of this wave
+        const bool busy = tb <= tg;
+        const bool mask = busy && (tb + SW - 1 > kmin);
         T carry[SW];
 #pragma unroll
         for (int j = 0; j < SW; ++j) carry[j] = T(0);
-        const int lo = max(t0 - 1, 0);
-        for (int lp = nl - 1; lp >= lo; --lp) {
-            T v = col[int64_t(lp) * N];
-            // sweep t = t1 - j, applied in order j = 0 .. SW-1
+        const int lp0 = t0 - 1;
+        const int nchunks = (nl - lp0 + SW_CHUNK - 1) / SW_CHUNK;
+        for (int s = 0; s < nchunks + SW_WAVES - 1; ++s) {
+            const int c = s - wave;
+            if (c >= 0 && c < nchunks) {
 #pragma unroll
-            for (int j = 0; j < SW; ++j) {
-                const int t = t1 - j;
-                if (t < 1) break;
-                const bool act = (t <= kk);
-                if (lp >= t) {
-                    const T* cs = Gt + (int64_t(lp) * tpad + (t - 1)) * 2;
-                    const T c = cs[0], s = cs[1];
-                    const T nv = s * v + c * carry[j];
-                    const T nc = c * v - s * carry[j];
-                    if (act) {
-                        v = nv;
-                        carry[j] = nc;
+                for (int i = 0; i < SW_CHUNK; ++i) {
+                    const int lp = lp0 + c * SW_CHUNK + i;
+                    T v;
+                    if (wave == 0) v = (lp < nl) ? col[int64_t(lp) * N] : T(0);
+                    else v = slots[wave][c & 1][i][lane];
+                    if (busy && lp < nl) {
+                        ConstPtr<T> cs = as_const(Gt + (int64_t(lp) * tpad + (tb - 1)) * 2);
+                        v = mask ? fwd_position<T, true>(v, lp, tb, tg, kk, carry, cs)
+                                 : fwd_position<T, false>(v, lp, tb, tg, kk, carry, cs);
                     }
-                } else if (lp == t - 1) {
-                    if (act) v = carry[j];
+                    if (wave == SW_WAVES - 1) {
+                        if (valid && lp < nl) col[int64_t(lp) * N] = v;
+                    } else {
+                        slots[wave + 1][c & 1][i][lane] = v;
+                    }
                 }
             }
-            if (valid) col[int64_t(lp) * N] = v;
+            __syncthreads();
         }
+        __threadfence_block();
+        __syncthreads();
     }
 }
 
+// backward (synthesis) sweeps of one wave over one position lp;
+// sweeps t = tb + SW - 1 down to tb
+template <class T, bool MASK>
+__device__ __forceinline__ T bwd_position(T v, int lp, int tb, int tg, int kk, T (&carry)[SW], ConstPtr<T> cs) {
+#pragma unroll
+    for (int jj = 0; jj < SW; ++jj) {
+        const int j = SW - 1 - jj;
+        const int t = tb + j;
+        if (t > tg) continue;
+        const bool act = MASK ? (t <= kk) : true;
+        if (lp >= t) {
+            const T c = cs[2 * j], s = cs[2 * j + 1];
+            const T nv = s * v + c * carry[j];
+            const T nc = c * v - s * carry[j];
+            if (MASK) {
+                if (act) {
+                    v = nv;
+                    carry[j] = nc;
+                }
+            } else {
+                v = nv;
+                carry[j] = nc;
+            }
+        } else if (lp == t - 1) {
+            if (act) v = carry[j];
+        }
+    }
+    return v;
+}
+
 template <class T>
-static int sweep_waves(const GroupDims& g) {
+__global__ __launch_bounds__(64 * SW_WAVES) void k_sweep_bwd(Blocks4<T> U, Blocks4<const T> G, GroupDims g) {
+    __shared__ T slots[SW_WAVES][2][SW_CHUNK][64];
+    int blk, grp, map;
+    sweep_locate(g, blk, grp, map);
+    const int kpar = blk >> 1;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
+    const int lane = threadIdx.x & 63;
+    const int kk = grp * kSweepCols + (lane >> 1);
+    const int nk = g.nk[blk], nl = g.nl[blk], tpad = g.tpad[blk];
+    const int64_t N = g.N[kpar];
+    const bool valid = kk < nk;
+    const int kcol = valid ? kk : nk - 1;
+    T* col = U.p[blk] + int64_t(map) * g.Npm[kpar] + 2 * kcol + (lane & 1);
+    const T* __restrict__ Gt = G.p[blk];
+    const int tg = min(grp * kSweepCols + kSweepCols - 1, nk - 1);
+    const int kmin = grp * kSweepCols;
+    const int qtop = (tg - 1) / SW;                     // highest aligned block of sweeps
+    for (int q0 = qtop; q0 >= 0; q0 -= SW_WAVES) {
+        const int q = q0 - wave;                        // this wave's block
+        const bool busy = q >= 0;
+        const int tb = q * SW + 1;
+        const bool mask = busy && (tb + SW - 1 > kmin);
+        T carry[SW];
+#pragma unroll
+        for (int j = 0; j < SW; ++j) carry[j] = T(0);
+        const int qlow = max(q0 - SW_WAVES + 1, 0);
+        const int lo = qlow * SW;                       // lowest position touched: t_min - 1
+        const int npos = nl - lo;
+        const int nchunks = (npos + SW_CHUNK - 1) / SW_CHUNK;
+        for (int s = 0; s < nchunks + SW_WAVES - 1; ++s) {
+            const int c = s - wave;
+            if (c >= 0 && c < nchunks) {
+#pragma unroll
+                for (int i = 0; i < SW_CHUNK; ++i) {
+                    const int lp = nl - 1 - (c * SW_CHUNK + i);
+                    T v;
+                    if (wave == 0) v = (lp >= lo) ? col[int64_t(lp) * N] : T(0);
+                    else v = slots[wave][c & 1][i][lane];
+                    if (busy && lp >= lo) {
+                        ConstPtr<T> cs = as_const(Gt + (int64_t(lp) * tpad + (tb - 1)) * 2);
+                        v = mask ? bwd_position<T, true>(v, lp, tb, tg, kk, carry, cs)
+                                 : bwd_position<T, false>(v, lp, tb, tg, kk, carry, cs);
+                    }
+                    if (wave == SW_WAVES - 1) {
+                        if (valid && lp >= lo) col[int64_t(lp) * N] = v;
+                    } else {
+                        slots[wave + 1][c & 1][i][lane] = v;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        __threadfence_block();
+        __syncthreads();
+    }
+}
+
+static int sweep_workgroups(const GroupDims& g) {
     int w = 0;
     for (int b = 0; b < 4; ++b) w += (g.nk[b] + kSweepCols - 1) / kSweepCols;
     return w * g.nmaps;
@@ -493,13 +610,13 @@ static int sweep_waves(const GroupDims& g) {
 
 template <class T>
 hipError_t launch_sweep_fwd(Blocks4<T> U, Blocks4<const T> G, const GroupDims& g, hipStream_t s) {
-    hipLaunchKernelGGL(k_sweep_fwd<T>, dim3(sweep_waves<T>(g)), dim3(64), 0, s, U, G, g);
+    hipLaunchKernelGGL(k_sweep_fwd<T>, dim3(sweep_workgroups(g)), dim3(64 * SW_WAVES), 0, s, U, G, g);
     return hipGetLastError();
 }
 
 template <class T>
 hipError_t launch_sweep_bwd(Blocks4<T> U, Blocks4<const T> G, const GroupDims& g, hipStream_t s) {
-    hipLaunchKernelGGL(k_sweep_bwd<T>, dim3(sweep_waves<T>(g)), dim3(64), 0, s, U, G, g);
+    hipLaunchKernelGGL(k_sweep_bwd<T>, dim3(sweep_workgroups(g)), dim3(64 * SW_WAVES), 0, s, U, G, g);
     return hipGetLastError();
 }
 

@@ -111,3 +111,32 @@ def test_f64_analysis_nside256_L512():
     ref = O.analyze(f, 256, 512)
     print(f"nside 256: rel err {rel_err(a, ref):.3e}")
     assert rel_err(a, ref) < TOL64
+
+
+@pytest.mark.parametrize("nside", [8, 32, 64])
+def test_f32_refine_vs_refined_oracle(nside):
+    """FP32 stages + one FP64-residual round against the same recipe in FP64."""
+    f, _ = cmb_map(1, nside, nside)
+    plan = P.Plan(nside, mode="f32_refine")
+    a = plan.analyze(_dev(f))
+    cl = plan.power_spectrum(a)
+    torch.cuda.synchronize()
+    a, cl = a.cpu().numpy(), cl.cpu().numpy()
+    ref = O.analyze_refined(f, nside)
+    plain = O.analyze(f, nside)
+    clr = O.power_spectrum(ref, 2 * nside)
+    e_ref = rel_err(a, ref)
+    e_plain = rel_err(a, plain)
+    e_cl = float(np.max(np.abs(cl[2:] - clr[2:]) / clr[2:]))
+    print(f"nside {nside}: vs O_ref {e_ref:.3e}, vs O_plain {e_plain:.3e}, rel C_l {e_cl:.3e}")
+    assert e_ref < 1e-5
+
+
+@pytest.mark.parametrize("nside", [16, 64])
+def test_f32_single_pass_vs_oracle(nside):
+    f, _ = cmb_map(1, 100 + nside, nside)
+    plan = P.Plan(nside, mode="f32")
+    a = plan.analyze(_dev(f)).cpu().numpy()
+    e = rel_err(a, O.analyze(f, nside))
+    print(f"nside {nside}: f32 single pass rel err {e:.3e}")
+    assert e < 1e-5
