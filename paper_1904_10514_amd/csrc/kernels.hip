@@ -379,31 +379,34 @@ hipError_t launch_gemm(GemmBatch<T> gb, hipStream_t s) {
 // that order for analysis (each sweep: a carry runs up the chain l' = t-1 ..
 // nl-1, rotating (carry, x[l']) and dropping the final carry), and t = k' ..
 // 1 with the transposed rotations for synthesis (a zero carry runs down the
-// chain and is deposited at l' = t-1).  The angles depend on (t, l') only.
+// chain and is deposited at l' = t-1).  The angles depend on (t, l') only,
+// so they are the same for every map and every column that needs sweep t.
 //
 // One workgroup = SW_WAVES waves on the same 32 columns k' (lane = (k',
-// re/im)) of one map and block.  Sweeps are grouped in aligned blocks of
-// SW = 8 (t = 8q+1 .. 8q+8); in one pass wave w applies block q0 + w, so a
-// pass applies SW * SW_WAVES sweeps.  Chain values stream through the waves
-// in chunks of SW_CHUNK positions: wave 0 reads from global memory, hands
-// each chunk to wave 1 through LDS, .., the last wave writes back; at step s
-// wave w works on chunk s - w, with a barrier per step.  The carries of a
-// wave's SW sweeps stay in registers for the whole pass; the angles are the
-// same for every lane and come through the scalar cache.  Columns that need
-// fewer sweeps than their neighbours are masked per lane only in the wave
-// blocks that contain their last sweep.
+// re/im)) of MB maps of one block; each lane carries its column for all MB
+// maps, so every angle pair read serves MB rotations per lane.  Sweeps are
+// grouped in aligned blocks of SW (t = SW q + 1 .. SW q + SW); in one pass
+// wave w applies block q0 + w, so a pass applies SW * SW_WAVES sweeps and
+// streams the chains through HBM once.  Chain values move through the waves
+// in chunks of SW_CHUNK positions: wave 0 reads from global memory (one
+// chunk ahead), hands each chunk to wave 1 through LDS, .., the last wave
+// writes back; at step s wave w works on chunk s - w, with a barrier per
+// step.  The carries of a wave's sweeps stay in registers for the pass; the
+// angles come through the scalar cache.  Columns that need fewer sweeps than
+// their neighbours are masked per lane only in the wave blocks that contain
+// their last sweep.
 // ---------------------------------------------------------------------------
 
 constexpr int SW = 8;
-constexpr int SW_WAVES = 16;
-constexpr int SW_CHUNK = 4;
+constexpr int SW_WAVES = 8;
+constexpr int SW_CHUNK = 2;
 constexpr int kSweepCols = 32;
 
-__device__ __forceinline__ void sweep_locate(const GroupDims& g, int& blk, int& grp, int& map) {
+__device__ __forceinline__ void sweep_locate(const GroupDims& g, int nmg, int& blk, int& grp, int& mg) {
     // work items ordered longest first: highest column groups of all blocks first
     int w = blockIdx.x;
-    map = w % g.nmaps;
-    w /= g.nmaps;
+    mg = w % nmg;
+    w /= nmg;
     int ng[4], gmax = 0;
     for (int b = 0; b < 4; ++b) {
         ng[b] = (g.nk[b] + kSweepCols - 1) / kSweepCols;
@@ -435,89 +438,48 @@ __device__ __forceinline__ ConstPtr<T> as_const(const T* p) {
     return (ConstPtr<T>)(p);
 }
 
-// forward sweeps of one wave over one position lp
-template <class T, bool MASK>
-__device__ __forceinline__ T fwd_position(T v, int lp, int tb, int tg, int kk, T (&carry)[SW], ConstPtr<T> cs) {
-    T vf = v;
+// forward sweeps tb .. tb+SW-1 of one wave at position lp, for MB maps.
+// Sweep t rotates at positions lp >= t and takes its carry at lp = t - 1, so
+// at a given lp the wave applies the first nrot sweeps and then (if it is
+// one of its own) starts the carry of sweep lp + 1.
+template <class T, int MB, bool MASK>
+__device__ __forceinline__ void fwd_position(T (&v)[MB], int lp, int tb, int tg, int kk, T (&carry)[SW][MB],
+                                             ConstPtr<T> cs) {
+    const int nrot = max(0, min(min(lp - tb + 1, tg - tb + 1), SW));   // wave-uniform
+    const int jinit = (lp - tb + 1 < SW && lp + 1 <= tg) ? lp - tb + 1 : -1;
+    T vf[MB];
+#pragma unroll
+    for (int b = 0; b < MB; ++b) vf[b] = v[b];
 #pragma unroll
     for (int j = 0; j < SW; ++j) {
-        const int t = tb + j;
-        if (t > tg || lp < t - 1) break;
-        if (lp == t - 1) {
-            carry[j] = v;
-            break;
-        }
-        const T c = cs[2 * j], s = cs[2 * j + 1];
-        const T nv = c * carry[j] + s * v;
-        carry[j] = c * v - s * carry[j];
-        v = nv;
-        if (MASK) {
-            if (t <= kk) vf = v;
-        } else {
-            vf = v;
-        }
-    }
-    return vf;
-}
-
-template <class T>
-__global__ __launch_bounds__(64 * SW_WAVES) void k_sweep_fwd(Blocks4<T> U, Blocks4<const T> G, GroupDims g) {
-    __shared__ T slots[SW_WAVES][2][SW_CHUNK][64];
-    int blk, grp, map;
-    sweep_locate(g, blk, grp, map);
-    const int kpar = blk >> 1;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
-    const int lane = threadIdx.x & 63;
-    const int kk = grp * kSweepCols + (lane >> 1);
-    const int nk = g.nk[blk], nl = g.nl[blk], tpad = g.tpad[blk];
-    const int64_t N = g.N[kpar];
-    const bool valid = kk < nk;
-    const int kcol = valid ? kk : nk - 1;
-    T* col = U.p[blk] + int64_t(map) * g.Npm[kpar] + 2 * kcol + (lane & 1);
-    const T* __restrict__ Gt = G.p[blk];
-    const int tg = min(grp * kSweepCols + kSweepCols - 1, nk - 1);
-    const int kmin = grp * kSweepCols;
-    for (int t0 = 1; t0 <= tg; t0 += SW * SW_WAVES) {
-        const int tb = t0 + wave * SW;                 // first sweep of this wave
-        const bool busy = tb <= tg;
-        const bool mask = busy && (tb + SW - 1 > kmin);
-        T carry[SW];
+        if (j < nrot) {
+            const int t = tb + j;
+            const T c = cs[2 * j], s = cs[2 * j + 1];
 #pragma unroll
-        for (int j = 0; j < SW; ++j) carry[j] = T(0);
-        const int lp0 = t0 - 1;
-        const int nchunks = (nl - lp0 + SW_CHUNK - 1) / SW_CHUNK;
-        for (int s = 0; s < nchunks + SW_WAVES - 1; ++s) {
-            const int c = s - wave;
-            if (c >= 0 && c < nchunks) {
-#pragma unroll
-                for (int i = 0; i < SW_CHUNK; ++i) {
-                    const int lp = lp0 + c * SW_CHUNK + i;
-                    T v;
-                    if (wave == 0) v = (lp < nl) ? col[int64_t(lp) * N] : T(0);
-                    else v = slots[wave][c & 1][i][lane];
-                    if (busy && lp < nl) {
-                        ConstPtr<T> cs = as_const(Gt + (int64_t(lp) * tpad + (tb - 1)) * 2);
-                        v = mask ? fwd_position<T, true>(v, lp, tb, tg, kk, carry, cs)
-                                 : fwd_position<T, false>(v, lp, tb, tg, kk, carry, cs);
-                    }
-                    if (wave == SW_WAVES - 1) {
-                        if (valid && lp < nl) col[int64_t(lp) * N] = v;
-                    } else {
-                        slots[wave + 1][c & 1][i][lane] = v;
-                    }
+            for (int b = 0; b < MB; ++b) {
+                // explicit fma order: every instantiation rounds identically
+                const T nv = fma(c, carry[j][b], s * v[b]);
+                carry[j][b] = fma(c, v[b], -(s * carry[j][b]));
+                v[b] = nv;
+                if (MASK) {
+                    if (t <= kk) vf[b] = v[b];
+                } else {
+                    vf[b] = v[b];
                 }
             }
-            __syncthreads();
+        } else if (j == jinit) {
+#pragma unroll
+            for (int b = 0; b < MB; ++b) carry[j][b] = v[b];
         }
-        __threadfence_block();
-        __syncthreads();
     }
+#pragma unroll
+    for (int b = 0; b < MB; ++b) v[b] = vf[b];
 }
 
-// backward (synthesis) sweeps of one wave over one position lp;
-// sweeps t = tb + SW - 1 down to tb
-template <class T, bool MASK>
-__device__ __forceinline__ T bwd_position(T v, int lp, int tb, int tg, int kk, T (&carry)[SW], ConstPtr<T> cs) {
+// backward (synthesis) sweeps tb+SW-1 down to tb at position lp, for MB maps
+template <class T, int MB, bool MASK>
+__device__ __forceinline__ void bwd_position(T (&v)[MB], int lp, int tb, int tg, int kk, T (&carry)[SW][MB],
+                                             ConstPtr<T> cs) {
 #pragma unroll
     for (int jj = 0; jj < SW; ++jj) {
         const int j = SW - 1 - jj;
@@ -526,72 +488,131 @@ __device__ __forceinline__ T bwd_position(T v, int lp, int tb, int tg, int kk, T
         const bool act = MASK ? (t <= kk) : true;
         if (lp >= t) {
             const T c = cs[2 * j], s = cs[2 * j + 1];
-            const T nv = s * v + c * carry[j];
-            const T nc = c * v - s * carry[j];
-            if (MASK) {
+#pragma unroll
+            for (int b = 0; b < MB; ++b) {
+                const T nv = fma(s, v[b], c * carry[j][b]);
+                const T nc = fma(c, v[b], -(s * carry[j][b]));
                 if (act) {
-                    v = nv;
-                    carry[j] = nc;
+                    v[b] = nv;
+                    carry[j][b] = nc;
                 }
-            } else {
-                v = nv;
-                carry[j] = nc;
             }
         } else if (lp == t - 1) {
-            if (act) v = carry[j];
+            if (act) {
+#pragma unroll
+                for (int b = 0; b < MB; ++b) v[b] = carry[j][b];
+            }
         }
     }
-    return v;
 }
 
-template <class T>
-__global__ __launch_bounds__(64 * SW_WAVES) void k_sweep_bwd(Blocks4<T> U, Blocks4<const T> G, GroupDims g) {
-    __shared__ T slots[SW_WAVES][2][SW_CHUNK][64];
-    int blk, grp, map;
-    sweep_locate(g, blk, grp, map);
+template <class T, int MB, bool FWD>
+__global__ __launch_bounds__(64 * SW_WAVES) void k_sweep(Blocks4<T> U, Blocks4<const T> G, GroupDims g) {
+    __shared__ T slots[SW_WAVES][2][SW_CHUNK][MB][64];
+    const int nmg = (g.nmaps + MB - 1) / MB;
+    int blk, grp, mg;
+    sweep_locate(g, nmg, blk, grp, mg);
     const int kpar = blk >> 1;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
     const int lane = threadIdx.x & 63;
     const int kk = grp * kSweepCols + (lane >> 1);
     const int nk = g.nk[blk], nl = g.nl[blk], tpad = g.tpad[blk];
     const int64_t N = g.N[kpar];
-    const bool valid = kk < nk;
-    const int kcol = valid ? kk : nk - 1;
-    T* col = U.p[blk] + int64_t(map) * g.Npm[kpar] + 2 * kcol + (lane & 1);
-    const T* __restrict__ Gt = G.p[blk];
+    const bool kvalid = kk < nk;
+    const int kcol = kvalid ? kk : nk - 1;
+    T* col[MB];
+    bool ok[MB];
+#pragma unroll
+    for (int b = 0; b < MB; ++b) {
+        const int map = mg * MB + b;
+        ok[b] = kvalid && map < g.nmaps;
+        col[b] = U.p[blk] + int64_t(map < g.nmaps ? map : 0) * g.Npm[kpar] + 2 * kcol + (lane & 1);
+    }
+    const T* Gt = G.p[blk];
     const int tg = min(grp * kSweepCols + kSweepCols - 1, nk - 1);
     const int kmin = grp * kSweepCols;
-    const int qtop = (tg - 1) / SW;                     // highest aligned block of sweeps
-    for (int q0 = qtop; q0 >= 0; q0 -= SW_WAVES) {
-        const int q = q0 - wave;                        // this wave's block
-        const bool busy = q >= 0;
+    const int qtop = (tg - 1) / SW;
+    const int npass = qtop / SW_WAVES + 1;
+    for (int pass = 0; pass < npass; ++pass) {
+        // sweep block of this wave and the chain range of the pass
+        int q, lo;
+        if (FWD) {
+            q = pass * SW_WAVES + wave;
+            lo = pass * SW_WAVES * SW;                  // first position: t0 - 1
+        } else {
+            const int q0 = qtop - pass * SW_WAVES;
+            q = q0 - wave;
+            lo = max(q0 - SW_WAVES + 1, 0) * SW;        // lowest deposit position
+        }
         const int tb = q * SW + 1;
+        const bool busy = FWD ? (tb <= tg) : (q >= 0);
         const bool mask = busy && (tb + SW - 1 > kmin);
-        T carry[SW];
+        T carry[SW][MB];
 #pragma unroll
-        for (int j = 0; j < SW; ++j) carry[j] = T(0);
-        const int qlow = max(q0 - SW_WAVES + 1, 0);
-        const int lo = qlow * SW;                       // lowest position touched: t_min - 1
+        for (int j = 0; j < SW; ++j)
+#pragma unroll
+            for (int b = 0; b < MB; ++b) carry[j][b] = T(0);
         const int npos = nl - lo;
         const int nchunks = (npos + SW_CHUNK - 1) / SW_CHUNK;
+        // position of chunk element (c, i)
+        auto posof = [&](int c, int i) { return FWD ? lo + c * SW_CHUNK + i : nl - 1 - (c * SW_CHUNK + i); };
+        T nx[SW_CHUNK][MB];
+        if (wave == 0) {
+#pragma unroll
+            for (int i = 0; i < SW_CHUNK; ++i) {
+                const int lp = posof(0, i);
+                const bool in = FWD ? (lp < nl) : (lp >= lo);
+#pragma unroll
+                for (int b = 0; b < MB; ++b) nx[i][b] = in ? col[b][int64_t(lp) * N] : T(0);
+            }
+        }
         for (int s = 0; s < nchunks + SW_WAVES - 1; ++s) {
             const int c = s - wave;
             if (c >= 0 && c < nchunks) {
+                T v[SW_CHUNK][MB];
+                if (wave == 0) {
+#pragma unroll
+                    for (int i = 0; i < SW_CHUNK; ++i)
+#pragma unroll
+                        for (int b = 0; b < MB; ++b) v[i][b] = nx[i][b];
+                    if (c + 1 < nchunks) {
+#pragma unroll
+                        for (int i = 0; i < SW_CHUNK; ++i) {
+                            const int lp = posof(c + 1, i);
+                            const bool in = FWD ? (lp < nl) : (lp >= lo);
+#pragma unroll
+                            for (int b = 0; b < MB; ++b) nx[i][b] = in ? col[b][int64_t(lp) * N] : T(0);
+                        }
+                    }
+                } else {
+#pragma unroll
+                    for (int i = 0; i < SW_CHUNK; ++i)
+#pragma unroll
+                        for (int b = 0; b < MB; ++b) v[i][b] = slots[wave][c & 1][i][b][lane];
+                }
 #pragma unroll
                 for (int i = 0; i < SW_CHUNK; ++i) {
-                    const int lp = nl - 1 - (c * SW_CHUNK + i);
-                    T v;
-                    if (wave == 0) v = (lp >= lo) ? col[int64_t(lp) * N] : T(0);
-                    else v = slots[wave][c & 1][i][lane];
-                    if (busy && lp >= lo) {
+                    const int lp = posof(c, i);
+                    const bool in = FWD ? (lp < nl) : (lp >= lo);
+                    if (busy && in) {
                         ConstPtr<T> cs = as_const(Gt + (int64_t(lp) * tpad + (tb - 1)) * 2);
-                        v = mask ? bwd_position<T, true>(v, lp, tb, tg, kk, carry, cs)
-                                 : bwd_position<T, false>(v, lp, tb, tg, kk, carry, cs);
+                        if (FWD) {
+                            if (mask) fwd_position<T, MB, true>(v[i], lp, tb, tg, kk, carry, cs);
+                            else fwd_position<T, MB, false>(v[i], lp, tb, tg, kk, carry, cs);
+                        } else {
+                            if (mask) bwd_position<T, MB, true>(v[i], lp, tb, tg, kk, carry, cs);
+                            else bwd_position<T, MB, false>(v[i], lp, tb, tg, kk, carry, cs);
+                        }
                     }
                     if (wave == SW_WAVES - 1) {
-                        if (valid && lp >= lo) col[int64_t(lp) * N] = v;
+                        if (in) {
+#pragma unroll
+                            for (int b = 0; b < MB; ++b)
+                                if (ok[b]) col[b][int64_t(lp) * N] = v[i][b];
+                        }
                     } else {
-                        slots[wave + 1][c & 1][i][lane] = v;
+#pragma unroll
+                        for (int b = 0; b < MB; ++b) slots[wave + 1][c & 1][i][b][lane] = v[i][b];
                     }
                 }
             }
@@ -602,22 +623,36 @@ __global__ __launch_bounds__(64 * SW_WAVES) void k_sweep_bwd(Blocks4<T> U, Block
     }
 }
 
-static int sweep_workgroups(const GroupDims& g) {
+static int sweep_workgroups(const GroupDims& g, int mb) {
     int w = 0;
     for (int b = 0; b < 4; ++b) w += (g.nk[b] + kSweepCols - 1) / kSweepCols;
-    return w * g.nmaps;
+    return w * ((g.nmaps + mb - 1) / mb);
+}
+
+#ifndef HP2SPH_SWEEP_MB_MAX
+#define HP2SPH_SWEEP_MB_MAX 2   // maps carried per lane by the sweep kernels (1, 2 or 4)
+#endif
+
+template <class T, bool FWD>
+static hipError_t launch_sweep(Blocks4<T> U, Blocks4<const T> G, const GroupDims& g, hipStream_t s) {
+    if (HP2SPH_SWEEP_MB_MAX >= 4 && g.nmaps >= 4) {
+        hipLaunchKernelGGL((k_sweep<T, 4, FWD>), dim3(sweep_workgroups(g, 4)), dim3(64 * SW_WAVES), 0, s, U, G, g);
+    } else if (HP2SPH_SWEEP_MB_MAX >= 2 && g.nmaps >= 2) {
+        hipLaunchKernelGGL((k_sweep<T, 2, FWD>), dim3(sweep_workgroups(g, 2)), dim3(64 * SW_WAVES), 0, s, U, G, g);
+    } else {
+        hipLaunchKernelGGL((k_sweep<T, 1, FWD>), dim3(sweep_workgroups(g, 1)), dim3(64 * SW_WAVES), 0, s, U, G, g);
+    }
+    return hipGetLastError();
 }
 
 template <class T>
 hipError_t launch_sweep_fwd(Blocks4<T> U, Blocks4<const T> G, const GroupDims& g, hipStream_t s) {
-    hipLaunchKernelGGL(k_sweep_fwd<T>, dim3(sweep_workgroups(g)), dim3(64 * SW_WAVES), 0, s, U, G, g);
-    return hipGetLastError();
+    return launch_sweep<T, true>(U, G, g, s);
 }
 
 template <class T>
 hipError_t launch_sweep_bwd(Blocks4<T> U, Blocks4<const T> G, const GroupDims& g, hipStream_t s) {
-    hipLaunchKernelGGL(k_sweep_bwd<T>, dim3(sweep_workgroups(g)), dim3(64 * SW_WAVES), 0, s, U, G, g);
-    return hipGetLastError();
+    return launch_sweep<T, false>(U, G, g, s);
 }
 
 // ---------------------------------------------------------------------------
