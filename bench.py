@@ -103,8 +103,30 @@ def roofline(stage, mode, nside, nmaps, ms_total, launches):
         achieved = amount / avg_s / 1e12
         peak, unit = PEAK_TFLOPS[bound][dt], "TFLOP/s"
     return {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit, "frac": achieved / peak,
-            "traffic": None, "kernel": stage, "dtype": dt, "avg_launch_ms": avg_s * 1e3,
+            "traffic": measured_traffic(stage, dt, nside, nmaps), "kernel": stage, "dtype": dt,
+            "avg_launch_ms": avg_s * 1e3,
             "work_per_launch": amount, "work_unit": kind}
+
+
+def measured_traffic(stage, dtype, nside, nmaps):
+    """HBM bytes per launch from the committed counter runs (profiles/), scaled
+    by the copy-kernel calibration; None if the kernels changed since then or
+    the workload differs."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_nside1024_L2048_b64.json")
+    try:
+        with open(path) as fh:
+            js = json.load(fh)
+        src = os.path.join(ROOT, "paper_1904_10514_amd", "csrc", "kernels.hip")
+        with open(src, "rb") as fh:
+            if hashlib.sha256(fh.read()).hexdigest() != js["kernels_hip_sha256"]:
+                return None
+        if js["workload"] != {"nside": nside, "lmax": 2 * nside, "batch": nmaps}:
+            return None
+        e = js["stages"].get(f"{stage}/{dtype}")
+        return None if e is None else e["read_bytes"] + e["write_bytes"]
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def make_inputs(torch, P, W, nside, nmaps):
