@@ -95,6 +95,38 @@ enum {
 int hp2sph_plan_create(const int32_t* nside, const int32_t* lmax, int32_t batch,
                        int32_t mode, hp2sph_plan_t* out);
 
+/*
+ * Execution strategies for the colatitude fit and the conversion to
+ * spherical harmonics (Steps 2-3); both compute the same a_lm up to rounding.
+ *   HP2SPH_STRATEGY_STAGED  a dense GEMM per parity block (the fused
+ *       colatitude least squares + order-0/1 Legendre connection, shared by
+ *       all modes and maps) followed by the Givens sweeps of Slevinsky's
+ *       conversion for every order m in the hot path.
+ *   HP2SPH_STRATEGY_TABLES  the sweeps are applied once, at plan creation, to
+ *       the columns of that matrix, giving one dense matrix per (parity
+ *       block, order m) -- the "per-m precomputed tables"; the hot path is
+ *       then one grouped MFMA GEMM over all orders, which also skips the polar
+ *       rings that cannot carry mode m.  Costs O(nside^3) device memory
+ *       (~29 GB FP64 at nside 1024).
+ *   HP2SPH_STRATEGY_AUTO    tables when the group has >= 8 maps and its tables
+ *       fit in a quarter of device memory; staged otherwise.
+ */
+enum {
+    HP2SPH_STRATEGY_AUTO = 0,
+    HP2SPH_STRATEGY_STAGED = 1,
+    HP2SPH_STRATEGY_TABLES = 2
+};
+
+/* hp2sph_plan_create with an explicit strategy (see above).  Table
+ * construction runs on the GPU (Givens sweeps on the set-up matrices) and
+ * synchronises the device.  Errors: as hp2sph_plan_create, EINVAL for an
+ * unknown strategy, ENOMEM if the tables do not fit. */
+int hp2sph_plan_create_ex(const int32_t* nside, const int32_t* lmax, int32_t batch,
+                          int32_t mode, int32_t strategy, hp2sph_plan_t* out);
+
+/* Strategy in use: STAGED or TABLES if all nside groups use it, AUTO if mixed. */
+int hp2sph_plan_strategy(hp2sph_plan_t plan, int32_t* strategy);
+
 /* Device workspace (bytes) hp2sph_analyze / hp2sph_synthesize need. */
 int hp2sph_workspace_size(hp2sph_plan_t plan, size_t* bytes);
 

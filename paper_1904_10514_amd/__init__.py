@@ -40,8 +40,9 @@ MAX_NSIDE = 2048
 EXPORTED = [
     "hp2sph_plan_create", "hp2sph_workspace_size", "hp2sph_analyze", "hp2sph_synthesize",
     "hp2sph_power_spectrum", "hp2sph_plan_destroy", "hp2sph_last_error", "hp2sph_host_table",
-    "hp2sph_profile", "hp2sph_profile_read",
+    "hp2sph_profile", "hp2sph_profile_read", "hp2sph_plan_create_ex", "hp2sph_plan_strategy",
 ]
+STRATEGIES = {"auto": 0, "staged": 1, "tables": 2}
 NSTAGES = 10
 STAGES = ["ring_forward", "pole", "gemm_analysis", "sweep_analysis", "pack", "unpack",
           "sweep_synthesis", "gemm_synthesis", "ring_inverse_residual", "cl"]
@@ -55,6 +56,9 @@ _lib.hp2sph_synthesize.argtypes = [_vp, _vp, _vp, _vp, _vp]
 _lib.hp2sph_power_spectrum.argtypes = [_vp, _vp, _vp, _vp]
 _lib.hp2sph_plan_destroy.argtypes = [_vp]
 _lib.hp2sph_last_error.restype = ctypes.c_char_p
+_lib.hp2sph_plan_create_ex.argtypes = [ctypes.POINTER(_i32), ctypes.POINTER(_i32), _i32, _i32, _i32,
+                                        ctypes.POINTER(_vp)]
+_lib.hp2sph_plan_strategy.argtypes = [_vp, ctypes.POINTER(_i32)]
 _lib.hp2sph_profile.argtypes = [_vp, _i32]
 _lib.hp2sph_profile_read.argtypes = [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i32), _i32]
 _lib.hp2sph_host_table.argtypes = [_i32, _i32, _i32, _vp, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
@@ -108,7 +112,7 @@ def _torch():
 class Plan:
     """A plan for a batch of maps (uniform or uneven nside)."""
 
-    def __init__(self, nside, lmax=None, batch=None, mode="f64"):
+    def __init__(self, nside, lmax=None, batch=None, mode="f64", strategy="auto"):
         torch = _torch()
         if np.isscalar(nside):
             if batch is None:
@@ -128,8 +132,12 @@ class Plan:
         arr_n = (_i32 * batch)(*nside)
         arr_l = (_i32 * batch)(*lmax)
         h = _vp()
-        _check(_lib.hp2sph_plan_create(arr_n, arr_l, batch, self.mode, ctypes.byref(h)), "plan_create")
+        strat = STRATEGIES[strategy] if isinstance(strategy, str) else int(strategy)
+        _check(_lib.hp2sph_plan_create_ex(arr_n, arr_l, batch, self.mode, strat, ctypes.byref(h)), "plan_create")
         self._h = h
+        s = _i32(0)
+        _check(_lib.hp2sph_plan_strategy(self._h, ctypes.byref(s)), "plan_strategy")
+        self.strategy = {v: k for k, v in STRATEGIES.items()}[s.value]
         ws = ctypes.c_size_t(0)
         _check(_lib.hp2sph_workspace_size(self._h, ctypes.byref(ws)), "workspace_size")
         self.workspace_bytes = ws.value

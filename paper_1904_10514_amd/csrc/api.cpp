@@ -66,6 +66,12 @@ I* upload_int(std::vector<std::unique_ptr<DevBuf>>& owned, const std::vector<I>&
     return out;
 }
 
+template <class T>
+struct GemmList {
+    GemmProblem<T>* dev = nullptr;
+    int n = 0, tiles = 0;
+};
+
 struct Group {
     int nside = 0;
     std::vector<int> members;         // batch indices
@@ -85,7 +91,20 @@ struct Group {
     size_t off_D = 0, off_U = 0;
     size_t bytes_D = 0, bytes_U = 0;
     int64_t rows_D[4] = {}, rows_U[4] = {};
+    size_t blk_off_D[4] = {}, blk_off_U[4] = {};   // byte offset of each block in its region
+    // strategy: per-order tables (fused colatitude fit + Givens sweeps) or staged
+    bool tables = false;
+    // device GEMM problem lists
+    GemmList<double> ana64, syn64, syn64_staged;
+    GemmList<float> ana32;
 };
+
+template <class T>
+const GemmList<T>& gemm_list(const Group& G);
+template <>
+const GemmList<double>& gemm_list<double>(const Group& G) { return G.ana64; }
+template <>
+const GemmList<float>& gemm_list<float>(const Group& G) { return G.ana32; }
 
 }  // namespace
 }  // namespace hp2sph
@@ -151,6 +170,7 @@ struct hp2sph_plan_s {
     std::vector<std::unique_ptr<hp2sph::Group>> groups;
     size_t ws_bytes = 0;
     size_t off_R = 0;                 // residual map (refinement)
+    int strategy = 0;                 // requested HP2SPH_STRATEGY_*
     uint32_t magic = 0x48503253u;
 };
 
@@ -187,6 +207,16 @@ std::vector<double> pad_givens(const std::vector<double>& g, int nl, int T, int 
     return out;
 }
 
+// Column order of Dsym / U (see GroupDims): map-major for the staged
+// strategy, mode-major for the per-order tables.
+void set_layout(GroupDims& d, bool modemajor) {
+    d.modemajor = modemajor ? 1 : 0;
+    for (int kp = 0; kp < 2; ++kp) {
+        d.cm[kp] = modemajor ? 2 : d.Npm[kp];
+        d.ck[kp] = modemajor ? 2 * int64_t(d.nmaps) : 2;
+    }
+}
+
 void build_group(hp2sph_plan_t plan, Group& G) {
     HostTables h;
     build_tables(G.nside, h, true);
@@ -207,6 +237,7 @@ void build_group(hp2sph_plan_t plan, Group& G) {
     d.Npm[1] = 2 * d.nk[2];
     d.N[0] = int64_t(d.nmaps) * d.Npm[0];
     d.N[1] = int64_t(d.nmaps) * d.Npm[1];
+    set_layout(d, false);
     for (int i = 0; i < 3; ++i) G.pole_w[i] = h.pole_w[i];
 
     // rings
@@ -264,6 +295,8 @@ void build_group(hp2sph_plan_t plan, Group& G) {
         const int kpar = b >> 1;
         G.rows_D[b] = K;
         G.rows_U[b] = d.nl[b];
+        G.blk_off_D[b] = G.bytes_D;
+        G.blk_off_U[b] = G.bytes_U;
         G.bytes_D += align_up(size_t(K) * d.N[kpar] * sizeof(double));
         G.bytes_U += align_up(size_t(d.nl[b]) * d.N[kpar] * sizeof(double));
     }
@@ -286,6 +319,244 @@ Blocks4<const T> cblocks(Blocks4<T> b) {
     Blocks4<const T> o;
     for (int i = 0; i < 4; ++i) o.p[i] = b.p[i];
     return o;
+}
+
+// ---------------------------------------------------------------------------
+// GEMM problem lists and the per-order tables
+// ---------------------------------------------------------------------------
+
+// Smallest half-ring row that carries mode m in the analysis: polar ring j
+// holds modes |k| <= 2j only, so rows h < m/2 are zero for mode m (and the
+// pole row carries m = 0 only).
+int first_row(int m) { return m == 0 ? 0 : (m + 1) / 2; }
+
+template <class T>
+void upload_list(Group& G, std::vector<GemmProblem<T>>& v, GemmList<T>& out) {
+    // longest problems first, then tile ranges in that order
+    std::stable_sort(v.begin(), v.end(), [](const GemmProblem<T>& x, const GemmProblem<T>& y) {
+        return int64_t(x.M) * x.K > int64_t(y.M) * y.K;
+    });
+    out.tiles = finalize_gemm_problems<T>(v.data(), int(v.size()));
+    out.n = int(v.size());
+    out.dev = upload_int(G.owned, v);
+}
+
+template <class T>
+void staged_analysis_list(Group& G, const DevTables<T>& t, GemmList<T>& out) {
+    const GroupDims& d = G.dims;
+    std::vector<GemmProblem<T>> v;
+    for (int b = 0; b < 4; ++b) {
+        const int kpar = b >> 1;
+        GemmProblem<T> P{};
+        P.A = t.ana[b];
+        P.M = d.nl[b];
+        P.N = int(d.N[kpar]);
+        P.K = 2 * G.nside + 1;
+        P.lda = d.nl[b];
+        P.boff = int64_t(G.blk_off_D[b] / sizeof(T));
+        P.ldb = d.N[kpar];
+        P.bps = 2;
+        P.coff = int64_t(G.blk_off_U[b] / sizeof(T));
+        P.ldc = d.N[kpar];
+        P.cps = 2;
+        v.push_back(P);
+    }
+    upload_list(G, v, out);
+}
+
+void staged_synthesis_list(Group& G, GemmList<double>& out) {
+    const GroupDims& d = G.dims;
+    std::vector<GemmProblem<double>> v;
+    for (int b = 0; b < 4; ++b) {
+        const int kpar = b >> 1;
+        GemmProblem<double> P{};
+        P.A = G.syn[b];
+        P.M = 2 * G.nside + 1;
+        P.N = int(d.N[kpar]);
+        P.K = d.nl[b];
+        P.lda = 2 * G.nside + 1;
+        P.boff = int64_t(G.blk_off_U[b] / sizeof(double));
+        P.ldb = d.N[kpar];
+        P.bps = 2;
+        P.coff = int64_t(G.blk_off_D[b] / sizeof(double));
+        P.ldc = d.N[kpar];
+        P.cps = 2;
+        v.push_back(P);
+    }
+    upload_list(G, v, out);
+}
+
+// Element offsets and sizes of the per-order tables of one block.
+struct OrderLayout {
+    std::vector<int64_t> ana_off, syn_off;
+    std::vector<int32_t> h0;
+    int64_t ana_size = 0, syn_size = 0;
+};
+
+OrderLayout order_layout(const Group& G, int b) {
+    const GroupDims& d = G.dims;
+    const int kpar = b >> 1, K = 2 * G.nside + 1;
+    OrderLayout L;
+    for (int kk = 0; kk < d.nk[b]; ++kk) {
+        const int h0 = first_row(2 * kk + kpar);
+        L.h0.push_back(h0);
+        L.ana_off.push_back(L.ana_size);
+        L.ana_size += int64_t(K - h0) * (d.nl[b] - kk);
+        L.syn_off.push_back(L.syn_size);
+        L.syn_size += int64_t(d.nl[b] - kk) * (2 * G.nside);
+    }
+    return L;
+}
+
+size_t order_table_bytes(const Group& G, int mode) {
+    size_t ana = 0, syn = 0;
+    for (int b = 0; b < 4; ++b) {
+        OrderLayout L = order_layout(G, b);
+        ana += size_t(L.ana_size);
+        syn += size_t(L.syn_size);
+    }
+    if (mode == HP2SPH_F64) return ana * 8;
+    if (mode == HP2SPH_F32) return ana * 4;
+    return ana * 4 + syn * 8;
+}
+
+#define HIPTHROW(expr)                                                                        \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess) throw std::runtime_error(std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+// Build the per-order tables on the GPU: for every block and mode k', the
+// analysis matrix is the analysis sweeps of column k' applied to every
+// half-ring column of the fused colatitude-fit matrix; the synthesis matrix
+// is the same sweeps applied to every ring row of the evaluation matrix
+// (the transpose of the synthesis sweeps).  Runs once per plan.
+void build_order_tables(hp2sph_plan_t plan, Group& G) {
+    const GroupDims& d = G.dims;
+    const int K = 2 * G.nside + 1;
+    const bool want_syn = (plan->mode == HP2SPH_F32_REFINE);
+    std::vector<GemmProblem<double>> la64, ls64;
+    std::vector<GemmProblem<float>> la32;
+    // temporary buffer for the virtual batch (chains replicated over k')
+    size_t per_v = 0;
+    for (int b = 0; b < 4; ++b) per_v = std::max(per_v, size_t(d.nl[b]) * 2 * d.nk[b] * sizeof(double));
+    const int nv_max = int(std::max<size_t>(1, std::min<size_t>((K + 1) / 2, (size_t(1) << 31) / per_v)));
+    DevBuf tmp;
+    tmp.bytes = per_v * nv_max;
+    HIPTHROW(hipMalloc(&tmp.p, tmp.bytes));
+    double* Uv = static_cast<double*>(tmp.p);
+    for (int b = 0; b < 4; ++b) {
+        const int kpar = b >> 1;
+        OrderLayout L = order_layout(G, b);
+        auto ana64 = std::make_unique<DevBuf>();
+        ana64->bytes = size_t(L.ana_size) * 8;
+        HIPTHROW(hipMalloc(&ana64->p, ana64->bytes));
+        std::unique_ptr<DevBuf> syn64;
+        if (want_syn) {
+            syn64 = std::make_unique<DevBuf>();
+            syn64->bytes = size_t(L.syn_size) * 8;
+            HIPTHROW(hipMalloc(&syn64->p, syn64->bytes));
+        }
+        std::vector<std::unique_ptr<DevBuf>> scratch;
+        const int64_t* d_ana_off = upload_int(scratch, L.ana_off);
+        const int64_t* d_syn_off = upload_int(scratch, L.syn_off);
+        const int32_t* d_h0 = upload_int(scratch, L.h0);
+        // dims of the virtual batch: only block b is swept
+        GroupDims gv = d;
+        for (int o = 0; o < 4; ++o)
+            if (o != b) gv.nk[o] = 0;
+        gv.nmaps = nv_max;
+        gv.Npm[kpar] = 2 * d.nk[b];
+        gv.N[kpar] = int64_t(nv_max) * gv.Npm[kpar];
+        set_layout(gv, false);
+        Blocks4<double> Ub{};
+        Ub.p[b] = Uv;
+        Blocks4<const double> Gv{};
+        Gv.p[b] = G.t64.givens[b];
+        for (int pass = 0; pass < (want_syn ? 2 : 1); ++pass) {
+            const bool syn = (pass == 1);
+            const int h_lo = syn ? 1 : 0, h_hi = K - 1;
+            for (int hf = h_lo; hf <= h_hi; hf += 2 * nv_max) {
+                if (syn) {
+                    HIPTHROW(launch_replicate<double>(G.syn[b], 1, K, d.nl[b], hf, h_hi, Uv, d.nk[b], nv_max, nullptr));
+                } else {
+                    HIPTHROW(launch_replicate<double>(G.t64.ana[b], d.nl[b], 1, d.nl[b], hf, h_hi, Uv, d.nk[b],
+                                                      nv_max, nullptr));
+                }
+                HIPTHROW(launch_sweep_fwd<double>(Ub, Gv, gv, nullptr));
+                HIPTHROW(launch_scatter_tables<double>(Uv, d.nl[b], d.nk[b], nv_max, hf, h_hi, syn ? d_syn_off : d_ana_off,
+                                                       d_h0, 2 * G.nside, syn,
+                                                       static_cast<double*>(syn ? syn64->p : ana64->p), nullptr));
+            }
+        }
+        HIPTHROW(hipDeviceSynchronize());
+        // problem lists of this block
+        const double* tana64 = static_cast<const double*>(ana64->p);
+        float* tana32 = nullptr;
+        if (plan->mode != HP2SPH_F64) {
+            auto a32 = std::make_unique<DevBuf>();
+            a32->bytes = size_t(L.ana_size) * 4;
+            HIPTHROW(hipMalloc(&a32->p, a32->bytes));
+            HIPTHROW(launch_convert(tana64, static_cast<float*>(a32->p), L.ana_size, nullptr));
+            HIPTHROW(hipDeviceSynchronize());
+            tana32 = static_cast<float*>(a32->p);
+            G.owned.push_back(std::move(a32));
+        }
+        for (int kk = 0; kk < d.nk[b]; ++kk) {
+            const int h0 = L.h0[kk];
+            GemmProblem<double> P{};
+            P.M = d.nl[b] - kk;
+            P.K = K - h0;
+            P.N = 2 * d.nmaps;
+            // mode-major layout: mode k' of every map is one contiguous run of 2 nmaps
+            const int64_t kcol = int64_t(kk) * 2 * d.nmaps;
+            P.lda = P.M;
+            P.ldb = d.N[kpar];
+            P.bps = 2;
+            P.ldc = d.N[kpar];
+            P.cps = 2;
+            if (plan->mode == HP2SPH_F64) {
+                P.A = tana64 + L.ana_off[kk];
+                P.boff = int64_t(G.blk_off_D[b] / 8) + int64_t(h0) * d.N[kpar] + kcol;
+                P.coff = int64_t(G.blk_off_U[b] / 8) + int64_t(kk) * d.N[kpar] + kcol;
+                la64.push_back(P);
+            } else {
+                GemmProblem<float> Q{};
+                Q.A = tana32 + L.ana_off[kk];
+                Q.M = P.M;
+                Q.K = P.K;
+                Q.N = P.N;
+                Q.lda = P.lda;
+                Q.ldb = P.ldb;
+                Q.bps = P.bps;
+                Q.ldc = P.ldc;
+                Q.cps = P.cps;
+                Q.boff = int64_t(G.blk_off_D[b] / 4) + int64_t(h0) * d.N[kpar] + kcol;
+                Q.coff = int64_t(G.blk_off_U[b] / 4) + int64_t(kk) * d.N[kpar] + kcol;
+                la32.push_back(Q);
+            }
+            if (want_syn) {
+                GemmProblem<double> S{};
+                S.A = static_cast<const double*>(syn64->p) + L.syn_off[kk];
+                S.M = 2 * G.nside;
+                S.K = d.nl[b] - kk;
+                S.N = 2 * d.nmaps;
+                S.lda = 2 * G.nside;
+                S.boff = int64_t(G.blk_off_U[b] / 8) + int64_t(kk) * d.N[kpar] + kcol;
+                S.ldb = d.N[kpar];
+                S.bps = 2;
+                S.coff = int64_t(G.blk_off_D[b] / 8) + int64_t(1) * d.N[kpar] + kcol;
+                S.ldc = d.N[kpar];
+                S.cps = 2;
+                ls64.push_back(S);
+            }
+        }
+        if (plan->mode == HP2SPH_F64) G.owned.push_back(std::move(ana64));
+        if (want_syn) G.owned.push_back(std::move(syn64));
+    }
+    if (plan->mode == HP2SPH_F64) upload_list(G, la64, G.ana64);
+    else upload_list(G, la32, G.ana32);
+    if (want_syn) upload_list(G, ls64, G.syn64);
 }
 
 // Launch `expr` as stage `st`, bracketed by events when profiling is on.
@@ -326,25 +597,11 @@ int analysis_pass(Group& G, const double* maps_in, double* alm, void* ws, bool a
     Blocks4<T> U = blocks_at<T>(ws, G.off_U, G, G.rows_U);
     STAGE(0, launch_ring_forward<T>(maps_in, G.d_map_off, G.rings, t.fft, D, G.dims, s));
     STAGE(1, launch_pole<T>(D, G.dims, G.pole_w[0], G.pole_w[1], G.pole_w[2], s));
-    GemmBatch<T> gb{};
-    gb.nprob = 4;
-    for (int b = 0; b < 4; ++b) {
-        const int kpar = b >> 1;
-        GemmProblem<T>& P = gb.pr[b];
-        P.A = t.ana[b];
-        P.B = D.p[b];
-        P.C = U.p[b];
-        P.M = G.dims.nl[b];
-        P.N = int(G.dims.N[kpar]);
-        P.K = 2 * G.nside + 1;
-        P.lda = G.dims.nl[b];
-        P.ldb = G.dims.N[kpar];
-        P.ldc = G.dims.N[kpar];
-    }
-    STAGE(2, launch_gemm<T>(gb, s));
+    const GemmList<T>& gl = gemm_list<T>(G);
+    STAGE(2, launch_gemm<T>(gl.dev, gl.n, gl.tiles, D.p[0], U.p[0], s));
     Blocks4<const T> Gv;
     for (int b = 0; b < 4; ++b) Gv.p[b] = t.givens[b];
-    STAGE(3, launch_sweep_fwd<T>(U, Gv, G.dims, s));
+    if (!G.tables) STAGE(3, launch_sweep_fwd<T>(U, Gv, G.dims, s));
     STAGE(4, launch_pack<T>(cblocks(U), alm, G.d_alm_off, G.d_lmax, G.dims, accumulate, s));
     return HP2SPH_OK;
 }
@@ -353,27 +610,20 @@ int analysis_pass(Group& G, const double* maps_in, double* alm, void* ws, bool a
 int synthesis_pass(Group& G, const double* alm, double* out, const double* minus_from, void* ws, hipStream_t s) {
     Blocks4<double> D = blocks_at<double>(ws, G.off_D, G, G.rows_D);
     Blocks4<double> U = blocks_at<double>(ws, G.off_U, G, G.rows_U);
-    STAGE(5, launch_unpack(alm, G.d_alm_off, G.d_lmax, U, G.dims, s));
-    Blocks4<const double> Gv;
-    for (int b = 0; b < 4; ++b) Gv.p[b] = G.t64.givens[b];
-    STAGE(6, launch_sweep_bwd<double>(U, Gv, G.dims, s));
-    GemmBatch<double> gb{};
-    gb.nprob = 4;
-    for (int b = 0; b < 4; ++b) {
-        const int kpar = b >> 1;
-        GemmProblem<double>& P = gb.pr[b];
-        P.A = G.syn[b];
-        P.B = U.p[b];
-        P.C = D.p[b];
-        P.M = 2 * G.nside + 1;
-        P.N = int(G.dims.N[kpar]);
-        P.K = G.dims.nl[b];
-        P.lda = 2 * G.nside + 1;
-        P.ldb = G.dims.N[kpar];
-        P.ldc = G.dims.N[kpar];
+    const bool tab = G.syn64.n > 0 && G.tables;
+    // the staged synthesis sweeps need the map-major column order, whatever
+    // the group uses for its analysis
+    GroupDims dd = G.dims;
+    if (!tab) set_layout(dd, false);
+    STAGE(5, launch_unpack(alm, G.d_alm_off, G.d_lmax, U, dd, s));
+    if (!tab) {
+        Blocks4<const double> Gv;
+        for (int b = 0; b < 4; ++b) Gv.p[b] = G.t64.givens[b];
+        STAGE(6, launch_sweep_bwd<double>(U, Gv, dd, s));
     }
-    STAGE(7, launch_gemm<double>(gb, s));
-    STAGE(8, launch_ring_inverse(cblocks(D), G.rings, G.t64.fft, out, minus_from, G.d_map_off, G.dims, s));
+    const GemmList<double>& gl = tab ? G.syn64 : G.syn64_staged;
+    STAGE(7, launch_gemm<double>(gl.dev, gl.n, gl.tiles, U.p[0], D.p[0], s));
+    STAGE(8, launch_ring_inverse(cblocks(D), G.rings, G.t64.fft, out, minus_from, G.d_map_off, dd, s));
     return HP2SPH_OK;
 }
 
@@ -392,12 +642,19 @@ const char* hp2sph_last_error(void) { return g_last_error.c_str(); }
 
 int hp2sph_plan_create(const int32_t* nside, const int32_t* lmax, int32_t batch, int32_t mode,
                        hp2sph_plan_t* out) {
+    return hp2sph_plan_create_ex(nside, lmax, batch, mode, HP2SPH_STRATEGY_AUTO, out);
+}
+
+int hp2sph_plan_create_ex(const int32_t* nside, const int32_t* lmax, int32_t batch, int32_t mode, int32_t strategy,
+                          hp2sph_plan_t* out) {
     if (!out) return fail(HP2SPH_EINVAL, "out is null");
     *out = nullptr;
     if (!nside || !lmax) return fail(HP2SPH_EINVAL, "nside/lmax is null");
     if (batch <= 0) return fail(HP2SPH_EINVAL, "batch must be positive");
     if (mode != HP2SPH_F64 && mode != HP2SPH_F32_REFINE && mode != HP2SPH_F32)
         return fail(HP2SPH_EINVAL, "unknown precision mode");
+    if (strategy != HP2SPH_STRATEGY_AUTO && strategy != HP2SPH_STRATEGY_STAGED && strategy != HP2SPH_STRATEGY_TABLES)
+        return fail(HP2SPH_EINVAL, "unknown strategy");
     for (int b = 0; b < batch; ++b) {
         if (nside[b] < 2 || nside[b] > HP2SPH_MAX_NSIDE || !is_pow2(nside[b]))
             return fail(HP2SPH_EINVAL, "nside must be a power of two in [2, " + std::to_string(HP2SPH_MAX_NSIDE) + "]");
@@ -408,6 +665,7 @@ int hp2sph_plan_create(const int32_t* nside, const int32_t* lmax, int32_t batch,
         plan.reset(new hp2sph_plan_s());
         plan->batch = batch;
         plan->mode = mode;
+        plan->strategy = strategy;
         if (hipGetDevice(&plan->device) != hipSuccess) return fail(HP2SPH_EDEVICE, "hipGetDevice failed");
         plan->nside.assign(nside, nside + batch);
         plan->lmax.assign(lmax, lmax + batch);
@@ -434,6 +692,25 @@ int hp2sph_plan_create(const int32_t* nside, const int32_t* lmax, int32_t batch,
             build_group(plan.get(), *G);
             G->off_D = 0;
             G->off_U = align_up(G->bytes_D);
+            // strategy: per-order tables when asked, or (auto) when the batch is
+            // large enough to fill MFMA tiles and the tables take at most a
+            // quarter of the device memory; staged sweeps otherwise
+            bool tables = (strategy == HP2SPH_STRATEGY_TABLES);
+            if (strategy == HP2SPH_STRATEGY_AUTO) {
+                size_t fre = 0, tot = 0;
+                if (hipMemGetInfo(&fre, &tot) != hipSuccess) tot = 0;
+                tables = G->dims.nmaps >= 8 && order_table_bytes(*G, mode) <= tot / 4;
+            }
+            G->tables = tables;
+            set_layout(G->dims, tables);
+            staged_synthesis_list(*G, G->syn64_staged);
+            if (tables) {
+                build_order_tables(plan.get(), *G);
+            } else if (mode == HP2SPH_F64) {
+                staged_analysis_list<double>(*G, G->t64, G->ana64);
+            } else {
+                staged_analysis_list<float>(*G, G->t32, G->ana32);
+            }
             max_group = std::max(max_group, G->off_U + align_up(G->bytes_U));
             plan->groups.push_back(std::move(G));
         }
@@ -451,6 +728,16 @@ int hp2sph_plan_create(const int32_t* nside, const int32_t* lmax, int32_t batch,
         return fail(HP2SPH_EDEVICE, e.what());
     }
     *out = plan.release();
+    return HP2SPH_OK;
+}
+
+int hp2sph_plan_strategy(hp2sph_plan_t plan, int32_t* strategy) {
+    if (int e = check_plan(plan)) return e;
+    if (!strategy) return fail(HP2SPH_EINVAL, "strategy is null");
+    int nt = 0;
+    for (auto& g : plan->groups) nt += g->tables ? 1 : 0;
+    *strategy = (nt == 0) ? HP2SPH_STRATEGY_STAGED
+                          : (nt == int(plan->groups.size()) ? HP2SPH_STRATEGY_TABLES : HP2SPH_STRATEGY_AUTO);
     return HP2SPH_OK;
 }
 

@@ -2,9 +2,10 @@
 //
 // Data layout shared by the stages (one nside group of `nmaps` maps):
 //   Dsym_b [h][n]   block b = 0..3 (see tables.h), h = 0 .. 2 nside (the pole
-//                   row, the ring pairs, the equator), n = map * Npm + 2 k' + c
-//                   with k' = k / 2 the index of the longitude mode k of the
-//                   block's parity and c = 0 (real), 1 (imaginary).
+//                   row, the ring pairs, the equator), n = column of
+//                   (map, k', c) (GroupDims::cm/ck) with k' = k / 2 the index
+//                   of the longitude mode k of the block's parity and c = 0
+//                   (real), 1 (imaginary).
 //   U_b    [l'][n]  order-0/1 Legendre coefficients of block b (after the
 //                   fused colatitude fit), then, in place, a_l^m after the
 //                   Givens sweeps: column k' holds order m = 2k' + kpar at
@@ -47,24 +48,33 @@ struct GroupDims {
     int Npm[2];               // columns per map for k parity 0 / 1
     int64_t N[2];             // row strides nmaps * Npm
     int nl[4], nk[4], lmin[4], tpad[4];
+    // column of (map, k', c) within a row: map * cm[kpar] + k' * ck[kpar] + c.
+    // map-major (staged strategy; the sweeps need k' contiguous): cm = Npm,
+    // ck = 2.  mode-major (tables strategy; one mode's maps contiguous for the
+    // per-order GEMMs): cm = 2, ck = 2 * nmaps.
+    int64_t cm[2], ck[2];
+    int modemajor;
 };
 
+// One product of a grouped GEMM: C[m][n] = sum_k A[k][m] B[k][n].
+// A is absolute (a set-up table); B and C are element offsets from the
+// launch's base pointers, so a problem list can be built once per plan and
+// reused with any workspace.  Column n of B (C) is at (n >> 1) * bps + (n & 1)
+// (pair stride; 2 = contiguous), which lets a problem pick one mode's
+// (re, im) pair out of every map of an interleaved layout.
 template <class T>
 struct GemmProblem {
     const T* A;               // [K][M], row stride lda
-    const T* B;               // [K][N], row stride ldb
-    T* C;                     // [M][N], row stride ldc
+    int64_t boff, coff;       // element offsets of B and C
     int M, N, K;
     int64_t lda, ldb, ldc;
-    int tiles_n, tile_begin;
+    int64_t bps, cps;         // column-pair strides of B and C
+    int tiles_n, tile_begin;  // set by finalize_gemm_problems
 };
 
+// Assign tile ranges (in list order) and return the number of tiles.
 template <class T>
-struct GemmBatch {
-    GemmProblem<T> pr[4];
-    int nprob;
-    int total_tiles;
-};
+int finalize_gemm_problems(GemmProblem<T>* p, int n);
 
 // S1: per-ring real DFT, shift to unshifted longitudes, Nyquist rule and the
 // north/south combination, written into Dsym rows 1 .. 2 nside.
@@ -77,9 +87,25 @@ hipError_t launch_ring_forward(const double* maps, const int64_t* map_off, RingT
 template <class T>
 hipError_t launch_pole(Blocks4<T> D, const GroupDims& g, double w0, double w1, double w2, hipStream_t s);
 
-// C[m][n] = sum_k A[k][m] B[k][n] for up to four problems, one launch.
+// Grouped GEMM over a device-resident problem list (finalized), one launch.
 template <class T>
-hipError_t launch_gemm(GemmBatch<T> gb, hipStream_t s);
+hipError_t launch_gemm(const GemmProblem<T>* probs_dev, int nprob, int total_tiles, const T* Bbase, T* Cbase,
+                       hipStream_t s);
+
+// Set-up helpers for the per-order tables (see api.cpp):
+// U_v[l'][(v, k', c)] = M[row(h)][l'] (or M[l'][h]) for h = h_first + 2v + c,
+// replicated over every column k' of the block.
+template <class T>
+hipError_t launch_replicate(const T* mat, int64_t rs, int64_t cs, int nl, int h_first, int h_last, T* Uv, int nk,
+                            int nv, hipStream_t s);
+// Copy finished columns out of U_v into per-order tables.
+//   analysis:  tab[off[k']] [h - h0(k')][l' - k']   for h >= h0(k'), l' >= k'
+//   synthesis: tab[off[k']] [l' - k'][h - 1]        for h >= 1,      l' >= k'
+template <class T>
+hipError_t launch_scatter_tables(const T* Uv, int nl, int nk, int nv, int h_first, int h_last,
+                                 const int64_t* off, const int32_t* h0, int ldm_syn, bool synthesis, T* tab,
+                                 hipStream_t s);
+hipError_t launch_convert(const double* in, float* out, int64_t n, hipStream_t s);
 
 // S4 analysis sweeps (Givens, order 0/1 -> order m), in place on U.
 template <class T>

@@ -175,8 +175,9 @@ __global__ __launch_bounds__(kRingThreads) void k_ring_forward(const double* __r
                                                                FftTab<T> ft, Blocks4<T> D, GroupDims g) {
     extern __shared__ unsigned char smem_raw[];
     C2<T>* buf = reinterpret_cast<C2<T>*>(smem_raw);
-    const int h = blockIdx.x + 1;
-    const int b = blockIdx.y;
+    // map fastest: consecutive workgroups write the same rows of all maps
+    const int b = blockIdx.x;
+    const int h = blockIdx.y + 1;
     const int ns = g.nside, p = g.p;
     const double* m = maps + map_off[b];
     C2<T> DN[kRingKPT], DS[kRingKPT];
@@ -202,7 +203,7 @@ __global__ __launch_bounds__(kRingThreads) void k_ring_forward(const double* __r
             dm = cscale(csub(DN[i], DS[i]), T(0.5));
         }
         const int kpar = k & 1, kk = k >> 1;
-        const int64_t col = int64_t(b) * g.Npm[kpar] + 2 * kk;
+        const int64_t col = int64_t(b) * g.cm[kpar] + int64_t(kk) * g.ck[kpar];
         const int64_t row = int64_t(h) * g.N[kpar];
         T* bp = D.p[2 * kpar + 0];
         T* bm = D.p[2 * kpar + 1];
@@ -216,7 +217,7 @@ __global__ __launch_bounds__(kRingThreads) void k_ring_forward(const double* __r
 template <class T>
 hipError_t launch_ring_forward(const double* maps, const int64_t* map_off, RingTab rt, FftTab<T> ft, Blocks4<T> D,
                                const GroupDims& g, hipStream_t s) {
-    dim3 grid(2 * g.nside, g.nmaps);
+    dim3 grid(g.nmaps, 2 * g.nside);
     size_t shm = size_t(ft.fft_max) * sizeof(C2<T>);
     hipLaunchKernelGGL(k_ring_forward<T>, grid, dim3(kRingThreads), shm, s, maps, map_off, rt, ft, D, g);
     return hipGetLastError();
@@ -240,7 +241,9 @@ __global__ void k_pole(Blocks4<T> D, GroupDims g, double w0, double w1, double w
     else { blk = 3; col = i - 2 * N0 - N1; N = N1; }
     T* P = D.p[blk];
     T val = T(0);
-    if (blk < 2 && (col % g.Npm[0]) == 0) {
+    // (k' = 0, real part) columns of the k-even blocks hold the pole value
+    const bool k0re = g.modemajor ? (col < 2 * int64_t(g.nmaps) && (col & 1) == 0) : ((col % g.Npm[0]) == 0);
+    if (blk < 2 && k0re) {
         // k = 0, real part: the pole value (f_N +- f_S) / 2 from the ring means
         val = T(w0 * double(P[1 * N + col]) + w1 * double(P[2 * N + col]) + w2 * double(P[3 * N + col]));
     }
@@ -287,16 +290,24 @@ struct MfmaAcc<float> {
 constexpr int GBM = 128, GBN = 128, GBK = 16, GPAD = 4;
 
 template <class T>
-__global__ __launch_bounds__(256) void k_gemm(GemmBatch<T> gb) {
+__global__ __launch_bounds__(256) void k_gemm(const GemmProblem<T>* __restrict__ probs, int nprob,
+                                              const T* __restrict__ Bbase, T* __restrict__ Cbase) {
     __shared__ T As[GBK][GBM + GPAD];
     __shared__ T Bs[GBK][GBN + GPAD];
     int tile = blockIdx.x;
-    int pi = 0;
-    while (pi + 1 < gb.nprob && tile >= gb.pr[pi + 1].tile_begin) ++pi;
-    const GemmProblem<T> P = gb.pr[pi];
+    // problem of this tile: the last one whose tile_begin <= tile
+    int lo = 0, hi = nprob - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (probs[mid].tile_begin <= tile) lo = mid;
+        else hi = mid - 1;
+    }
+    const GemmProblem<T> P = probs[lo];
     tile -= P.tile_begin;
     const int tm = tile / P.tiles_n, tn = tile % P.tiles_n;
     const int m0 = tm * GBM, n0 = tn * GBN;
+    const T* B = Bbase + P.boff;
+    T* C = Cbase + P.coff;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
     using Acc = MfmaAcc<T>;
@@ -315,7 +326,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmBatch<T> gb) {
         for (int e = 0; e < 8; ++e) {
             const int mm = m0 + lc + e, nn = n0 + lc + e;
             ra[e] = (k < P.K && mm < P.M) ? P.A[int64_t(k) * P.lda + mm] : T(0);
-            rb[e] = (k < P.K && nn < P.N) ? P.B[int64_t(k) * P.ldb + nn] : T(0);
+            rb[e] = (k < P.K && nn < P.N) ? B[int64_t(k) * P.ldb + int64_t(nn >> 1) * P.bps + (nn & 1)] : T(0);
         }
     };
     gload(0);
@@ -350,25 +361,105 @@ __global__ __launch_bounds__(256) void k_gemm(GemmBatch<T> gb) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int mm = m0 + wm * 64 + i * 16 + Acc::row(lane, r);
-                if (mm < P.M && nn < P.N) P.C[int64_t(mm) * P.ldc + nn] = acc[i][j][r];
+                if (mm < P.M && nn < P.N)
+                    C[int64_t(mm) * P.ldc + int64_t(nn >> 1) * P.cps + (nn & 1)] = acc[i][j][r];
             }
         }
     }
 }
 
 template <class T>
-hipError_t launch_gemm(GemmBatch<T> gb, hipStream_t s) {
+int finalize_gemm_problems(GemmProblem<T>* p, int n) {
     int t = 0;
-    for (int i = 0; i < gb.nprob; ++i) {
-        auto& P = gb.pr[i];
-        const int tm = (P.M + GBM - 1) / GBM;
-        P.tiles_n = (P.N + GBN - 1) / GBN;
-        P.tile_begin = t;
-        t += tm * P.tiles_n;
+    for (int i = 0; i < n; ++i) {
+        const int tm = (p[i].M + GBM - 1) / GBM;
+        p[i].tiles_n = (p[i].N + GBN - 1) / GBN;
+        p[i].tile_begin = t;
+        t += tm * p[i].tiles_n;
     }
-    gb.total_tiles = t;
-    if (t == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_gemm<T>, dim3(t), dim3(256), 0, s, gb);
+    return t;
+}
+
+template <class T>
+hipError_t launch_gemm(const GemmProblem<T>* probs_dev, int nprob, int total_tiles, const T* Bbase, T* Cbase,
+                       hipStream_t s) {
+    if (total_tiles == 0 || nprob == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gemm<T>, dim3(total_tiles), dim3(256), 0, s, probs_dev, nprob, Bbase, Cbase);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Set-up helpers for the per-order tables
+// ---------------------------------------------------------------------------
+
+template <class T>
+__global__ void k_replicate(const T* __restrict__ mat, int64_t rs, int64_t cs, int nl, int h_first, int h_last,
+                            T* __restrict__ Uv, int nk, int nv) {
+    // one thread per (l', v, k', c)
+    const int64_t npm = 2 * int64_t(nk);
+    const int64_t total = int64_t(nl) * nv * npm;
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= total) return;
+    const int lp = int(i / (nv * npm));
+    const int64_t rem = i % (nv * npm);
+    const int v = int(rem / npm);
+    const int c = int(rem % 2);
+    const int h = h_first + 2 * v + c;
+    Uv[i] = (h <= h_last) ? mat[int64_t(h) * rs + int64_t(lp) * cs] : T(0);
+}
+
+template <class T>
+hipError_t launch_replicate(const T* mat, int64_t rs, int64_t cs, int nl, int h_first, int h_last, T* Uv, int nk,
+                            int nv, hipStream_t s) {
+    const int64_t total = int64_t(nl) * nv * 2 * nk;
+    hipLaunchKernelGGL(k_replicate<T>, dim3(unsigned((total + 255) / 256)), dim3(256), 0, s, mat, rs, cs, nl,
+                       h_first, h_last, Uv, nk, nv);
+    return hipGetLastError();
+}
+
+template <class T>
+__global__ void k_scatter_tables(const T* __restrict__ Uv, int nl, int nk, int nv, int h_first, int h_last,
+                                 const int64_t* __restrict__ off, const int32_t* __restrict__ h0v, int ldm_syn,
+                                 int synthesis, T* __restrict__ tab) {
+    const int64_t npm = 2 * int64_t(nk);
+    const int64_t total = int64_t(nl) * nv * npm;
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= total) return;
+    const int lp = int(i / (nv * npm));
+    const int64_t rem = i % (nv * npm);
+    const int v = int(rem / npm);
+    const int kk = int((rem % npm) >> 1);
+    const int c = int(rem % 2);
+    const int h = h_first + 2 * v + c;
+    if (h > h_last || lp < kk) return;
+    const int M = nl - kk;
+    if (synthesis) {
+        if (h < 1) return;
+        tab[off[kk] + int64_t(lp - kk) * ldm_syn + (h - 1)] = Uv[i];
+    } else {
+        const int h0 = h0v[kk];
+        if (h < h0) return;
+        tab[off[kk] + int64_t(h - h0) * M + (lp - kk)] = Uv[i];
+    }
+}
+
+template <class T>
+hipError_t launch_scatter_tables(const T* Uv, int nl, int nk, int nv, int h_first, int h_last, const int64_t* off,
+                                 const int32_t* h0, int ldm_syn, bool synthesis, T* tab, hipStream_t s) {
+    const int64_t total = int64_t(nl) * nv * 2 * nk;
+    hipLaunchKernelGGL(k_scatter_tables<T>, dim3(unsigned((total + 255) / 256)), dim3(256), 0, s, Uv, nl, nk, nv,
+                       h_first, h_last, off, h0, ldm_syn, synthesis ? 1 : 0, tab);
+    return hipGetLastError();
+}
+
+__global__ void k_convert(const double* __restrict__ in, float* __restrict__ out, int64_t n) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = float(in[i]);
+}
+
+hipError_t launch_convert(const double* in, float* out, int64_t n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_convert, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, in, out, n);
     return hipGetLastError();
 }
 
@@ -673,7 +764,7 @@ __global__ void k_pack(Blocks4<const T> U, double* __restrict__ alm, const int64
     const int l = g.lmin[blk] + 2 * lp, m = 2 * kk + kpar;
     const int L = lmaxv[map];
     if (l < m || l > L) return;
-    const T* src = U.p[blk] + int64_t(lp) * g.N[kpar] + int64_t(map) * g.Npm[kpar] + 2 * kk;
+    const T* src = U.p[blk] + int64_t(lp) * g.N[kpar] + int64_t(map) * g.cm[kpar] + int64_t(kk) * g.ck[kpar];
     const int64_t o = 2 * (alm_off[map] + int64_t(m) * (2 * L + 1 - m) / 2 + l);
     const double re = double(src[0]), im = double(src[1]);
     if (accumulate) {
@@ -712,7 +803,7 @@ __global__ void k_unpack(const double* __restrict__ alm, const int64_t* __restri
         re = alm[o];
         im = alm[o + 1];
     }
-    double* dst = U.p[blk] + int64_t(lp) * g.N[kpar] + int64_t(map) * g.Npm[kpar] + 2 * kk;
+    double* dst = U.p[blk] + int64_t(lp) * g.N[kpar] + int64_t(map) * g.cm[kpar] + int64_t(kk) * g.ck[kpar];
     dst[0] = re;
     dst[1] = im;
 }
@@ -747,7 +838,7 @@ __device__ void ring_synth(const Blocks4<const double>& D, int h, int sgn, int n
     // G_k = D_k e^{i k phi0}, D_k = D+_k + sgn D-_k
     auto Gk = [&](int k) -> C2<double> {
         const int kpar = k & 1, kk = k >> 1;
-        const int64_t o = int64_t(h) * g.N[kpar] + int64_t(map) * g.Npm[kpar] + 2 * kk;
+        const int64_t o = int64_t(h) * g.N[kpar] + int64_t(map) * g.cm[kpar] + int64_t(kk) * g.ck[kpar];
         const double* bp = D.p[2 * kpar];
         const double* bm = D.p[2 * kpar + 1];
         C2<double> d = {bp[o] + sgn * bm[o], bp[o + 1] + sgn * bm[o + 1]};
@@ -866,8 +957,14 @@ template hipError_t launch_ring_forward<float>(const double*, const int64_t*, Ri
                                                Blocks4<float>, const GroupDims&, hipStream_t);
 template hipError_t launch_pole<double>(Blocks4<double>, const GroupDims&, double, double, double, hipStream_t);
 template hipError_t launch_pole<float>(Blocks4<float>, const GroupDims&, double, double, double, hipStream_t);
-template hipError_t launch_gemm<double>(GemmBatch<double>, hipStream_t);
-template hipError_t launch_gemm<float>(GemmBatch<float>, hipStream_t);
+template hipError_t launch_gemm<double>(const GemmProblem<double>*, int, int, const double*, double*, hipStream_t);
+template hipError_t launch_gemm<float>(const GemmProblem<float>*, int, int, const float*, float*, hipStream_t);
+template int finalize_gemm_problems<double>(GemmProblem<double>*, int);
+template int finalize_gemm_problems<float>(GemmProblem<float>*, int);
+template hipError_t launch_replicate<double>(const double*, int64_t, int64_t, int, int, int, double*, int, int,
+                                             hipStream_t);
+template hipError_t launch_scatter_tables<double>(const double*, int, int, int, int, int, const int64_t*,
+                                                  const int32_t*, int, bool, double*, hipStream_t);
 template hipError_t launch_sweep_fwd<double>(Blocks4<double>, Blocks4<const double>, const GroupDims&, hipStream_t);
 template hipError_t launch_sweep_fwd<float>(Blocks4<float>, Blocks4<const float>, const GroupDims&, hipStream_t);
 template hipError_t launch_sweep_bwd<double>(Blocks4<double>, Blocks4<const double>, const GroupDims&, hipStream_t);

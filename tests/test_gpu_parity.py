@@ -140,3 +140,69 @@ def test_f32_single_pass_vs_oracle(nside):
     e = rel_err(a, O.analyze(f, nside))
     print(f"nside {nside}: f32 single pass rel err {e:.3e}")
     assert e < 1e-5
+
+
+# ---- per-order tables strategy (sweeps applied at plan creation) ----
+
+@pytest.mark.parametrize("nside,nb", [(2, 1), (4, 3), (16, 2), (64, 2)])
+def test_tables_f64_vs_oracle(nside, nb):
+    maps = [white_map(nside, 400 + nside + i) for i in range(nb)]
+    plan = P.Plan(nside, batch=nb, mode="f64", strategy="tables")
+    assert plan.strategy == "tables"
+    a = plan.analyze(_dev(np.concatenate(maps))).cpu().numpy()
+    sz = O.alm_size(2 * nside)
+    for i in range(nb):
+        e = rel_err(a[i * sz:(i + 1) * sz], O.analyze(maps[i], nside))
+        print(f"tables nside {nside} map {i}: rel err {e:.3e}")
+        assert e < TOL64
+
+
+def test_tables_and_staged_agree_on_uneven_batch():
+    nsides = [16, 8, 16, 32, 8]
+    maps = np.concatenate([white_map(n, 500 + i) for i, n in enumerate(nsides)])
+    lmax = [2 * n - (i % 2) for i, n in enumerate(nsides)]
+    a_t = P.Plan(nsides, lmax, mode="f64", strategy="tables").analyze(_dev(maps)).cpu().numpy()
+    a_s = P.Plan(nsides, lmax, mode="f64", strategy="staged").analyze(_dev(maps)).cpu().numpy()
+    assert rel_err(a_t, a_s) < TOL64
+
+
+@pytest.mark.parametrize("nside", [8, 32])
+def test_tables_f32_refine_vs_refined_oracle(nside):
+    f, _ = cmb_map(1, 600 + nside, nside)
+    plan = P.Plan(nside, batch=1, mode="f32_refine", strategy="tables")
+    assert plan.strategy == "tables"
+    a = plan.analyze(_dev(f)).cpu().numpy()
+    e = rel_err(a, O.analyze_refined(f, nside))
+    print(f"tables f32+refine nside {nside}: vs O_ref {e:.3e}")
+    assert e < 1e-5
+
+
+def test_tables_synthesis_path_in_refinement_matches_staged():
+    """The FP64 synthesis of the refinement through the tables equals the staged one."""
+    nside = 16
+    rng = np.random.default_rng(7)
+    lmax = 2 * nside
+    a = rng.standard_normal(O.alm_size(lmax)) + 1j * rng.standard_normal(O.alm_size(lmax))
+    for l in range(lmax + 1):
+        a[O.alm_index(l, 0, lmax)] = a[O.alm_index(l, 0, lmax)].real
+    pt = P.Plan(nside, batch=1, mode="f32_refine", strategy="tables")
+    f = pt.synthesize(_dev(a)).cpu().numpy()
+    assert rel_err(f, O.synthesize(a, nside, lmax)) < TOL64
+
+
+def test_tables_f64_plan_synthesis_uses_staged_path_correctly():
+    """An F64 tables plan synthesises through the staged sweeps (map-major)."""
+    nside, nb = 8, 3
+    lmax = 2 * nside
+    rng = np.random.default_rng(8)
+    a = rng.standard_normal(nb * O.alm_size(lmax)) + 1j * rng.standard_normal(nb * O.alm_size(lmax))
+    for i in range(nb):
+        for l in range(lmax + 1):
+            k = i * O.alm_size(lmax) + O.alm_index(l, 0, lmax)
+            a[k] = a[k].real
+    plan = P.Plan(nside, batch=nb, mode="f64", strategy="tables")
+    f = plan.synthesize(_dev(a)).cpu().numpy()
+    sz, npx = O.alm_size(lmax), O.npix(nside)
+    for i in range(nb):
+        ref = O.synthesize(a[i * sz:(i + 1) * sz], nside, lmax)
+        assert rel_err(f[i * npx:(i + 1) * npx], ref) < TOL64
