@@ -52,12 +52,31 @@ def sweep_rotations(nside, nmaps):
     return 2 * nmaps * tot
 
 
-def stage_work(stage, nside, nmaps, tsize):
+def order_gemm_flops(nside, nmaps, synthesis):
+    """Flops of the per-order GEMMs: for block b and mode k' a (nl-k') x K' matrix
+    times 2*nmaps columns; K' skips the polar rings that cannot carry the mode
+    (analysis) or is the 2*nside rings (synthesis)."""
+    p, nl, nk = block_dims(nside)
+    K = 2 * nside + 1
+    tot = 0
+    for b in range(4):
+        kpar = b >> 1
+        for kk in range(nk[b]):
+            m = 2 * kk + kpar
+            h0 = 0 if m == 0 else (m + 1) // 2
+            kd = 2 * nside if synthesis else K - h0
+            tot += 2 * (nl[b] - kk) * kd * 2 * nmaps
+    return tot
+
+
+def stage_work(stage, nside, nmaps, tsize, strategy="staged"):
     """(kind, amount) algorithmic work of one launch: ('flop', n) or ('byte', n)."""
     p, nl, nk = block_dims(nside)
     K = 2 * nside + 1
     N = [nmaps * 2 * nk[0], nmaps * 2 * nk[2]]
     npix = 12 * nside * nside * nmaps
+    if stage in ("gemm_analysis", "gemm_synthesis") and strategy == "tables":
+        return "flop", order_gemm_flops(nside, nmaps, stage == "gemm_synthesis")
     if stage == "gemm_analysis":
         return "flop", sum(2 * nl[b] * K * N[b >> 1] for b in range(4))
     if stage == "gemm_synthesis":
@@ -91,9 +110,9 @@ def stage_dtype(stage, mode):
     return "f32"
 
 
-def roofline(stage, mode, nside, nmaps, ms_total, launches):
+def roofline(stage, mode, nside, nmaps, ms_total, launches, strategy="staged"):
     dt = stage_dtype(stage, mode)
-    kind, amount = stage_work(stage, nside, nmaps, 4 if dt == "f32" else 8)
+    kind, amount = stage_work(stage, nside, nmaps, 4 if dt == "f32" else 8, strategy)
     avg_s = ms_total / launches / 1e3
     bound = stage_bound(stage)
     if bound == "hbm":
@@ -103,12 +122,13 @@ def roofline(stage, mode, nside, nmaps, ms_total, launches):
         achieved = amount / avg_s / 1e12
         peak, unit = PEAK_TFLOPS[bound][dt], "TFLOP/s"
     return {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit, "frac": achieved / peak,
-            "traffic": measured_traffic(stage, dt, nside, nmaps), "kernel": stage, "dtype": dt,
+            "traffic": measured_traffic(stage, dt, nside, nmaps, strategy), "kernel": stage, "dtype": dt,
+            "strategy": strategy,
             "avg_launch_ms": avg_s * 1e3,
             "work_per_launch": amount, "work_unit": kind}
 
 
-def measured_traffic(stage, dtype, nside, nmaps):
+def measured_traffic(stage, dtype, nside, nmaps, strategy):
     """HBM bytes per launch from the committed counter runs (profiles/), scaled
     by the copy-kernel calibration; None if the kernels changed since then or
     the workload differs."""
@@ -121,7 +141,7 @@ def measured_traffic(stage, dtype, nside, nmaps):
         with open(src, "rb") as fh:
             if hashlib.sha256(fh.read()).hexdigest() != js["kernels_hip_sha256"]:
                 return None
-        if js["workload"] != {"nside": nside, "lmax": 2 * nside, "batch": nmaps}:
+        if js["workload"] != {"nside": nside, "lmax": 2 * nside, "batch": nmaps, "strategy": strategy}:
             return None
         e = js["stages"].get(f"{stage}/{dtype}")
         return None if e is None else e["read_bytes"] + e["write_bytes"]
@@ -135,7 +155,7 @@ def make_inputs(torch, P, W, nside, nmaps):
     lmax = 2 * nside
     cl = W.spectrum(2, lmax)
     alm = np.concatenate([W.draw_alm(cl, lmax, W.rng_for(2, i)) for i in range(nmaps)])
-    syn = P.Plan(nside, lmax, batch=nmaps, mode="f64")
+    syn = P.Plan(nside, lmax, batch=nmaps, mode="f64", strategy="staged")
     maps = syn.synthesize(torch.from_numpy(alm).cuda())
     torch.cuda.synchronize()
     syn.close()
@@ -151,9 +171,9 @@ def make_inputs(torch, P, W, nside, nmaps):
     return maps
 
 
-def time_mode(torch, P, maps, nside, nmaps, mode, steps, warmup):
+def time_mode(torch, P, maps, nside, nmaps, mode, steps, warmup, strategy):
     t0 = time.perf_counter()
-    plan = P.Plan(nside, 2 * nside, batch=nmaps, mode=mode)
+    plan = P.Plan(nside, 2 * nside, batch=nmaps, mode=mode, strategy=strategy)
     setup_s = time.perf_counter() - t0
     alm = torch.empty(plan.alm_total, dtype=torch.complex128, device="cuda")
     cl = torch.empty(plan.cl_total, dtype=torch.float64, device="cuda")
@@ -216,6 +236,9 @@ def main():
     ap.add_argument("--nside", type=int, default=1024)
     ap.add_argument("--batch", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--strategy", default="auto", choices=["auto", "staged", "tables"])
+    ap.add_argument("--modes", default="f32_refine,f64",
+                    help="precision modes to time; the headline is f32_refine (profiling runs may pick one)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (maps of a batch "
@@ -235,39 +258,46 @@ def main():
     print(f"[bench] building inputs: {nmaps} maps, nside {nside}", file=sys.stderr, flush=True)
     maps = make_inputs(torch, P, W, nside, nmaps)
 
+    modes = [m for m in args.modes.split(",") if m]
     results = {}
-    for mode in ("f32_refine", "f64"):
+    for mode in modes:
         print(f"[bench] timing {mode}", file=sys.stderr, flush=True)
-        plan, alm, cl, dt, setup_s, prof = time_mode(torch, P, maps, nside, nmaps, mode, args.steps, args.warmup)
-        results[mode] = {"plan": plan, "alm": alm, "cl": cl, "dt": dt, "setup_s": setup_s, "prof": prof}
+        plan, alm, cl, dt, setup_s, prof = time_mode(torch, P, maps, nside, nmaps, mode, args.steps, args.warmup,
+                                                     args.strategy)
+        results[mode] = {"plan": plan, "alm": alm, "cl": cl, "dt": dt, "setup_s": setup_s, "prof": prof,
+                         "strategy": plan.strategy}
         print(f"[bench] {mode}: {1e3 * dt / args.steps:.2f} ms/step, set-up {setup_s:.1f} s", file=sys.stderr,
               flush=True)
 
-    head = results["f32_refine"]
-    f64 = results["f64"]
+    head = results.get("f32_refine") or results[modes[0]]
+    head_mode = "f32_refine" if "f32_refine" in results else modes[0]
+    f64 = results.get("f64")
     ms_step = 1e3 * head["dt"] / args.steps
     value = nmaps * args.steps / head["dt"]
-    f64_value = nmaps * args.steps / f64["dt"]
+    f64_value = nmaps * args.steps / f64["dt"] if f64 else None
 
     # dominant kernel of the headline mode, against its binding roofline
     prof = head["prof"]
     dom = max(prof, key=lambda k: prof[k][0])
-    roof = roofline(dom, "f32_refine", nside, nmaps, prof[dom][0], prof[dom][1])
+    roof = roofline(dom, head_mode, nside, nmaps, prof[dom][0], prof[dom][1], head["strategy"])
     stages = {}
-    for mode in ("f32_refine", "f64"):
+    for mode in modes:
         pr = results[mode]["prof"]
         stages[mode] = {k: {"ms_per_step": v[0] / args.steps, "launches": v[1],
-                            **{kk: vv for kk, vv in roofline(k, mode, nside, nmaps, v[0], v[1]).items()
+                            **{kk: vv for kk, vv in roofline(k, mode, nside, nmaps, v[0], v[1],
+                                                             results[mode]["strategy"]).items()
                                if kk in ("achieved", "unit", "frac")}}
                         for k, v in pr.items() if v[1] > 0}
 
     # FP32+refine against the FP64 GPU result (both on the same maps)
-    a32 = head["alm"].cpu().numpy()
-    a64 = f64["alm"].cpu().numpy()
-    c32 = head["cl"].cpu().numpy()
-    c64 = f64["cl"].cpu().numpy()
-    rel_a = float(np.max(np.abs(a32 - a64)) / np.max(np.abs(a64)))
-    rel_cl = float(np.max(np.abs(c32[2:] - c64[2:]) / np.abs(c64[2:])))
+    rel_a = rel_cl = None
+    if f64 is not None and head is not f64:
+        a32 = head["alm"].cpu().numpy()
+        a64 = f64["alm"].cpu().numpy()
+        c32 = head["cl"].cpu().numpy()
+        c64 = f64["cl"].cpu().numpy()
+        rel_a = float(np.max(np.abs(a32 - a64)) / np.max(np.abs(a64)))
+        rel_cl = float(np.max(np.abs(c32[2:] - c64[2:]) / np.abs(c64[2:])))
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -289,12 +319,13 @@ def main():
         "dtype": "f32+f64",
         "data": "synthetic",
         "config": {"workload": f"nside{nside}_L{lmax}_b{nmaps}", "nside": nside, "lmax": lmax, "batch": nmaps,
-                   "mode": "f32_refine",
+                   "mode": head_mode, "strategy": head["strategy"],
                    "input": "seeded Gaussian a_lm, C_l=exp(-l(l+1)s^2)/(l(l+1)), s=0.005, GPU FP64 synthesis, "
                             "+ white noise 1e-3 x map rms"},
         "f64_maps_per_s": f64_value,
-        "f64_ms_per_step": 1e3 * f64["dt"] / args.steps,
+        "f64_ms_per_step": 1e3 * f64["dt"] / args.steps if f64 else None,
         "setup_s": {m: results[m]["setup_s"] for m in results},
+        "strategy": {m: results[m]["strategy"] for m in results},
         "roofline": roof,
         "stages": stages,
         "f32refine_vs_gpu_f64": {"max_abs_da_over_max_a": rel_a, "max_rel_dcl_l_ge_2": rel_cl},

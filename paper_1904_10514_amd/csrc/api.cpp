@@ -69,7 +69,8 @@ I* upload_int(std::vector<std::unique_ptr<DevBuf>>& owned, const std::vector<I>&
 template <class T>
 struct GemmList {
     GemmProblem<T>* dev = nullptr;
-    int n = 0, tiles = 0;
+    int32_t* tmap = nullptr;      // workgroup -> (problem, tile), XCD-aware
+    int n = 0, tiles = 0, slots = 0;
 };
 
 struct Group {
@@ -339,6 +340,9 @@ void upload_list(Group& G, std::vector<GemmProblem<T>>& v, GemmList<T>& out) {
     out.tiles = finalize_gemm_problems<T>(v.data(), int(v.size()));
     out.n = int(v.size());
     out.dev = upload_int(G.owned, v);
+    std::vector<int32_t> tm = xcd_tile_map<T>(v.data(), int(v.size()));
+    out.slots = int(tm.size() / 2);
+    out.tmap = upload_int(G.owned, tm);
 }
 
 template <class T>
@@ -598,7 +602,7 @@ int analysis_pass(Group& G, const double* maps_in, double* alm, void* ws, bool a
     STAGE(0, launch_ring_forward<T>(maps_in, G.d_map_off, G.rings, t.fft, D, G.dims, s));
     STAGE(1, launch_pole<T>(D, G.dims, G.pole_w[0], G.pole_w[1], G.pole_w[2], s));
     const GemmList<T>& gl = gemm_list<T>(G);
-    STAGE(2, launch_gemm<T>(gl.dev, gl.n, gl.tiles, D.p[0], U.p[0], s));
+    STAGE(2, launch_gemm<T>(gl.dev, gl.tmap, gl.slots, D.p[0], U.p[0], s));
     Blocks4<const T> Gv;
     for (int b = 0; b < 4; ++b) Gv.p[b] = t.givens[b];
     if (!G.tables) STAGE(3, launch_sweep_fwd<T>(U, Gv, G.dims, s));
@@ -622,7 +626,7 @@ int synthesis_pass(Group& G, const double* alm, double* out, const double* minus
         STAGE(6, launch_sweep_bwd<double>(U, Gv, dd, s));
     }
     const GemmList<double>& gl = tab ? G.syn64 : G.syn64_staged;
-    STAGE(7, launch_gemm<double>(gl.dev, gl.n, gl.tiles, U.p[0], D.p[0], s));
+    STAGE(7, launch_gemm<double>(gl.dev, gl.tmap, gl.slots, U.p[0], D.p[0], s));
     STAGE(8, launch_ring_inverse(cblocks(D), G.rings, G.t64.fft, out, minus_from, G.d_map_off, dd, s));
     return HP2SPH_OK;
 }

@@ -16,6 +16,7 @@
 
 #include <hip/hip_runtime.h>
 #include <cstdint>
+#include <vector>
 
 namespace hp2sph {
 
@@ -76,6 +77,13 @@ struct GemmProblem {
 template <class T>
 int finalize_gemm_problems(GemmProblem<T>* p, int n);
 
+// Workgroup -> (problem, tile) map that keeps every problem on one XCD:
+// problems are dealt to the 8 XCDs in list order (longest first), and
+// workgroup id is placed so that id mod 8 (the XCD the hardware dispatches it
+// to) is the problem's XCD.  Entries of -1 pad the XCDs to equal length.
+template <class T>
+std::vector<int32_t> xcd_tile_map(const GemmProblem<T>* p, int n);
+
 // S1: per-ring real DFT, shift to unshifted longitudes, Nyquist rule and the
 // north/south combination, written into Dsym rows 1 .. 2 nside.
 template <class T>
@@ -89,8 +97,8 @@ hipError_t launch_pole(Blocks4<T> D, const GroupDims& g, double w0, double w1, d
 
 // Grouped GEMM over a device-resident problem list (finalized), one launch.
 template <class T>
-hipError_t launch_gemm(const GemmProblem<T>* probs_dev, int nprob, int total_tiles, const T* Bbase, T* Cbase,
-                       hipStream_t s);
+hipError_t launch_gemm(const GemmProblem<T>* probs_dev, const int32_t* tmap_dev, int nslots, const T* Bbase,
+                       T* Cbase, hipStream_t s);
 
 // Set-up helpers for the per-order tables (see api.cpp):
 // U_v[l'][(v, k', c)] = M[row(h)][l'] (or M[l'][h]) for h = h_first + 2v + c,

@@ -130,6 +130,22 @@ __device__ DftResult<T> lds_dft(C2<T>* buf, int L, int M_blue, const T* chirp, c
 // S1: forward ring transform
 // ---------------------------------------------------------------------------
 
+// Workgroup -> (map, ring pair).  Consecutive workgroups are dealt to the 8
+// XCDs in turn, so ring pairs are assigned to XCDs (h mod 8) and, within an
+// XCD, all maps of one ring pair run back to back: their writes (reads) of
+// the same Dsym rows then meet in that XCD's L2.
+__device__ __forceinline__ void ring_block(int nmaps, int npairs, int& map, int& h) {
+    const int id = blockIdx.x + gridDim.x * blockIdx.y;
+    if ((npairs & 7) == 0) {
+        const int x = id & 7, s = id >> 3;
+        h = (s / nmaps) * 8 + x + 1;
+        map = s % nmaps;
+    } else {
+        map = blockIdx.x;
+        h = blockIdx.y + 1;
+    }
+}
+
 constexpr int kRingThreads = 512;
 constexpr int kRingKPT = 9;   // (HP2SPH_MAX_NSIDE * 2 + 1) / kRingThreads, rounded up
 
@@ -175,9 +191,8 @@ __global__ __launch_bounds__(kRingThreads) void k_ring_forward(const double* __r
                                                                FftTab<T> ft, Blocks4<T> D, GroupDims g) {
     extern __shared__ unsigned char smem_raw[];
     C2<T>* buf = reinterpret_cast<C2<T>*>(smem_raw);
-    // map fastest: consecutive workgroups write the same rows of all maps
-    const int b = blockIdx.x;
-    const int h = blockIdx.y + 1;
+    int b, h;
+    ring_block(g.nmaps, 2 * g.nside, b, h);
     const int ns = g.nside, p = g.p;
     const double* m = maps + map_off[b];
     C2<T> DN[kRingKPT], DS[kRingKPT];
@@ -290,20 +305,15 @@ struct MfmaAcc<float> {
 constexpr int GBM = 128, GBN = 128, GBK = 16, GPAD = 4;
 
 template <class T>
-__global__ __launch_bounds__(256) void k_gemm(const GemmProblem<T>* __restrict__ probs, int nprob,
-                                              const T* __restrict__ Bbase, T* __restrict__ Cbase) {
+__global__ __launch_bounds__(256) void k_gemm(const GemmProblem<T>* __restrict__ probs,
+                                              const int32_t* __restrict__ tmap, const T* __restrict__ Bbase,
+                                              T* __restrict__ Cbase) {
     __shared__ T As[GBK][GBM + GPAD];
     __shared__ T Bs[GBK][GBN + GPAD];
-    int tile = blockIdx.x;
-    // problem of this tile: the last one whose tile_begin <= tile
-    int lo = 0, hi = nprob - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (probs[mid].tile_begin <= tile) lo = mid;
-        else hi = mid - 1;
-    }
-    const GemmProblem<T> P = probs[lo];
-    tile -= P.tile_begin;
+    const int pi = tmap[2 * blockIdx.x];
+    if (pi < 0) return;
+    const GemmProblem<T> P = probs[pi];
+    int tile = tmap[2 * blockIdx.x + 1];
     const int tm = tile / P.tiles_n, tn = tile % P.tiles_n;
     const int m0 = tm * GBM, n0 = tn * GBN;
     const T* B = Bbase + P.boff;
@@ -381,10 +391,32 @@ int finalize_gemm_problems(GemmProblem<T>* p, int n) {
 }
 
 template <class T>
-hipError_t launch_gemm(const GemmProblem<T>* probs_dev, int nprob, int total_tiles, const T* Bbase, T* Cbase,
-                       hipStream_t s) {
-    if (total_tiles == 0 || nprob == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_gemm<T>, dim3(total_tiles), dim3(256), 0, s, probs_dev, nprob, Bbase, Cbase);
+std::vector<int32_t> xcd_tile_map(const GemmProblem<T>* p, int n) {
+    constexpr int kXcd = 8;
+    std::vector<std::vector<int32_t>> per(kXcd);
+    for (int i = 0; i < n; ++i) {
+        const int tiles = ((p[i].M + GBM - 1) / GBM) * p[i].tiles_n;
+        for (int t = 0; t < tiles; ++t) {
+            per[i % kXcd].push_back(i);
+            per[i % kXcd].push_back(t);
+        }
+    }
+    size_t len = 0;
+    for (auto& v : per) len = std::max(len, v.size() / 2);
+    std::vector<int32_t> out(2 * len * kXcd, -1);
+    for (int x = 0; x < kXcd; ++x)
+        for (size_t s = 0; s < per[x].size() / 2; ++s) {
+            out[2 * (s * kXcd + x)] = per[x][2 * s];
+            out[2 * (s * kXcd + x) + 1] = per[x][2 * s + 1];
+        }
+    return out;
+}
+
+template <class T>
+hipError_t launch_gemm(const GemmProblem<T>* probs_dev, const int32_t* tmap_dev, int nslots, const T* Bbase,
+                       T* Cbase, hipStream_t s) {
+    if (nslots == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gemm<T>, dim3(nslots), dim3(256), 0, s, probs_dev, tmap_dev, Bbase, Cbase);
     return hipGetLastError();
 }
 
@@ -750,17 +782,33 @@ hipError_t launch_sweep_bwd(Blocks4<T> U, Blocks4<const T> G, const GroupDims& g
 // pack / unpack between U and the packed complex128 alm
 // ---------------------------------------------------------------------------
 
-// one thread per (map, block, l', k') complex entry
+// one thread per (block, map, l', k') complex entry; the fastest-varying index
+// follows the column order of U (k' for map-major, map for mode-major) so
+// that the U side is coalesced
+__device__ __forceinline__ bool pack_index(const GroupDims& g, int blk, int64_t e, int& map, int& lp, int& kk) {
+    const int nk = g.nk[blk], nl = g.nl[blk];
+    if (e >= int64_t(nk) * nl * g.nmaps) return false;
+    if (g.modemajor) {
+        map = int(e % g.nmaps);
+        const int64_t t = e / g.nmaps;
+        kk = int(t % nk);
+        lp = int(t / nk);
+    } else {
+        kk = int(e % nk);
+        const int64_t t = e / nk;
+        lp = int(t % nl);
+        map = int(t / nl);
+    }
+    return true;
+}
+
 template <class T>
 __global__ void k_pack(Blocks4<const T> U, double* __restrict__ alm, const int64_t* __restrict__ alm_off,
                        const int32_t* __restrict__ lmaxv, GroupDims g, int accumulate) {
-    const int blk = blockIdx.z;
-    const int map = blockIdx.y;
+    const int blk = blockIdx.y;
     const int kpar = blk >> 1;
-    const int nk = g.nk[blk], nl = g.nl[blk];
-    const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (idx >= int64_t(nk) * nl) return;
-    const int lp = int(idx / nk), kk = int(idx % nk);
+    int map, lp, kk;
+    if (!pack_index(g, blk, int64_t(blockIdx.x) * blockDim.x + threadIdx.x, map, lp, kk)) return;
     const int l = g.lmin[blk] + 2 * lp, m = 2 * kk + kpar;
     const int L = lmaxv[map];
     if (l < m || l > L) return;
@@ -776,25 +824,25 @@ __global__ void k_pack(Blocks4<const T> U, double* __restrict__ alm, const int64
     }
 }
 
+static dim3 pack_grid(const GroupDims& g) {
+    int64_t most = 0;
+    for (int b = 0; b < 4; ++b) most = std::max<int64_t>(most, int64_t(g.nk[b]) * g.nl[b] * g.nmaps);
+    return dim3(unsigned((most + 255) / 256), 4);
+}
+
 template <class T>
 hipError_t launch_pack(Blocks4<const T> U, double* alm, const int64_t* alm_off, const int32_t* lmax,
                        const GroupDims& g, bool accumulate, hipStream_t s) {
-    int64_t most = 0;
-    for (int b = 0; b < 4; ++b) most = std::max<int64_t>(most, int64_t(g.nk[b]) * g.nl[b]);
-    dim3 grid(unsigned((most + 255) / 256), g.nmaps, 4);
-    hipLaunchKernelGGL(k_pack<T>, grid, dim3(256), 0, s, U, alm, alm_off, lmax, g, accumulate ? 1 : 0);
+    hipLaunchKernelGGL(k_pack<T>, pack_grid(g), dim3(256), 0, s, U, alm, alm_off, lmax, g, accumulate ? 1 : 0);
     return hipGetLastError();
 }
 
 __global__ void k_unpack(const double* __restrict__ alm, const int64_t* __restrict__ alm_off,
                          const int32_t* __restrict__ lmaxv, Blocks4<double> U, GroupDims g) {
-    const int blk = blockIdx.z;
-    const int map = blockIdx.y;
+    const int blk = blockIdx.y;
     const int kpar = blk >> 1;
-    const int nk = g.nk[blk], nl = g.nl[blk];
-    const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (idx >= int64_t(nk) * nl) return;
-    const int lp = int(idx / nk), kk = int(idx % nk);
+    int map, lp, kk;
+    if (!pack_index(g, blk, int64_t(blockIdx.x) * blockDim.x + threadIdx.x, map, lp, kk)) return;
     const int l = g.lmin[blk] + 2 * lp, m = 2 * kk + kpar;
     const int L = lmaxv[map];
     double re = 0.0, im = 0.0;
@@ -810,10 +858,7 @@ __global__ void k_unpack(const double* __restrict__ alm, const int64_t* __restri
 
 hipError_t launch_unpack(const double* alm, const int64_t* alm_off, const int32_t* lmax, Blocks4<double> U,
                          const GroupDims& g, hipStream_t s) {
-    int64_t most = 0;
-    for (int b = 0; b < 4; ++b) most = std::max<int64_t>(most, int64_t(g.nk[b]) * g.nl[b]);
-    dim3 grid(unsigned((most + 255) / 256), g.nmaps, 4);
-    hipLaunchKernelGGL(k_unpack, grid, dim3(256), 0, s, alm, alm_off, lmax, U, g);
+    hipLaunchKernelGGL(k_unpack, pack_grid(g), dim3(256), 0, s, alm, alm_off, lmax, U, g);
     return hipGetLastError();
 }
 
@@ -883,8 +928,8 @@ __global__ __launch_bounds__(kRingThreads) void k_ring_inverse(Blocks4<const dou
                                                                const int64_t* __restrict__ map_off, GroupDims g) {
     extern __shared__ unsigned char smem_raw[];
     C2<double>* buf = reinterpret_cast<C2<double>*>(smem_raw);
-    const int h = blockIdx.x + 1;
-    const int map = blockIdx.y;
+    int map, h;
+    ring_block(g.nmaps, 2 * g.nside, map, h);
     const int ns = g.nside;
     const int64_t mo = map_off[map];
     {
@@ -904,7 +949,7 @@ __global__ __launch_bounds__(kRingThreads) void k_ring_inverse(Blocks4<const dou
 hipError_t launch_ring_inverse(Blocks4<const double> D, RingTab rt, FftTab<double> ft, double* out,
                                const double* minus_from, const int64_t* map_off, const GroupDims& g,
                                hipStream_t s) {
-    dim3 grid(2 * g.nside, g.nmaps);
+    dim3 grid(g.nmaps, 2 * g.nside);
     size_t shm = size_t(ft.fft_max) * sizeof(C2<double>);
     hipLaunchKernelGGL(k_ring_inverse, grid, dim3(kRingThreads), shm, s, D, rt, ft, out, minus_from, map_off, g);
     return hipGetLastError();
@@ -957,8 +1002,12 @@ template hipError_t launch_ring_forward<float>(const double*, const int64_t*, Ri
                                                Blocks4<float>, const GroupDims&, hipStream_t);
 template hipError_t launch_pole<double>(Blocks4<double>, const GroupDims&, double, double, double, hipStream_t);
 template hipError_t launch_pole<float>(Blocks4<float>, const GroupDims&, double, double, double, hipStream_t);
-template hipError_t launch_gemm<double>(const GemmProblem<double>*, int, int, const double*, double*, hipStream_t);
-template hipError_t launch_gemm<float>(const GemmProblem<float>*, int, int, const float*, float*, hipStream_t);
+template hipError_t launch_gemm<double>(const GemmProblem<double>*, const int32_t*, int, const double*, double*,
+                                       hipStream_t);
+template hipError_t launch_gemm<float>(const GemmProblem<float>*, const int32_t*, int, const float*, float*,
+                                      hipStream_t);
+template std::vector<int32_t> xcd_tile_map<double>(const GemmProblem<double>*, int);
+template std::vector<int32_t> xcd_tile_map<float>(const GemmProblem<float>*, int);
 template int finalize_gemm_problems<double>(GemmProblem<double>*, int);
 template int finalize_gemm_problems<float>(GemmProblem<float>*, int);
 template hipError_t launch_replicate<double>(const double*, int64_t, int64_t, int, int, int, double*, int, int,
