@@ -43,6 +43,7 @@
  *   - Maps: FP64, RING order (rings north to south, points of a ring with
  *     longitude ascending from the ring's first point, eq. healpts), the maps
  *     of a batch back to back: map b starts at sum_{b'<b} 12 nside[b']^2.
+ *     16-byte aligned (rings are read and written as pairs of doubles).
  *   - a_lm: complex128 as interleaved (re, im) doubles, per map packed
  *     m-major for m >= 0: index(l, m) = m (2 lmax + 1 - m) / 2 + l,
  *     0 <= m <= l <= lmax; a_l^{-m} = (-1)^m conj(a_l^m) is implied.  The

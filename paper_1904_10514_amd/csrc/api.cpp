@@ -756,7 +756,7 @@ int hp2sph_analyze(hp2sph_plan_t plan, const double* maps, double* alm, void* wo
     if (int e = check_plan(plan)) return e;
     g_prof = &plan->prof;
     if (!maps || !alm) return fail(HP2SPH_EINVAL, "maps/alm is null");
-    if (!aligned(maps, 8) || !aligned(alm, 16)) return fail(HP2SPH_EINVAL, "maps/alm misaligned");
+    if (!aligned(maps, 16) || !aligned(alm, 16)) return fail(HP2SPH_EINVAL, "maps/alm not 16-byte aligned");
     if (!workspace || !aligned(workspace, kAlign)) return fail(HP2SPH_EWORKSPACE, "workspace null or not 256-byte aligned");
     hipStream_t s = static_cast<hipStream_t>(stream);
     for (auto& gp : plan->groups) {
@@ -779,7 +779,7 @@ int hp2sph_synthesize(hp2sph_plan_t plan, const double* alm, double* maps, void*
     if (int e = check_plan(plan)) return e;
     g_prof = &plan->prof;
     if (!maps || !alm) return fail(HP2SPH_EINVAL, "maps/alm is null");
-    if (!aligned(maps, 8) || !aligned(alm, 16)) return fail(HP2SPH_EINVAL, "maps/alm misaligned");
+    if (!aligned(maps, 16) || !aligned(alm, 16)) return fail(HP2SPH_EINVAL, "maps/alm not 16-byte aligned");
     if (!workspace || !aligned(workspace, kAlign)) return fail(HP2SPH_EWORKSPACE, "workspace null or not 256-byte aligned");
     hipStream_t s = static_cast<hipStream_t>(stream);
     for (auto& gp : plan->groups)

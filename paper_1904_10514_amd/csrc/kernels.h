@@ -22,7 +22,7 @@ namespace hp2sph {
 
 template <class T>
 struct FftTab {
-    const T* twiddle;         // e^{-2 pi i t / fft_max}, t < fft_max / 2 (complex)
+    const T* twiddle;         // e^{-2 pi i t / fft_max}, t < fft_max (complex)
     const T* roots;           // per ring size: e^{-i pi k / n}, k = 0 .. n
     const T* chirp;           // per ring size (Bluestein): w_k = e^{-i pi k^2 / L}
     const T* chirpfft;        // per ring size (Bluestein): FFT_M(conj chirp)

@@ -32,98 +32,178 @@ __device__ __forceinline__ C2<T> ldc(const T* p, int64_t i) { return {p[2 * i], 
 __device__ __forceinline__ int ilog2(int v) { return 31 - __clz(v); }
 __device__ __forceinline__ int bitrev(int v, int lg) { return lg == 0 ? 0 : int(__brev(unsigned(v)) >> (32 - lg)); }
 
-// In-place radix-2 FFT in LDS, e^{-2 pi i jk / M}.  DIT: input in
-// bit-reversed order, output natural.  DIF: input natural, output
-// bit-reversed.  Caller synchronises before (data written) and the routine
-// ends with a barrier.
-template <class T>
-__device__ void lds_fft_dit(C2<T>* buf, int M, const T* tw, int fft_max) {
-    const int nt = blockDim.x;
-    for (int len = 2; len <= M; len <<= 1) {
-        const int half = len >> 1, lh = ilog2(half);
-        const int stride = fft_max / len;
-        for (int b = threadIdx.x; b < (M >> 1); b += nt) {
-            const int grp = b >> lh, pos = b & (half - 1);
-            const int i = grp * len + pos, j = i + half;
-            const C2<T> w = ldc(tw, int64_t(pos) * stride);
-            const C2<T> u = buf[i], v = cmul(w, buf[j]);
-            buf[i] = cadd(u, v);
-            buf[j] = csub(u, v);
+struct alignas(16) D2 {
+    double x, y;
+};
+
+// LDS slot of FFT entry i: one pad slot every 16 entries, so that the
+// strided accesses of the Stockham passes spread over the banks.
+__device__ __forceinline__ int lpad(int i) { return i + (i >> 4); }
+
+// Multiplication by e^{-2 pi i q / 16}, q = 0..7, with the exact forms for
+// q = 0, 2, 4, 6.
+template <class T, int Q>
+__device__ __forceinline__ C2<T> rot16(C2<T> a) {
+    constexpr T c1 = T(0.92387953251128675613), s1 = T(0.38268343236508977173);
+    constexpr T h = T(0.70710678118654752440);
+    if constexpr (Q == 0) return a;
+    else if constexpr (Q == 1) return {c1 * a.x + s1 * a.y, c1 * a.y - s1 * a.x};
+    else if constexpr (Q == 2) return {h * (a.x + a.y), h * (a.y - a.x)};
+    else if constexpr (Q == 3) return {s1 * a.x + c1 * a.y, s1 * a.y - c1 * a.x};
+    else if constexpr (Q == 4) return {a.y, -a.x};
+    else if constexpr (Q == 5) return {c1 * a.y - s1 * a.x, -s1 * a.y - c1 * a.x};
+    else if constexpr (Q == 6) return {h * (a.y - a.x), -h * (a.x + a.y)};
+    else return {s1 * a.y - c1 * a.x, -c1 * a.y - s1 * a.x};
+}
+
+template <int R>
+constexpr int rev_bits(int v) {
+    int r = 0;
+    for (int b = 1; b < R; b <<= 1) {
+        r = (r << 1) | (v & 1);
+        v >>= 1;
+    }
+    return r;
+}
+
+// One butterfly stage (half-length H) of an in-register radix-2 DIT FFT of
+// size R over bit-reversed input; recursion over the positions keeps every
+// twiddle a compile-time constant.
+template <class T, int R, int H, int POS>
+__device__ __forceinline__ void dit_stage_pos(C2<T>* v) {
+    if constexpr (POS < H) {
+#pragma unroll
+        for (int g = 0; g < R; g += 2 * H) {
+            const C2<T> u = v[g + POS];
+            const C2<T> t = rot16<T, POS * (8 / H)>(v[g + POS + H]);
+            v[g + POS] = cadd(u, t);
+            v[g + POS + H] = csub(u, t);
         }
-        __syncthreads();
+        dit_stage_pos<T, R, H, POS + 1>(v);
     }
 }
 
-template <class T>
-__device__ void lds_fft_dif(C2<T>* buf, int M, const T* tw, int fft_max) {
-    const int nt = blockDim.x;
-    for (int len = M; len >= 2; len >>= 1) {
-        const int half = len >> 1, lh = ilog2(half);
-        const int stride = fft_max / len;
-        for (int b = threadIdx.x; b < (M >> 1); b += nt) {
-            const int grp = b >> lh, pos = b & (half - 1);
-            const int i = grp * len + pos, j = i + half;
-            const C2<T> w = ldc(tw, int64_t(pos) * stride);
-            const C2<T> u = buf[i], v = buf[j];
-            buf[i] = cadd(u, v);
-            buf[j] = cmul(csub(u, v), w);
-        }
-        __syncthreads();
+template <class T, int R, int H>
+__device__ __forceinline__ void dit_stages(C2<T>* v) {
+    if constexpr (H < R) {
+        dit_stage_pos<T, R, H, 0>(v);
+        dit_stages<T, R, 2 * H>(v);
     }
+}
+
+// In-register DFT of size R (2, 4, 8 or 16), e^{-2 pi i r s / R}, natural
+// order in and out.
+template <class T, int R>
+__device__ __forceinline__ void dft_regs(C2<T>* v) {
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        const int r = rev_bits<R>(i);
+        if (r > i) {
+            const C2<T> t = v[i];
+            v[i] = v[r];
+            v[r] = t;
+        }
+    }
+    dit_stages<T, R, 1>(v);
+}
+
+// One Stockham pass of radix R over M points with NT threads: group j reads
+// entries j + r M/R (from `load`), multiplies entry r by w^r with
+// w = e^{-2 pi i (j mod Ns) / (Ns R)}, transforms, and stores output r at
+// (j / Ns) Ns R + (j mod Ns) + r Ns of the LDS buffer.  After the last pass
+// the buffer holds the DFT in natural order.  Reads complete (barrier) before
+// any thread writes, so the pass may read the buffer it writes.
+template <class T, int R, int NT, int MAXV, class Load>
+__device__ __forceinline__ void stockham_pass(C2<T>* buf, int M, int lgNs, const T* tw, int fft_max, Load load) {
+    constexpr int NG = MAXV / R;
+    const int G = M / R, Ns = 1 << lgNs;
+    C2<T> v[MAXV];
+#pragma unroll
+    for (int i = 0; i < NG; ++i) {
+        const int j = threadIdx.x + NT * i;
+        if (j < G) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[i * R + r] = load(j + r * G);
+            if (lgNs > 0) {
+                const int st = (fft_max >> lgNs) / R * (j & (Ns - 1));
+#pragma unroll
+                for (int r = 1; r < R; ++r) v[i * R + r] = cmul(v[i * R + r], ldc(tw, int64_t(st) * r));
+            }
+            dft_regs<T, R>(v + i * R);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NG; ++i) {
+        const int j = threadIdx.x + NT * i;
+        if (j < G) {
+            const int base = ((j >> lgNs) << lgNs) * R + (j & (Ns - 1));
+#pragma unroll
+            for (int r = 0; r < R; ++r) buf[lpad(base + r * Ns)] = v[i * R + r];
+        }
+    }
+    __syncthreads();
+}
+
+template <class T, int NT, int MAXV, class Load>
+__device__ __forceinline__ void stockham_dispatch(int bits, C2<T>* buf, int M, int lgNs, const T* tw, int fft_max,
+                                                  Load load) {
+    switch (bits) {
+        case 4: stockham_pass<T, 16, NT, MAXV>(buf, M, lgNs, tw, fft_max, load); break;
+        case 3: stockham_pass<T, 8, NT, MAXV>(buf, M, lgNs, tw, fft_max, load); break;
+        case 2: stockham_pass<T, 4, NT, MAXV>(buf, M, lgNs, tw, fft_max, load); break;
+        default: stockham_pass<T, 2, NT, MAXV>(buf, M, lgNs, tw, fft_max, load); break;
+    }
+}
+
+// Forward DFT of M = 2^e points (2 <= M <= NT * MAXV) in LDS:
+// X_s = sum_q x_q e^{-2 pi i q s / M}.  The first pass takes its input from
+// `load0(q)` (which may read the buffer); on return the buffer holds X in
+// natural order at slots lpad(s).  Radix-16 passes, the remainder last.
+// Table tw: e^{-2 pi i t / fft_max}, t < fft_max, M divides fft_max.
+template <class T, int NT, int MAXV, class Load0>
+__device__ __forceinline__ void fft_lds(C2<T>* buf, int M, const T* tw, int fft_max, Load0 load0) {
+    const int e = ilog2(M);
+    const int P = (e + 3) >> 2;
+    const int last = e - 4 * (P - 1);
+    auto lds_load = [buf](int i) { return buf[lpad(i)]; };
+    // straight-line pass sequence (at most 4 passes for M <= 2^16)
+    stockham_dispatch<T, NT, MAXV>(P == 1 ? last : 4, buf, M, 0, tw, fft_max, load0);
+    if (P > 1) stockham_dispatch<T, NT, MAXV>(P == 2 ? last : 4, buf, M, 4, tw, fft_max, lds_load);
+    if (P > 2) stockham_dispatch<T, NT, MAXV>(P == 3 ? last : 4, buf, M, 8, tw, fft_max, lds_load);
+    if (P > 3) stockham_dispatch<T, NT, MAXV>(last, buf, M, 12, tw, fft_max, lds_load);
 }
 
 // Forward DFT of length L (a power of two, or any L through Bluestein's
-// chirp-z with M = chirpm) of the complex sequence produced by `src(q)`,
-// q < L.  On return Z(k) gives the k-th output (valid until the next
-// barrier that rewrites buf).
+// chirp-z with M = M_blue points) of the sequence src(q), q < L.  On return
+// Z(k), k < L, gives output k (valid until the buffer is rewritten).
 template <class T>
-struct DftResult {
-    C2<T>* buf;
-    const T* w;      // chirp (Bluestein) or null
-    int M, lg;
-    bool blue;
+struct DftOut {
+    const C2<T>* buf;
+    const T* chirp;   // null for a direct transform
     T invM;
     __device__ C2<T> Z(int k) const {
-        if (!blue) return buf[k];
-        C2<T> c = cconj(buf[bitrev(k, lg)]);
-        c = cscale(c, invM);
-        return cmul(ldc(w, k), c);
+        const C2<T> b = buf[lpad(k)];
+        if (!chirp) return b;
+        return cmul(ldc(chirp, k), cscale(cconj(b), invM));
     }
 };
 
-template <class T, class Src>
-__device__ DftResult<T> lds_dft(C2<T>* buf, int L, int M_blue, const T* chirp, const T* chirpfft,
-                                const T* tw, int fft_max, Src src) {
-    DftResult<T> r;
-    r.buf = buf;
+template <class T, int NT, int MAXV, class Src>
+__device__ __forceinline__ DftOut<T> ring_dft(C2<T>* buf, int L, int M_blue, const T* chirp, const T* chirpfft, const T* tw,
+                              int fft_max, Src src) {
     if (M_blue == 0) {
-        r.blue = false;
-        r.M = L;
-        r.lg = ilog2(L);
-        r.w = nullptr;
-        r.invM = T(1);
-        for (int q = threadIdx.x; q < L; q += blockDim.x) buf[bitrev(q, r.lg)] = src(q);
-        __syncthreads();
-        lds_fft_dit(buf, L, tw, fft_max);
-        return r;
+        fft_lds<T, NT, MAXV>(buf, L, tw, fft_max, src);
+        return {buf, nullptr, T(1)};
     }
-    r.blue = true;
-    r.M = M_blue;
-    r.lg = ilog2(M_blue);
-    r.w = chirp;
-    r.invM = T(1) / T(M_blue);
-    for (int q = threadIdx.x; q < M_blue; q += blockDim.x) {
-        C2<T> v = {T(0), T(0)};
-        if (q < L) v = cmul(src(q), ldc(chirp, q));
-        buf[bitrev(q, r.lg)] = v;
-    }
-    __syncthreads();
-    lds_fft_dit(buf, M_blue, tw, fft_max);
-    // pointwise product with the chirp spectrum, conjugated for the inverse
-    for (int k = threadIdx.x; k < M_blue; k += blockDim.x) buf[k] = cconj(cmul(buf[k], ldc(chirpfft, k)));
-    __syncthreads();
-    lds_fft_dif(buf, M_blue, tw, fft_max);
-    return r;
+    // y_q = src(q) w_q (zero padded to M), Y = FFT(y), then the inverse FFT of
+    // Y . FFT(conj w) through conj(FFT(conj(.))).
+    fft_lds<T, NT, MAXV>(buf, M_blue, tw, fft_max, [&](int q) -> C2<T> {
+        return q < L ? cmul(src(q), ldc(chirp, q)) : C2<T>{T(0), T(0)};
+    });
+    fft_lds<T, NT, MAXV>(buf, M_blue, tw, fft_max,
+                         [&](int q) -> C2<T> { return cconj(cmul(buf[lpad(q)], ldc(chirpfft, q))); });
+    return {buf, chirp, T(1) / T(M_blue)};
 }
 
 // ---------------------------------------------------------------------------
@@ -146,23 +226,32 @@ __device__ __forceinline__ void ring_block(int nmaps, int npairs, int& map, int&
     }
 }
 
-constexpr int kRingThreads = 512;
-constexpr int kRingKPT = 9;   // (HP2SPH_MAX_NSIDE * 2 + 1) / kRingThreads, rounded up
+// Ring kernels run NT = fft_max / 16 threads (256 up to nside 1024, 512 at
+// nside 2048), so that every FFT of up to fft_max points keeps at most 16
+// complex values per thread.
+constexpr int kRingMaxV = 16;
+constexpr int kRingKPT = 9;   // ceil((2 nside + 1) / NT) at the largest nside of each NT
 
-template <class T>
-__device__ void ring_spectrum(const double* x, int n, bool shifted, int p, FftTab<T> ft, C2<T>* buf,
+__host__ __device__ constexpr int ring_threads(int fft_max) { return fft_max <= 4096 ? 256 : 512; }
+
+template <class T, int NT>
+__device__ __forceinline__ void ring_spectrum(const double* x, int n, bool shifted, int p, FftTab<T> ft, C2<T>* buf,
                               C2<T> (&D)[kRingKPT]) {
     const int L = n >> 1, j = n >> 2;
     const int Mb = ft.chirpm[j];
     const T* chirp = ft.chirp + 2 * ft.chirpoff[j];
     const T* chirpfft = ft.chirpfft + 2 * ft.chirpfftoff[j];
     const T* roots = ft.roots + 2 * ft.rootoff[j];
-    auto src = [&](int q) -> C2<T> { return {T(x[2 * q]), T(x[2 * q + 1])}; };
-    DftResult<T> R = lds_dft<T>(buf, L, Mb, chirp, chirpfft, ft.twiddle, ft.fft_max, src);
+    // z_q = x_{2q} + i x_{2q+1}: the real ring as L complex points
+    auto src = [x](int q) -> C2<T> {
+        const D2 v = *reinterpret_cast<const D2*>(x + 2 * q);
+        return {T(v.x), T(v.y)};
+    };
+    const DftOut<T> R = ring_dft<T, NT, kRingMaxV>(buf, L, Mb, chirp, chirpfft, ft.twiddle, ft.fft_max, src);
     const T invn = T(1) / T(n);
 #pragma unroll
     for (int i = 0; i < kRingKPT; ++i) {
-        const int k = threadIdx.x + i * kRingThreads;
+        const int k = threadIdx.x + i * NT;
         C2<T> d = {T(0), T(0)};
         if (k <= p) {
             if (k < L) {
@@ -182,13 +271,13 @@ __device__ void ring_spectrum(const double* x, int n, bool shifted, int p, FftTa
         }
         D[i] = d;
     }
-    __syncthreads();
+    // The next transform's first pass synchronises before it writes the buffer.
 }
 
-template <class T>
-__global__ __launch_bounds__(kRingThreads) void k_ring_forward(const double* __restrict__ maps,
-                                                               const int64_t* __restrict__ map_off, RingTab rt,
-                                                               FftTab<T> ft, Blocks4<T> D, GroupDims g) {
+template <class T, int NT>
+__global__ __launch_bounds__(NT) void k_ring_forward(const double* __restrict__ maps,
+                                                     const int64_t* __restrict__ map_off, RingTab rt, FftTab<T> ft,
+                                                     Blocks4<T> D, GroupDims g) {
     extern __shared__ unsigned char smem_raw[];
     C2<T>* buf = reinterpret_cast<C2<T>*>(smem_raw);
     int b, h;
@@ -198,16 +287,16 @@ __global__ __launch_bounds__(kRingThreads) void k_ring_forward(const double* __r
     C2<T> DN[kRingKPT], DS[kRingKPT];
     {
         const int r0 = h - 1;
-        ring_spectrum<T>(m + rt.start[r0], rt.n[r0], rt.shifted[r0] != 0, p, ft, buf, DN);
+        ring_spectrum<T, NT>(m + rt.start[r0], rt.n[r0], rt.shifted[r0] != 0, p, ft, buf, DN);
     }
     const bool equator = (h == 2 * ns);
     if (!equator) {
         const int r0 = 4 * ns - h - 1;
-        ring_spectrum<T>(m + rt.start[r0], rt.n[r0], rt.shifted[r0] != 0, p, ft, buf, DS);
+        ring_spectrum<T, NT>(m + rt.start[r0], rt.n[r0], rt.shifted[r0] != 0, p, ft, buf, DS);
     }
 #pragma unroll
     for (int i = 0; i < kRingKPT; ++i) {
-        const int k = threadIdx.x + i * kRingThreads;
+        const int k = threadIdx.x + i * NT;
         if (k > p) continue;
         C2<T> dp, dm;
         if (equator) {
@@ -229,12 +318,20 @@ __global__ __launch_bounds__(kRingThreads) void k_ring_forward(const double* __r
     }
 }
 
+static size_t ring_lds_bytes(int fft_max, size_t elem) {
+    const int slots = fft_max > 256 ? fft_max : 256;
+    return size_t(slots + slots / 16) * elem;
+}
+
 template <class T>
 hipError_t launch_ring_forward(const double* maps, const int64_t* map_off, RingTab rt, FftTab<T> ft, Blocks4<T> D,
                                const GroupDims& g, hipStream_t s) {
     dim3 grid(g.nmaps, 2 * g.nside);
-    size_t shm = size_t(ft.fft_max) * sizeof(C2<T>);
-    hipLaunchKernelGGL(k_ring_forward<T>, grid, dim3(kRingThreads), shm, s, maps, map_off, rt, ft, D, g);
+    const size_t shm = ring_lds_bytes(ft.fft_max, sizeof(C2<T>));
+    if (ring_threads(ft.fft_max) == 256)
+        hipLaunchKernelGGL((k_ring_forward<T, 256>), grid, dim3(256), shm, s, maps, map_off, rt, ft, D, g);
+    else
+        hipLaunchKernelGGL((k_ring_forward<T, 512>), grid, dim3(512), shm, s, maps, map_off, rt, ft, D, g);
     return hipGetLastError();
 }
 
@@ -874,33 +971,57 @@ __device__ __forceinline__ C2<double> eplus(const double* roots, int64_t k, int 
     return {-r.x, r.y};   // -conj(r)
 }
 
-__device__ void ring_synth(const Blocks4<const double>& D, int h, int sgn, int n, bool shifted, int p,
+// One ring of the synthesis: values x_q, q < n, of the real trigonometric
+// polynomial with coefficients D_k = D+_k + sgn D-_k, k = 0..p (and the
+// conjugates at -k), evaluated at lambda_q = phi0 + 2 pi q / n.  Modes |k| >= n
+// alias onto k mod n.  Written to out (minus minus_from[q] - x_q if given).
+template <int NT>
+__device__ __forceinline__ void ring_synth(const Blocks4<const double>& D, int h, int sgn, int n, bool shifted, int p,
                            const GroupDims& g, int map, FftTab<double> ft, C2<double>* buf, double* out,
                            const double* minus_from) {
     const int L = n >> 1, j = n >> 2;
     const int Mb = ft.chirpm[j];
     const double* roots = ft.roots + 2 * ft.rootoff[j];
-    // G_k = D_k e^{i k phi0}, D_k = D+_k + sgn D-_k
+    // G_k = D_k e^{i k phi0}
     auto Gk = [&](int k) -> C2<double> {
         const int kpar = k & 1, kk = k >> 1;
         const int64_t o = int64_t(h) * g.N[kpar] + int64_t(map) * g.cm[kpar] + int64_t(kk) * g.ck[kpar];
-        const double* bp = D.p[2 * kpar];
-        const double* bm = D.p[2 * kpar + 1];
-        C2<double> d = {bp[o] + sgn * bm[o], bp[o + 1] + sgn * bm[o + 1]};
+        const D2 vp = *reinterpret_cast<const D2*>(D.p[2 * kpar] + o);
+        const D2 vm = *reinterpret_cast<const D2*>(D.p[2 * kpar + 1] + o);
+        C2<double> d = {vp.x + sgn * vm.x, vp.y + sgn * vm.y};
         if (shifted) d = cmul(d, eplus(roots, k, n));
         return d;
     };
-    // H_t = sum_{k = t mod n} G_k + conj(sum_{k>0, k = -t mod n} G_k)
-    auto Ht = [&](int t) -> C2<double> {
-        C2<double> a = {0.0, 0.0}, bsum = {0.0, 0.0};
-        for (int k = t; k <= p; k += n) a = cadd(a, Gk(k));
-        for (int k = (t == 0 ? n : n - t); k <= p; k += n) bsum = cadd(bsum, Gk(k));
-        return cadd(a, cconj(bsum));
+    // H_t = sum_{k = t mod n} G_k + conj(sum_{k > 0, k = -t mod n} G_k),
+    // t = 0..L, summed over the aliases a = s, s + c, s + 2c, ... of k = t + a n
+    // and k = (n - t) + a n.
+    auto Hpart = [&](int t, int s, int c) -> C2<double> {
+        C2<double> acc = {0.0, 0.0}, bsum = {0.0, 0.0};
+        for (int k = t + s * n; k <= p; k += c * n) acc = cadd(acc, Gk(k));
+        for (int k = (t == 0 ? n : n - t) + s * n; k <= p; k += c * n) bsum = cadd(bsum, Gk(k));
+        return cadd(acc, cconj(bsum));
     };
-    // Z'_t = (H_t + conj H_{L-t}) + i (H_t - conj H_{L-t}) e^{2 pi i t / n};
-    // the inverse DFT of length L is conj(DFT(conj Z')).
+    const int T1 = L + 1;
+    const int c = NT / T1;
+    if (c > 1) {
+        // c threads per t, partial sums in a fixed order
+        C2<double> part = {0.0, 0.0};
+        if (int(threadIdx.x) < c * T1) part = Hpart(int(threadIdx.x) % T1, int(threadIdx.x) / T1, c);
+        buf[lpad(threadIdx.x)] = part;
+        __syncthreads();
+        C2<double> hsum = {0.0, 0.0};
+        if (int(threadIdx.x) < T1)
+            for (int s = 0; s < c; ++s) hsum = cadd(hsum, buf[lpad(s * T1 + threadIdx.x)]);
+        __syncthreads();
+        if (int(threadIdx.x) < T1) buf[lpad(threadIdx.x)] = hsum;
+    } else {
+        for (int t = threadIdx.x; t < T1; t += NT) buf[lpad(t)] = Hpart(t, 0, 1);
+    }
+    __syncthreads();
+    // Z'_t = (H_t + conj H_{L-t}) + i (H_t - conj H_{L-t}) e^{2 pi i t / n}, t < L;
+    // x_{2q} + i x_{2q+1} = sum_t Z'_t e^{2 pi i t q / L}, computed as conj(DFT(conj Z')).
     auto src = [&](int t) -> C2<double> {
-        const C2<double> ht = Ht(t), hl = Ht(L - t);
+        const C2<double> ht = buf[lpad(t)], hl = buf[lpad(L - t)];
         const C2<double> e = cadd(ht, cconj(hl));
         const C2<double> o = cmul(csub(ht, cconj(hl)), cconj(ldc(roots, 2 * t)));
         const C2<double> z = {e.x - o.y, e.y + o.x};
@@ -908,24 +1029,24 @@ __device__ void ring_synth(const Blocks4<const double>& D, int h, int sgn, int n
     };
     const double* chirp = ft.chirp + 2 * ft.chirpoff[j];
     const double* chirpfft = ft.chirpfft + 2 * ft.chirpfftoff[j];
-    DftResult<double> R = lds_dft<double>(buf, L, Mb, chirp, chirpfft, ft.twiddle, ft.fft_max, src);
-    for (int q = threadIdx.x; q < L; q += blockDim.x) {
+    const DftOut<double> R =
+        ring_dft<double, NT, kRingMaxV>(buf, L, Mb, chirp, chirpfft, ft.twiddle, ft.fft_max, src);
+    for (int q = threadIdx.x; q < L; q += NT) {
         const C2<double> z = cconj(R.Z(q));
-        double v0 = z.x, v1 = z.y;
+        D2 v = {z.x, z.y};
         if (minus_from) {
-            v0 = minus_from[2 * q] - v0;
-            v1 = minus_from[2 * q + 1] - v1;
+            const D2 f = *reinterpret_cast<const D2*>(minus_from + 2 * q);
+            v = {f.x - v.x, f.y - v.y};
         }
-        out[2 * q] = v0;
-        out[2 * q + 1] = v1;
+        *reinterpret_cast<D2*>(out + 2 * q) = v;
     }
     __syncthreads();
 }
 
-__global__ __launch_bounds__(kRingThreads) void k_ring_inverse(Blocks4<const double> D, RingTab rt,
-                                                               FftTab<double> ft, double* out,
-                                                               const double* minus_from,
-                                                               const int64_t* __restrict__ map_off, GroupDims g) {
+template <int NT>
+__global__ __launch_bounds__(NT) void k_ring_inverse(Blocks4<const double> D, RingTab rt, FftTab<double> ft,
+                                                     double* out, const double* minus_from,
+                                                     const int64_t* __restrict__ map_off, GroupDims g) {
     extern __shared__ unsigned char smem_raw[];
     C2<double>* buf = reinterpret_cast<C2<double>*>(smem_raw);
     int map, h;
@@ -935,14 +1056,14 @@ __global__ __launch_bounds__(kRingThreads) void k_ring_inverse(Blocks4<const dou
     {
         const int r0 = h - 1;
         const int64_t st = mo + rt.start[r0];
-        ring_synth(D, h, +1, rt.n[r0], rt.shifted[r0] != 0, g.p, g, map, ft, buf, out + st,
-                   minus_from ? minus_from + st : nullptr);
+        ring_synth<NT>(D, h, +1, rt.n[r0], rt.shifted[r0] != 0, g.p, g, map, ft, buf, out + st,
+                       minus_from ? minus_from + st : nullptr);
     }
     if (h < 2 * ns) {
         const int r0 = 4 * ns - h - 1;
         const int64_t st = mo + rt.start[r0];
-        ring_synth(D, h, -1, rt.n[r0], rt.shifted[r0] != 0, g.p, g, map, ft, buf, out + st,
-                   minus_from ? minus_from + st : nullptr);
+        ring_synth<NT>(D, h, -1, rt.n[r0], rt.shifted[r0] != 0, g.p, g, map, ft, buf, out + st,
+                       minus_from ? minus_from + st : nullptr);
     }
 }
 
@@ -950,8 +1071,11 @@ hipError_t launch_ring_inverse(Blocks4<const double> D, RingTab rt, FftTab<doubl
                                const double* minus_from, const int64_t* map_off, const GroupDims& g,
                                hipStream_t s) {
     dim3 grid(g.nmaps, 2 * g.nside);
-    size_t shm = size_t(ft.fft_max) * sizeof(C2<double>);
-    hipLaunchKernelGGL(k_ring_inverse, grid, dim3(kRingThreads), shm, s, D, rt, ft, out, minus_from, map_off, g);
+    const size_t shm = ring_lds_bytes(ft.fft_max, sizeof(C2<double>));
+    if (ring_threads(ft.fft_max) == 256)
+        hipLaunchKernelGGL(k_ring_inverse<256>, grid, dim3(256), shm, s, D, rt, ft, out, minus_from, map_off, g);
+    else
+        hipLaunchKernelGGL(k_ring_inverse<512>, grid, dim3(512), shm, s, D, rt, ft, out, minus_from, map_off, g);
     return hipGetLastError();
 }
 
@@ -985,13 +1109,18 @@ hipError_t launch_cl(const double* alm, const int64_t* alm_off, const int32_t* l
 
 hipError_t configure_kernels() {
     const int bytes = 160 * 1024;
-    hipError_t e;
-    if ((e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_ring_forward<double>),
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, bytes)) != hipSuccess) return e;
-    if ((e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_ring_forward<float>),
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, bytes)) != hipSuccess) return e;
-    if ((e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_ring_inverse),
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, bytes)) != hipSuccess) return e;
+    const void* fns[] = {
+        reinterpret_cast<const void*>(&k_ring_forward<double, 256>),
+        reinterpret_cast<const void*>(&k_ring_forward<double, 512>),
+        reinterpret_cast<const void*>(&k_ring_forward<float, 256>),
+        reinterpret_cast<const void*>(&k_ring_forward<float, 512>),
+        reinterpret_cast<const void*>(&k_ring_inverse<256>),
+        reinterpret_cast<const void*>(&k_ring_inverse<512>),
+    };
+    for (const void* f : fns) {
+        const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+        if (e != hipSuccess) return e;
+    }
     return hipSuccess;
 }
 

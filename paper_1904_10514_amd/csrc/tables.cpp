@@ -322,8 +322,8 @@ void build_tables(int nside, HostTables& t, bool with_fft) {
 
     // FFT tables.
     t.fft_max = 4 * nside;
-    t.twiddle.assign(size_t(t.fft_max), 0.0);
-    for (int i = 0; i < t.fft_max / 2; ++i) {
+    t.twiddle.assign(size_t(2 * t.fft_max), 0.0);
+    for (int i = 0; i < t.fft_max; ++i) {
         const double ang = -2.0 * kPi * double(i) / double(t.fft_max);
         t.twiddle[2 * i] = std::cos(ang);
         t.twiddle[2 * i + 1] = std::sin(ang);

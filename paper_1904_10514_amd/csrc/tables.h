@@ -50,7 +50,7 @@ struct HostTables {
     std::vector<double> givens[4];
     // FFT tables
     int fft_max = 0;                    // largest power-of-two FFT length
-    std::vector<double> twiddle;        // e^{-2 pi i t / fft_max}, t < fft_max/2, (re, im)
+    std::vector<double> twiddle;        // e^{-2 pi i t / fft_max}, t < fft_max, (re, im)
     // per ring size n = 4j (j = 1 .. nside): offsets into the tables below
     std::vector<int64_t> rootoff;       // e^{-i pi k / n}, k = 0 .. n (n+1 complex)
     std::vector<double> roots;
