@@ -333,6 +333,9 @@ int first_row(int m) { return m == 0 ? 0 : (m + 1) / 2; }
 
 template <class T>
 void upload_list(Group& G, std::vector<GemmProblem<T>>& v, GemmList<T>& out) {
+    // the GEMM kernel reads B as aligned (re, im) pairs
+    for (const auto& P : v)
+        if ((P.boff | P.ldb | P.bps | P.N) & 1) throw std::runtime_error("GEMM problem with unpaired B columns");
     // longest problems first, then tile ranges in that order
     std::stable_sort(v.begin(), v.end(), [](const GemmProblem<T>& x, const GemmProblem<T>& y) {
         return int64_t(x.M) * x.K > int64_t(y.M) * y.K;
@@ -405,7 +408,7 @@ OrderLayout order_layout(const Group& G, int b) {
         const int h0 = first_row(2 * kk + kpar);
         L.h0.push_back(h0);
         L.ana_off.push_back(L.ana_size);
-        L.ana_size += int64_t(K - h0) * (d.nl[b] - kk);
+        L.ana_size += int64_t(K - h0) * order_table_lda(d.nl[b] - kk);
         L.syn_off.push_back(L.syn_size);
         L.syn_size += int64_t(d.nl[b] - kk) * (2 * G.nside);
     }
@@ -455,6 +458,7 @@ void build_order_tables(hp2sph_plan_t plan, Group& G) {
         auto ana64 = std::make_unique<DevBuf>();
         ana64->bytes = size_t(L.ana_size) * 8;
         HIPTHROW(hipMalloc(&ana64->p, ana64->bytes));
+        HIPTHROW(hipMemset(ana64->p, 0, ana64->bytes));   // row padding reads as zero
         std::unique_ptr<DevBuf> syn64;
         if (want_syn) {
             syn64 = std::make_unique<DevBuf>();
@@ -514,7 +518,7 @@ void build_order_tables(hp2sph_plan_t plan, Group& G) {
             P.N = 2 * d.nmaps;
             // mode-major layout: mode k' of every map is one contiguous run of 2 nmaps
             const int64_t kcol = int64_t(kk) * 2 * d.nmaps;
-            P.lda = P.M;
+            P.lda = order_table_lda(P.M);
             P.ldb = d.N[kpar];
             P.bps = 2;
             P.ldc = d.N[kpar];

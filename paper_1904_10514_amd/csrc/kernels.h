@@ -73,6 +73,10 @@ struct GemmProblem {
     int tiles_n, tile_begin;  // set by finalize_gemm_problems
 };
 
+// Row stride of a per-order analysis table with M columns: padded to a
+// multiple of 4 elements so that its rows can be read as 16-byte vectors.
+__host__ __device__ inline int order_table_lda(int M) { return (M + 3) & ~3; }
+
 // Assign tile ranges (in list order) and return the number of tiles.
 template <class T>
 int finalize_gemm_problems(GemmProblem<T>* p, int n);

@@ -10,7 +10,7 @@ namespace hp2sph {
 // ---------------------------------------------------------------------------
 
 template <class T>
-struct C2 {
+struct alignas(2 * sizeof(T)) C2 {
     T x, y;
 };
 
@@ -399,18 +399,36 @@ struct MfmaAcc<float> {
     static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
 };
 
-constexpr int GBM = 128, GBN = 128, GBK = 16, GPAD = 4;
+constexpr int GBM = 128, GBN = 128, GBK = 16;
+// Row pad of the LDS tiles: a row stride of GBM + 16 elements puts the four
+// k rows that one MFMA operand load touches on disjoint bank ranges.
+constexpr int GPAD = 16;
 
+// 16-byte vector of T (4 floats / 2 doubles) and the 2-element pair (re, im).
+template <class T>
+struct alignas(16) V16 {
+    T v[16 / sizeof(T)];
+};
+template <class T>
+struct alignas(2 * sizeof(T)) V2 {
+    T v[2];
+};
+
+// C[m][n] = sum_k A[k][m] B[k][n] for a list of problems; one 128 x 128 tile
+// of one problem per workgroup (4 waves of 64 x 64 each), k in steps of 16
+// through double-buffered LDS tiles, the next step's global loads in flight
+// while the current one is multiplied.  B and C columns come in (re, im)
+// pairs: column n lives at (n >> 1) * pair_stride + (n & 1).
 template <class T>
 __global__ __launch_bounds__(256) void k_gemm(const GemmProblem<T>* __restrict__ probs,
                                               const int32_t* __restrict__ tmap, const T* __restrict__ Bbase,
                                               T* __restrict__ Cbase) {
-    __shared__ T As[GBK][GBM + GPAD];
-    __shared__ T Bs[GBK][GBN + GPAD];
+    __shared__ T As[2][GBK][GBM + GPAD];
+    __shared__ T Bs[2][GBK][GBN + GPAD];
     const int pi = tmap[2 * blockIdx.x];
     if (pi < 0) return;
     const GemmProblem<T> P = probs[pi];
-    int tile = tmap[2 * blockIdx.x + 1];
+    const int tile = tmap[2 * blockIdx.x + 1];
     const int tm = tile / P.tiles_n, tn = tile % P.tiles_n;
     const int m0 = tm * GBM, n0 = tn * GBN;
     const T* B = Bbase + P.boff;
@@ -424,40 +442,77 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmProblem<T>* __restrict__
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = typename Acc::V{0, 0, 0, 0};
 
-    const int lr = tid >> 4;          // 0..15: k row of the tile this thread loads
-    const int lc = (tid & 15) * 8;    // 8 consecutive columns
+    // Each thread stages 8 consecutive elements of one k row of each tile.
+    constexpr int VE = 16 / sizeof(T);   // elements per 16-byte vector
+    const int lr = tid >> 4;             // 0..15
+    const int lc = (tid & 15) * 8;       // 0..120
+    // A rows are read as 16-byte vectors when the row stride and base allow it
+    const bool avec = (P.lda % VE) == 0 && (reinterpret_cast<uintptr_t>(P.A) % 16) == 0;
     T ra[8], rb[8];
     auto gload = [&](int k0) {
         const int k = k0 + lr;
+        const bool krow = k < P.K;
+        const T* arow = P.A + int64_t(k) * P.lda;
+        if (avec) {
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const int mm = m0 + lc + e, nn = n0 + lc + e;
-            ra[e] = (k < P.K && mm < P.M) ? P.A[int64_t(k) * P.lda + mm] : T(0);
-            rb[e] = (k < P.K && nn < P.N) ? B[int64_t(k) * P.ldb + int64_t(nn >> 1) * P.bps + (nn & 1)] : T(0);
+            for (int e = 0; e < 8; e += VE) {
+                const int mm = m0 + lc + e;
+                V16<T> v{};
+                if (krow && mm < P.lda) v = *reinterpret_cast<const V16<T>*>(arow + mm);
+#pragma unroll
+                for (int q = 0; q < VE; ++q) ra[e + q] = v.v[q];
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int mm = m0 + lc + e;
+                ra[e] = (krow && mm < P.M) ? arow[mm] : T(0);
+            }
+        }
+        const T* brow = B + int64_t(k) * P.ldb;
+#pragma unroll
+        for (int e = 0; e < 8; e += 2) {
+            const int nn = n0 + lc + e;
+            V2<T> v{};
+            if (krow && nn < P.N) v = *reinterpret_cast<const V2<T>*>(brow + int64_t(nn >> 1) * P.bps);
+            rb[e] = v.v[0];
+            rb[e + 1] = v.v[1];
         }
     };
-    gload(0);
-    for (int k0 = 0; k0 < P.K; k0 += GBK) {
+    auto lstore = [&](int buf) {
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            As[lr][lc + e] = ra[e];
-            Bs[lr][lc + e] = rb[e];
+        for (int e = 0; e < 8; e += VE) {
+            V16<T> va, vb;
+#pragma unroll
+            for (int q = 0; q < VE; ++q) {
+                va.v[q] = ra[e + q];
+                vb.v[q] = rb[e + q];
+            }
+            *reinterpret_cast<V16<T>*>(&As[buf][lr][lc + e]) = va;
+            *reinterpret_cast<V16<T>*>(&Bs[buf][lr][lc + e]) = vb;
         }
-        __syncthreads();
-        if (k0 + GBK < P.K) gload(k0 + GBK);
+    };
+    const int nk = (P.K + GBK - 1) / GBK;
+    gload(0);
+    lstore(0);
+    __syncthreads();
+    for (int kt = 0; kt < nk; ++kt) {
+        const int cur = kt & 1;
+        if (kt + 1 < nk) gload((kt + 1) * GBK);
 #pragma unroll
         for (int kk = 0; kk < GBK / 4; ++kk) {
             const int kr = kk * 4 + (lane >> 4);
             T a[4], b[4];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) a[i] = As[kr][wm * 64 + i * 16 + (lane & 15)];
+            for (int i = 0; i < 4; ++i) a[i] = As[cur][kr][wm * 64 + i * 16 + (lane & 15)];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) b[j] = Bs[kr][wn * 64 + j * 16 + (lane & 15)];
+            for (int j = 0; j < 4; ++j) b[j] = Bs[cur][kr][wn * 64 + j * 16 + (lane & 15)];
 #pragma unroll
             for (int i = 0; i < 4; ++i)
 #pragma unroll
                 for (int j = 0; j < 4; ++j) acc[i][j] = Acc::mma(a[i], b[j], acc[i][j]);
         }
+        if (kt + 1 < nk) lstore(cur ^ 1);
         __syncthreads();
     }
 #pragma unroll
@@ -568,7 +623,7 @@ __global__ void k_scatter_tables(const T* __restrict__ Uv, int nl, int nk, int n
     } else {
         const int h0 = h0v[kk];
         if (h < h0) return;
-        tab[off[kk] + int64_t(h - h0) * M + (lp - kk)] = Uv[i];
+        tab[off[kk] + int64_t(h - h0) * order_table_lda(M) + (lp - kk)] = Uv[i];
     }
 }
 
