@@ -9,8 +9,9 @@ Inputs are resident in HBM before the timed region.
 
 One step = one pass of the whole analysis path over the batch: the per-ring
 transforms, pole values, colatitude fit, Givens sweeps and packing of a_lm
-(for the FP32+refinement mode: FP32 analysis, FP64 synthesis and residual,
-FP32 analysis of the residual, FP64 accumulation), then C_l.  The headline
+(for the FP32+refinement mode: FP64 ring transforms, FP32 colatitude fit and
+Legendre conversion, FP64 synthesis coefficients, the residual in ring-Fourier
+space, FP32 analysis of the residual, FP64 accumulation), then C_l.  The headline
 value is maps/s of batched FP32+refinement; plain FP64 is timed beside it.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
@@ -83,10 +84,15 @@ def stage_work(stage, nside, nmaps, tsize, strategy="staged"):
         return "flop", sum(2 * nl[b] * K * N[b >> 1] for b in range(4))
     if stage in ("sweep_analysis", "sweep_synthesis"):
         return "flop", 6 * sweep_rotations(nside, nmaps)
+    rows = 2 * nside * (N[0] + N[1]) * 2   # values of Dsym rows 1..2 nside, both D+ and D-
     if stage == "ring_forward":
-        return "byte", npix * 8 + 2 * nside * (N[0] + N[1]) * 2 * tsize
-    if stage == "ring_inverse_residual":
-        return "byte", 2 * nside * (N[0] + N[1]) * 2 * 8 + 2 * npix * 8
+        return "byte", npix * 8 + rows * tsize
+    if stage == "ring_forward_dual":
+        return "byte", npix * 8 + rows * (8 + 4)
+    if stage == "ring_inverse":
+        return "byte", rows * 8 + npix * 8
+    if stage == "residual_fold":
+        return "byte", rows * (8 + 8 + 4)
     if stage == "pack":
         return "byte", sum(nl[b] * N[b >> 1] for b in range(4)) * tsize + (p + 1) * (p + 2) // 2 * 16 * nmaps
     if stage == "unpack":
@@ -105,14 +111,19 @@ def stage_bound(stage):
 
 
 def stage_dtype(stage, mode):
-    if mode == "f64" or stage in ("sweep_synthesis", "gemm_synthesis", "ring_inverse_residual", "unpack", "cl"):
+    if mode in ("f64", "f32_refine") and stage == "ring_forward":
+        return "f64"
+    if mode == "f64" or stage in ("sweep_synthesis", "gemm_synthesis", "ring_inverse", "unpack", "cl",
+                                  "residual_fold"):
         return "f64"
     return "f32"
 
 
 def roofline(stage, mode, nside, nmaps, ms_total, launches, strategy="staged"):
     dt = stage_dtype(stage, mode)
-    kind, amount = stage_work(stage, nside, nmaps, 4 if dt == "f32" else 8, strategy)
+    # the refinement's forward ring transform writes FP64 and FP32 rows
+    work_stage = "ring_forward_dual" if (stage == "ring_forward" and mode == "f32_refine") else stage
+    kind, amount = stage_work(work_stage, nside, nmaps, 4 if dt == "f32" else 8, strategy)
     avg_s = ms_total / launches / 1e3
     bound = stage_bound(stage)
     if bound == "hbm":

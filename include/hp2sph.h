@@ -25,11 +25,16 @@
  *
  * Precision modes:
  *   HP2SPH_F64         every stage in FP64.
- *   HP2SPH_F32_REFINE  the analysis stages run in FP32 (FP32 arithmetic and
- *                      accumulation, FP64-built tables rounded once); then one
- *                      step of eq. (uzawa) (Sec. 2.2) with A := HP2SPH:
- *                      a0 = A32 f, r = f - S64 a0 (exact synthesis and the
- *                      residual map in FP64), a1 = a0 + A32 r (FP64 add).
+ *   HP2SPH_F32_REFINE  the colatitude fit and Legendre conversion run in FP32
+ *                      (FP32 arithmetic and accumulation, FP64-built tables
+ *                      rounded once); then one step of eq. (uzawa) (Sec. 2.2)
+ *                      with A := HP2SPH: a0 = A32 f, r = f - S64 a0,
+ *                      a1 = a0 + A32 r (FP64 add).  The ring transforms of f
+ *                      and the residual are FP64: the residual is formed in
+ *                      ring-Fourier space, Ring(f) - Ring(S64 a0), where
+ *                      Ring(S64 a0) is evaluated exactly from the synthesis
+ *                      coefficients by folding aliased modes, and rounded to
+ *                      FP32 for the second FP32 pass.
  *   HP2SPH_F32         one FP32 analysis, no refinement (diagnostic).
  *
  * Conventions of every call:
@@ -176,10 +181,11 @@ const char* hp2sph_last_error(void);
  * number of launches (arrays of length nstages, at most HP2SPH_NSTAGES).
  * Stages: 0 ring transform (S1), 1 pole values (S2), 2 analysis GEMM (S3),
  * 3 analysis Givens sweeps (S4), 4 pack a_lm, 5 unpack a_lm, 6 synthesis
- * sweeps, 7 synthesis GEMM, 8 inverse ring transform and residual, 9 C_l (S5).
+ * sweeps, 7 synthesis GEMM, 8 inverse ring transform, 9 C_l (S5),
+ * 10 refinement residual in ring-Fourier space.
  * Errors: ESTATE, EINVAL, EDEVICE.
  */
-#define HP2SPH_NSTAGES 10
+#define HP2SPH_NSTAGES 11
 int hp2sph_profile(hp2sph_plan_t plan, int32_t enable);
 int hp2sph_profile_read(hp2sph_plan_t plan, double* ms, int32_t* launches, int32_t nstages);
 

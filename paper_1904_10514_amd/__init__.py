@@ -43,9 +43,9 @@ EXPORTED = [
     "hp2sph_profile", "hp2sph_profile_read", "hp2sph_plan_create_ex", "hp2sph_plan_strategy",
 ]
 STRATEGIES = {"auto": 0, "staged": 1, "tables": 2}
-NSTAGES = 10
+NSTAGES = 11
 STAGES = ["ring_forward", "pole", "gemm_analysis", "sweep_analysis", "pack", "unpack",
-          "sweep_synthesis", "gemm_synthesis", "ring_inverse_residual", "cl"]
+          "sweep_synthesis", "gemm_synthesis", "ring_inverse", "cl", "residual_fold"]
 
 _vp = ctypes.c_void_p
 _i32 = ctypes.c_int32

@@ -170,7 +170,7 @@ struct hp2sph_plan_s {
     int64_t total_pix = 0, total_alm = 0, total_cl = 0;
     std::vector<std::unique_ptr<hp2sph::Group>> groups;
     size_t ws_bytes = 0;
-    size_t off_R = 0;                 // residual map (refinement)
+    size_t off_Df = 0, off_Dr = 0;    // refinement: FP64 ring coefficients, FP32 residual coefficients
     int strategy = 0;                 // requested HP2SPH_STRATEGY_*
     uint32_t magic = 0x48503253u;
 };
@@ -635,6 +635,49 @@ int synthesis_pass(Group& G, const double* alm, double* out, const double* minus
     return HP2SPH_OK;
 }
 
+// FP32 analysis with one FP64 refinement of one group (Sec. 2.2, eq. uzawa,
+// with A the FP32 analysis and S the FP64 synthesis):
+//   a0 = A32 f,  a1 = a0 + A32 (f - S a0).
+// The residual is formed after the ring transform, which is linear:
+// Ring(f - S a0) = Ring(f) - Ring(S a0).  Ring(f) is computed once in FP64;
+// Ring(S a0) is the synthesis GEMM output folded onto each ring's modes
+// (k_residual_fold), exactly what an inverse and a forward ring FFT would
+// give, without the two transforms.  The residual enters the FP32 stages
+// rounded to FP32 (FP32 colatitude fit and Legendre conversion).
+int refine_pass(hp2sph_plan_t plan, Group& G, const double* maps, double* alm, void* ws, hipStream_t s) {
+    Blocks4<float> D32 = blocks_at<float>(ws, G.off_D, G, G.rows_D);
+    Blocks4<float> U32 = blocks_at<float>(ws, G.off_U, G, G.rows_U);
+    Blocks4<double> Gs = blocks_at<double>(ws, G.off_D, G, G.rows_D);   // after the first GEMM, D32 is dead
+    Blocks4<double> U64 = blocks_at<double>(ws, G.off_U, G, G.rows_U);
+    Blocks4<double> Df = blocks_at<double>(ws, plan->off_Df, G, G.rows_D);
+    Blocks4<float> Dr = blocks_at<float>(ws, plan->off_Dr, G, G.rows_D);
+    const GemmList<float>& ga = G.ana32;
+    Blocks4<const float> Gv32;
+    for (int b = 0; b < 4; ++b) Gv32.p[b] = G.t32.givens[b];
+    // a0 = A32 f
+    STAGE(0, launch_ring_forward_dual(maps, G.d_map_off, G.rings, G.t64.fft, Df, D32, G.dims, s));
+    STAGE(1, launch_pole<float>(D32, G.dims, G.pole_w[0], G.pole_w[1], G.pole_w[2], s));
+    STAGE(2, launch_gemm<float>(ga.dev, ga.tmap, ga.slots, D32.p[0], U32.p[0], s));
+    if (!G.tables) STAGE(3, launch_sweep_fwd<float>(U32, Gv32, G.dims, s));
+    STAGE(4, launch_pack<float>(cblocks(U32), alm, G.d_alm_off, G.d_lmax, G.dims, false, s));
+    // S a0 up to the inverse ring transform (FP64)
+    STAGE(5, launch_unpack(alm, G.d_alm_off, G.d_lmax, U64, G.dims, s));
+    if (!G.tables) {
+        Blocks4<const double> Gv;
+        for (int b = 0; b < 4; ++b) Gv.p[b] = G.t64.givens[b];
+        STAGE(6, launch_sweep_bwd<double>(U64, Gv, G.dims, s));
+    }
+    const GemmList<double>& gs = G.tables ? G.syn64 : G.syn64_staged;
+    STAGE(7, launch_gemm<double>(gs.dev, gs.tmap, gs.slots, U64.p[0], Gs.p[0], s));
+    // residual ring coefficients, then a0 + A32 r
+    STAGE(10, launch_residual_fold(cblocks(Df), cblocks(Gs), Dr, G.rings, G.t64.fft, G.dims, s));
+    STAGE(1, launch_pole<float>(Dr, G.dims, G.pole_w[0], G.pole_w[1], G.pole_w[2], s));
+    STAGE(2, launch_gemm<float>(ga.dev, ga.tmap, ga.slots, Dr.p[0], U32.p[0], s));
+    if (!G.tables) STAGE(3, launch_sweep_fwd<float>(U32, Gv32, G.dims, s));
+    STAGE(4, launch_pack<float>(cblocks(U32), alm, G.d_alm_off, G.d_lmax, G.dims, true, s));
+    return HP2SPH_OK;
+}
+
 bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
 
 int check_plan(hp2sph_plan_t plan) {
@@ -724,8 +767,11 @@ int hp2sph_plan_create_ex(const int32_t* nside, const int32_t* lmax, int32_t bat
         }
         ws = max_group;   // groups run one after another and share the buffers
         if (mode == HP2SPH_F32_REFINE) {
-            plan->off_R = ws;
-            ws += align_up(size_t(plan->total_pix) * sizeof(double));
+            size_t max_D = 0;
+            for (auto& g : plan->groups) max_D = std::max(max_D, align_up(g->bytes_D));
+            plan->off_Df = ws;
+            plan->off_Dr = ws + max_D;
+            ws += 2 * max_D;
         }
         plan->ws_bytes = ws;
         // kernels with more than 64 KB of dynamic LDS
@@ -770,10 +816,7 @@ int hp2sph_analyze(hp2sph_plan_t plan, const double* maps, double* alm, void* wo
         } else if (plan->mode == HP2SPH_F32) {
             if (int e = analysis_pass<float>(G, maps, alm, workspace, false, s)) return e;
         } else {
-            double* R = reinterpret_cast<double*>(static_cast<char*>(workspace) + plan->off_R);
-            if (int e = analysis_pass<float>(G, maps, alm, workspace, false, s)) return e;
-            if (int e = synthesis_pass(G, alm, R, maps, workspace, s)) return e;
-            if (int e = analysis_pass<float>(G, R, alm, workspace, true, s)) return e;
+            if (int e = refine_pass(plan, G, maps, alm, workspace, s)) return e;
         }
     }
     return HP2SPH_OK;

@@ -94,6 +94,16 @@ template <class T>
 hipError_t launch_ring_forward(const double* maps, const int64_t* map_off, RingTab rt, FftTab<T> ft,
                                Blocks4<T> D, const GroupDims& g, hipStream_t s);
 
+// S1 in FP64 writing the rows twice: FP64 into D and rounded to FP32 into D32.
+hipError_t launch_ring_forward_dual(const double* maps, const int64_t* map_off, RingTab rt, FftTab<double> ft,
+                                    Blocks4<double> D, Blocks4<float> D32, const GroupDims& g, hipStream_t s);
+
+// Refinement residual in ring-Fourier space: Dr = Df - Ring(Synth(Gs)) for
+// Dsym rows 1 .. 2 nside (Gs: synthesis GEMM output, Df: FP64 forward ring
+// coefficients of the maps), written in FP32.
+hipError_t launch_residual_fold(Blocks4<const double> Df, Blocks4<const double> Gs, Blocks4<float> Dr, RingTab rt,
+                                FftTab<double> ft, const GroupDims& g, hipStream_t s);
+
 // S2: pole row h = 0 (quadratic extrapolation of the three nearest ring
 // means); zeroes every other entry of the pole row.
 template <class T>

@@ -3,6 +3,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 namespace hp2sph {
 
 // ---------------------------------------------------------------------------
@@ -274,10 +276,12 @@ __device__ __forceinline__ void ring_spectrum(const double* x, int n, bool shift
     // The next transform's first pass synchronises before it writes the buffer.
 }
 
-template <class T, int NT>
+// DUAL: also write the rows rounded to FP32 into D2 (the FP32 analysis input
+// of the refinement, whose FP64 rows form the residual).
+template <class T, int NT, bool DUAL>
 __global__ __launch_bounds__(NT) void k_ring_forward(const double* __restrict__ maps,
                                                      const int64_t* __restrict__ map_off, RingTab rt, FftTab<T> ft,
-                                                     Blocks4<T> D, GroupDims g) {
+                                                     Blocks4<T> D, Blocks4<float> D2, GroupDims g) {
     extern __shared__ unsigned char smem_raw[];
     C2<T>* buf = reinterpret_cast<C2<T>*>(smem_raw);
     int b, h;
@@ -315,23 +319,44 @@ __global__ __launch_bounds__(NT) void k_ring_forward(const double* __restrict__ 
         bp[row + col + 1] = dp.y;
         bm[row + col] = dm.x;
         bm[row + col + 1] = dm.y;
+        if constexpr (DUAL) {
+            float* fp = D2.p[2 * kpar + 0];
+            float* fm = D2.p[2 * kpar + 1];
+            fp[row + col] = float(dp.x);
+            fp[row + col + 1] = float(dp.y);
+            fm[row + col] = float(dm.x);
+            fm[row + col + 1] = float(dm.y);
+        }
     }
 }
 
-static size_t ring_lds_bytes(int fft_max, size_t elem) {
-    const int slots = fft_max > 256 ? fft_max : 256;
-    return size_t(slots + slots / 16) * elem;
-}
+static size_t lds_slots_bytes(int slots, size_t elem) { return size_t(slots + slots / 16 + 1) * elem; }
+
+static size_t ring_lds_bytes(int fft_max, size_t elem) { return lds_slots_bytes(std::max(fft_max, 256), elem); }
 
 template <class T>
 hipError_t launch_ring_forward(const double* maps, const int64_t* map_off, RingTab rt, FftTab<T> ft, Blocks4<T> D,
                                const GroupDims& g, hipStream_t s) {
     dim3 grid(g.nmaps, 2 * g.nside);
     const size_t shm = ring_lds_bytes(ft.fft_max, sizeof(C2<T>));
+    const Blocks4<float> none{};
     if (ring_threads(ft.fft_max) == 256)
-        hipLaunchKernelGGL((k_ring_forward<T, 256>), grid, dim3(256), shm, s, maps, map_off, rt, ft, D, g);
+        hipLaunchKernelGGL((k_ring_forward<T, 256, false>), grid, dim3(256), shm, s, maps, map_off, rt, ft, D, none, g);
     else
-        hipLaunchKernelGGL((k_ring_forward<T, 512>), grid, dim3(512), shm, s, maps, map_off, rt, ft, D, g);
+        hipLaunchKernelGGL((k_ring_forward<T, 512, false>), grid, dim3(512), shm, s, maps, map_off, rt, ft, D, none, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_ring_forward_dual(const double* maps, const int64_t* map_off, RingTab rt, FftTab<double> ft,
+                                    Blocks4<double> D, Blocks4<float> D32, const GroupDims& g, hipStream_t s) {
+    dim3 grid(g.nmaps, 2 * g.nside);
+    const size_t shm = ring_lds_bytes(ft.fft_max, sizeof(C2<double>));
+    if (ring_threads(ft.fft_max) == 256)
+        hipLaunchKernelGGL((k_ring_forward<double, 256, true>), grid, dim3(256), shm, s, maps, map_off, rt, ft, D, D32,
+                           g);
+    else
+        hipLaunchKernelGGL((k_ring_forward<double, 512, true>), grid, dim3(512), shm, s, maps, map_off, rt, ft, D, D32,
+                           g);
     return hipGetLastError();
 }
 
@@ -1026,53 +1051,92 @@ __device__ __forceinline__ C2<double> eplus(const double* roots, int64_t k, int 
     return {-r.x, r.y};   // -conj(r)
 }
 
+// Mode sums of one ring from Dsym row h: with D_k = D+_k + sgn D-_k and
+// G_k = D_k e^{i k phi0} (k = 0..p), leaves in buf[lpad(t)], t = 0..n/2,
+//   H_t = sum_{k = t mod n} G_k + conj(sum_{k > 0, k = -t mod n} G_k),
+// the DFT coefficients (up to the factor n) of the real ring values the
+// coefficients D_k take at the ring's n points (modes |k| >= n alias).
+// For a shifted ring (phi0 = pi / n) the phase factors out of the alias
+// chains: e^{i pi (t + a n) / n} = (-1)^a e^{i pi t / n}, so
+//   H_t = e^{i pi t / n} (A_t - conj B_t),  A_t = sum_a (-1)^a D_{t + a n},
+//   B_t = sum_a (-1)^a D_{n - t + a n};  unshifted: H_t = A_t + conj B_t
+// without the signs.  D_k is staged in buf[0..p] (coalesced loads), partial
+// chain sums in buf[p+1 ..]; buf needs p + 1 + NT slots.  Ends with a barrier.
+template <int NT>
+__device__ __forceinline__ void ring_mode_sums(const Blocks4<const double>& D, int h, int sgn, int n, bool shifted,
+                                               int p, const GroupDims& g, int map, const double* roots,
+                                               C2<double>* buf) {
+    const int L = n >> 1, T1 = L + 1;
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int i = 0; i < kRingKPT; ++i) {
+        const int k = tid + i * NT;
+        if (k <= p) {
+            const int kpar = k & 1, kk = k >> 1;
+            const int64_t o = int64_t(h) * g.N[kpar] + int64_t(map) * g.cm[kpar] + int64_t(kk) * g.ck[kpar];
+            const D2 vp = *reinterpret_cast<const D2*>(D.p[2 * kpar] + o);
+            const D2 vm = *reinterpret_cast<const D2*>(D.p[2 * kpar + 1] + o);
+            buf[lpad(k)] = {vp.x + sgn * vm.x, vp.y + sgn * vm.y};
+        }
+    }
+    __syncthreads();
+    // sum over a = s, s + c, s + 2c, ... of (+-1)^a D_{k0 + a n}
+    auto chain = [&](int k0, int s, int c) -> C2<double> {
+        C2<double> acc = {0.0, 0.0};
+        for (int a = s, k = k0 + s * n; k <= p; a += c, k += c * n) {
+            const C2<double> v = buf[lpad(k)];
+            acc = (shifted && (a & 1)) ? csub(acc, v) : cadd(acc, v);
+        }
+        return acc;
+    };
+    auto combine = [&](int t, int s, int c) -> C2<double> {
+        const C2<double> A = chain(t, s, c), B = chain(n - t, s, c);
+        return shifted ? csub(A, cconj(B)) : cadd(A, cconj(B));
+    };
+    auto phase = [&](C2<double> v, int t) -> C2<double> {
+        return shifted ? cmul(v, cconj(ldc(roots, t))) : v;   // e^{+i pi t / n}
+    };
+    const int c = NT / T1;
+    if (c > 1) {
+        // c threads per t, partial sums added in a fixed order
+        C2<double> part = {0.0, 0.0};
+        if (tid < c * T1) part = combine(tid % T1, tid / T1, c);
+        buf[lpad(p + 1 + tid)] = part;
+        __syncthreads();
+        if (tid < T1) {
+            C2<double> hs = {0.0, 0.0};
+            for (int s = 0; s < c; ++s) hs = cadd(hs, buf[lpad(p + 1 + s * T1 + tid)]);
+            buf[lpad(tid)] = phase(hs, tid);   // D_k is no longer read: the chains ended at the barrier
+        }
+    } else {
+        C2<double> H[kRingKPT];
+#pragma unroll
+        for (int i = 0; i < kRingKPT; ++i) {
+            const int t = tid + i * NT;
+            H[i] = (t < T1) ? phase(combine(t, 0, 1), t) : C2<double>{0.0, 0.0};
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < kRingKPT; ++i) {
+            const int t = tid + i * NT;
+            if (t < T1) buf[lpad(t)] = H[i];
+        }
+    }
+    __syncthreads();
+}
+
 // One ring of the synthesis: values x_q, q < n, of the real trigonometric
 // polynomial with coefficients D_k = D+_k + sgn D-_k, k = 0..p (and the
 // conjugates at -k), evaluated at lambda_q = phi0 + 2 pi q / n.  Modes |k| >= n
 // alias onto k mod n.  Written to out (minus minus_from[q] - x_q if given).
 template <int NT>
 __device__ __forceinline__ void ring_synth(const Blocks4<const double>& D, int h, int sgn, int n, bool shifted, int p,
-                           const GroupDims& g, int map, FftTab<double> ft, C2<double>* buf, double* out,
-                           const double* minus_from) {
+                                           const GroupDims& g, int map, FftTab<double> ft, C2<double>* buf,
+                                           double* out, const double* minus_from) {
     const int L = n >> 1, j = n >> 2;
     const int Mb = ft.chirpm[j];
     const double* roots = ft.roots + 2 * ft.rootoff[j];
-    // G_k = D_k e^{i k phi0}
-    auto Gk = [&](int k) -> C2<double> {
-        const int kpar = k & 1, kk = k >> 1;
-        const int64_t o = int64_t(h) * g.N[kpar] + int64_t(map) * g.cm[kpar] + int64_t(kk) * g.ck[kpar];
-        const D2 vp = *reinterpret_cast<const D2*>(D.p[2 * kpar] + o);
-        const D2 vm = *reinterpret_cast<const D2*>(D.p[2 * kpar + 1] + o);
-        C2<double> d = {vp.x + sgn * vm.x, vp.y + sgn * vm.y};
-        if (shifted) d = cmul(d, eplus(roots, k, n));
-        return d;
-    };
-    // H_t = sum_{k = t mod n} G_k + conj(sum_{k > 0, k = -t mod n} G_k),
-    // t = 0..L, summed over the aliases a = s, s + c, s + 2c, ... of k = t + a n
-    // and k = (n - t) + a n.
-    auto Hpart = [&](int t, int s, int c) -> C2<double> {
-        C2<double> acc = {0.0, 0.0}, bsum = {0.0, 0.0};
-        for (int k = t + s * n; k <= p; k += c * n) acc = cadd(acc, Gk(k));
-        for (int k = (t == 0 ? n : n - t) + s * n; k <= p; k += c * n) bsum = cadd(bsum, Gk(k));
-        return cadd(acc, cconj(bsum));
-    };
-    const int T1 = L + 1;
-    const int c = NT / T1;
-    if (c > 1) {
-        // c threads per t, partial sums in a fixed order
-        C2<double> part = {0.0, 0.0};
-        if (int(threadIdx.x) < c * T1) part = Hpart(int(threadIdx.x) % T1, int(threadIdx.x) / T1, c);
-        buf[lpad(threadIdx.x)] = part;
-        __syncthreads();
-        C2<double> hsum = {0.0, 0.0};
-        if (int(threadIdx.x) < T1)
-            for (int s = 0; s < c; ++s) hsum = cadd(hsum, buf[lpad(s * T1 + threadIdx.x)]);
-        __syncthreads();
-        if (int(threadIdx.x) < T1) buf[lpad(threadIdx.x)] = hsum;
-    } else {
-        for (int t = threadIdx.x; t < T1; t += NT) buf[lpad(t)] = Hpart(t, 0, 1);
-    }
-    __syncthreads();
+    ring_mode_sums<NT>(D, h, sgn, n, shifted, p, g, map, roots, buf);
     // Z'_t = (H_t + conj H_{L-t}) + i (H_t - conj H_{L-t}) e^{2 pi i t / n}, t < L;
     // x_{2q} + i x_{2q+1} = sum_t Z'_t e^{2 pi i t q / L}, computed as conj(DFT(conj Z')).
     auto src = [&](int t) -> C2<double> {
@@ -1126,11 +1190,152 @@ hipError_t launch_ring_inverse(Blocks4<const double> D, RingTab rt, FftTab<doubl
                                const double* minus_from, const int64_t* map_off, const GroupDims& g,
                                hipStream_t s) {
     dim3 grid(g.nmaps, 2 * g.nside);
-    const size_t shm = ring_lds_bytes(ft.fft_max, sizeof(C2<double>));
-    if (ring_threads(ft.fft_max) == 256)
+    const int nt = ring_threads(ft.fft_max);
+    const size_t shm = lds_slots_bytes(std::max(ft.fft_max, g.p + 1 + nt), sizeof(C2<double>));
+    if (nt == 256)
         hipLaunchKernelGGL(k_ring_inverse<256>, grid, dim3(256), shm, s, D, rt, ft, out, minus_from, map_off, g);
     else
         hipLaunchKernelGGL(k_ring_inverse<512>, grid, dim3(512), shm, s, D, rt, ft, out, minus_from, map_off, g);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Refinement residual in ring-Fourier space
+// ---------------------------------------------------------------------------
+//
+// For the maps' FP64 ring coefficients Df (Dsym rows 1..2 nside, as the
+// forward ring transform writes them) and the synthesis GEMM output Gs (the
+// same rows of S a0 before the inverse ring transform), writes
+//   Dr = Df - Ring(Synth(Gs))
+// in FP32.  Ring(Synth(.)) of one ring with n points, L = n/2, is exact
+// arithmetic on the coefficients (no FFT): the inverse transform folds the
+// modes k = 0..p onto the ring's DFT bins and the forward transform reads the
+// bins back, so
+//   X_k = A_k + conj B_k (unshifted ring) or A_k - conj B_k (shifted),  k < L,
+//   A_k = sum_a s_a D_{k + a n},  B_k = sum_a s_a D_{n - k + a n},
+//   s_a = 1 (unshifted) or (-1)^a (shifted: the half-pixel phase e^{i pi k/n}
+//   turns into these signs and cancels against the forward shift),
+// X_L from the forward transform's Nyquist rule with alpha the (real)
+// Nyquist bin of the synthesized ring (Re X'_L, or -Im X'_L for a shifted
+// ring, X'_L = the k = L instance of the formula above), and X_k = 0 above L.
+// The N and S rings of a pair share n and the shift, and D_k = D+ +- D-, so
+// one pass over the aliases gives both.
+//
+// A workgroup takes one ring pair of 8 consecutive maps; lane bits 0..2 pick
+// the map, so that in the mode-major layout every access to one (row, mode)
+// is one contiguous run of 8 maps.
+
+constexpr int kFoldMaps = 8;
+
+template <int NT>
+__global__ __launch_bounds__(NT) void k_residual_fold(Blocks4<const double> Df, Blocks4<const double> Gs,
+                                                      Blocks4<float> Dr, RingTab rt, GroupDims g) {
+    constexpr int SL = NT / kFoldMaps;   // k slots per map
+    __shared__ C2<double> partN[NT], partS[NT];
+    const int mgroups = (g.nmaps + kFoldMaps - 1) / kFoldMaps;
+    int mg, h;
+    ring_block(mgroups, 2 * g.nside, mg, h);
+    const int m8 = threadIdx.x % kFoldMaps, slot = threadIdx.x / kFoldMaps;
+    const int map = mg * kFoldMaps + m8;
+    const bool valid = map < g.nmaps;
+    const int ns = g.nside, p = g.p;
+    const bool equator = (h == 2 * ns);
+    const int n = rt.n[h - 1], L = n >> 1, T1 = L + 1;
+    const bool shifted = rt.shifted[h - 1] != 0;
+    auto offs = [&](int k) -> int64_t {
+        const int kpar = k & 1, kk = k >> 1;
+        return int64_t(h) * g.N[kpar] + int64_t(map) * g.cm[kpar] + int64_t(kk) * g.ck[kpar];
+    };
+    // alias chains from a = s in steps of c of both rings
+    auto chains = [&](int t, int s, int c, C2<double>& SN, C2<double>& SS) {
+        C2<double> Ap = {0.0, 0.0}, Am = {0.0, 0.0}, Bp = {0.0, 0.0}, Bm = {0.0, 0.0};
+        if (valid) {
+            for (int a = s, k = t + s * n; k <= p; a += c, k += c * n) {
+                const int64_t o = offs(k);
+                const D2 vp = *reinterpret_cast<const D2*>(Gs.p[2 * (k & 1)] + o);
+                const D2 vm = *reinterpret_cast<const D2*>(Gs.p[2 * (k & 1) + 1] + o);
+                const double sg = (shifted && (a & 1)) ? -1.0 : 1.0;
+                Ap = {Ap.x + sg * vp.x, Ap.y + sg * vp.y};
+                Am = {Am.x + sg * vm.x, Am.y + sg * vm.y};
+            }
+            for (int a = s, k = n - t + s * n; k <= p; a += c, k += c * n) {
+                const int64_t o = offs(k);
+                const D2 vp = *reinterpret_cast<const D2*>(Gs.p[2 * (k & 1)] + o);
+                const D2 vm = *reinterpret_cast<const D2*>(Gs.p[2 * (k & 1) + 1] + o);
+                const double sg = (shifted && (a & 1)) ? -1.0 : 1.0;
+                Bp = {Bp.x + sg * vp.x, Bp.y + sg * vp.y};
+                Bm = {Bm.x + sg * vm.x, Bm.y + sg * vm.y};
+            }
+        }
+        const C2<double> AN = cadd(Ap, Am), BN = cadd(Bp, Bm), AS = csub(Ap, Am), BS = csub(Bp, Bm);
+        SN = shifted ? csub(AN, cconj(BN)) : cadd(AN, cconj(BN));
+        SS = shifted ? csub(AS, cconj(BS)) : cadd(AS, cconj(BS));
+    };
+    // X_k of one ring from its chain value at k (k <= L)
+    auto coeff = [&](int k, C2<double> S) -> C2<double> {
+        if (k < L) return S;
+        const double alpha = shifted ? -S.y : S.x;
+        if (L < p) return {0.0, -0.5 * alpha};
+        return {shifted ? 0.0 : 0.5 * alpha, 0.0};
+    };
+    auto emit = [&](int k, C2<double> XN, C2<double> XS) {
+        if (!valid) return;
+        C2<double> sp, sm;
+        if (equator) {
+            sp = XN;
+            sm = {0.0, 0.0};
+        } else {
+            sp = cscale(cadd(XN, XS), 0.5);
+            sm = cscale(csub(XN, XS), 0.5);
+        }
+        const int64_t o = offs(k);
+        const int kpar = k & 1;
+        const D2 fp = *reinterpret_cast<const D2*>(Df.p[2 * kpar] + o);
+        const D2 fm = *reinterpret_cast<const D2*>(Df.p[2 * kpar + 1] + o);
+        float* rp = Dr.p[2 * kpar];
+        float* rm = Dr.p[2 * kpar + 1];
+        rp[o] = float(fp.x - sp.x);
+        rp[o + 1] = float(fp.y - sp.y);
+        rm[o] = float(fm.x - sm.x);
+        rm[o + 1] = float(fm.y - sm.y);
+    };
+    const C2<double> zero = {0.0, 0.0};
+    const int c = SL / T1;
+    if (c > 1) {
+        // short rings: c slots per bin, partial sums added in a fixed order
+        C2<double> SN = zero, SS = zero;
+        if (slot < c * T1) chains(slot % T1, slot / T1, c, SN, SS);
+        partN[threadIdx.x] = SN;
+        partS[threadIdx.x] = SS;
+        __syncthreads();
+        if (slot < T1) {
+            C2<double> hn = zero, hs = zero;
+            for (int q = 0; q < c; ++q) {
+                hn = cadd(hn, partN[(q * T1 + slot) * kFoldMaps + m8]);
+                hs = cadd(hs, partS[(q * T1 + slot) * kFoldMaps + m8]);
+            }
+            emit(slot, coeff(slot, hn), coeff(slot, hs));
+        }
+        for (int k = T1 + slot; k <= p; k += SL) emit(k, zero, zero);
+    } else {
+        for (int k = slot; k <= p; k += SL) {
+            if (k <= L) {
+                C2<double> SN, SS;
+                chains(k, 0, 1, SN, SS);
+                emit(k, coeff(k, SN), coeff(k, SS));
+            } else {
+                emit(k, zero, zero);
+            }
+        }
+    }
+}
+
+hipError_t launch_residual_fold(Blocks4<const double> Df, Blocks4<const double> Gs, Blocks4<float> Dr, RingTab rt,
+                                FftTab<double> ft, const GroupDims& g, hipStream_t s) {
+    (void)ft;
+    const int mgroups = (g.nmaps + kFoldMaps - 1) / kFoldMaps;
+    dim3 grid(mgroups, 2 * g.nside);
+    hipLaunchKernelGGL(k_residual_fold<256>, grid, dim3(256), 0, s, Df, Gs, Dr, rt, g);
     return hipGetLastError();
 }
 
@@ -1165,12 +1370,15 @@ hipError_t launch_cl(const double* alm, const int64_t* alm_off, const int32_t* l
 hipError_t configure_kernels() {
     const int bytes = 160 * 1024;
     const void* fns[] = {
-        reinterpret_cast<const void*>(&k_ring_forward<double, 256>),
-        reinterpret_cast<const void*>(&k_ring_forward<double, 512>),
-        reinterpret_cast<const void*>(&k_ring_forward<float, 256>),
-        reinterpret_cast<const void*>(&k_ring_forward<float, 512>),
+        reinterpret_cast<const void*>(&k_ring_forward<double, 256, false>),
+        reinterpret_cast<const void*>(&k_ring_forward<double, 512, false>),
+        reinterpret_cast<const void*>(&k_ring_forward<double, 256, true>),
+        reinterpret_cast<const void*>(&k_ring_forward<double, 512, true>),
+        reinterpret_cast<const void*>(&k_ring_forward<float, 256, false>),
+        reinterpret_cast<const void*>(&k_ring_forward<float, 512, false>),
         reinterpret_cast<const void*>(&k_ring_inverse<256>),
         reinterpret_cast<const void*>(&k_ring_inverse<512>),
+
     };
     for (const void* f : fns) {
         const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
