@@ -87,8 +87,6 @@ def stage_work(stage, nside, nmaps, tsize, strategy="staged"):
     rows = 2 * nside * (N[0] + N[1]) * 2   # values of Dsym rows 1..2 nside, both D+ and D-
     if stage == "ring_forward":
         return "byte", npix * 8 + rows * tsize
-    if stage == "ring_forward_dual":
-        return "byte", npix * 8 + rows * (8 + 4)
     if stage == "ring_inverse":
         return "byte", rows * 8 + npix * 8
     if stage == "residual_fold":
@@ -121,9 +119,7 @@ def stage_dtype(stage, mode):
 
 def roofline(stage, mode, nside, nmaps, ms_total, launches, strategy="staged"):
     dt = stage_dtype(stage, mode)
-    # the refinement's forward ring transform writes FP64 and FP32 rows
-    work_stage = "ring_forward_dual" if (stage == "ring_forward" and mode == "f32_refine") else stage
-    kind, amount = stage_work(work_stage, nside, nmaps, 4 if dt == "f32" else 8, strategy)
+    kind, amount = stage_work(stage, nside, nmaps, 4 if dt == "f32" else 8, strategy)
     avg_s = ms_total / launches / 1e3
     bound = stage_bound(stage)
     if bound == "hbm":

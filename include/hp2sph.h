@@ -180,7 +180,8 @@ const char* hp2sph_last_error(void);
  * recorded events and returns, per stage, the summed milliseconds and the
  * number of launches (arrays of length nstages, at most HP2SPH_NSTAGES).
  * Stages: 0 ring transform (S1), 1 pole values (S2), 2 analysis GEMM (S3),
- * 3 analysis Givens sweeps (S4), 4 pack a_lm, 5 unpack a_lm, 6 synthesis
+ * 3 analysis Givens sweeps (S4), 4 pack a_lm, 5 unpack a_lm (in the
+ * refinement: FP32 a0 widened to FP64 in place of an unpack), 6 synthesis
  * sweeps, 7 synthesis GEMM, 8 inverse ring transform, 9 C_l (S5),
  * 10 refinement residual in ring-Fourier space.
  * Errors: ESTATE, EINVAL, EDEVICE.

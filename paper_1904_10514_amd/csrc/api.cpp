@@ -87,6 +87,8 @@ struct Group {
     int64_t* d_alm_off = nullptr;     // per member: offset of its alm (complex)
     int64_t* d_cl_off = nullptr;
     int32_t* d_lmax = nullptr;
+    int32_t* d_pack_tiles = nullptr;   // (m, l0) of the pack tiles
+    int n_pack_tiles = 0;
     int lmax_max = 0;
     // workspace offsets (bytes, relative to the plan's workspace)
     size_t off_D = 0, off_U = 0;
@@ -98,6 +100,7 @@ struct Group {
     // device GEMM problem lists
     GemmList<double> ana64, syn64, syn64_staged;
     GemmList<float> ana32;
+    GemmList<float> ana32_b64;   // FP32 analysis reading FP64 Dsym (first pass of the refinement)
 };
 
 template <class T>
@@ -171,6 +174,7 @@ struct hp2sph_plan_s {
     std::vector<std::unique_ptr<hp2sph::Group>> groups;
     size_t ws_bytes = 0;
     size_t off_Df = 0, off_Dr = 0;    // refinement: FP64 ring coefficients, FP32 residual coefficients
+    size_t off_Ua = 0;                // refinement: FP32 a0 in the U layout
     int strategy = 0;                 // requested HP2SPH_STRATEGY_*
     uint32_t magic = 0x48503253u;
 };
@@ -287,6 +291,11 @@ void build_group(hp2sph_plan_t plan, Group& G) {
     G.d_alm_off = upload_int(G.owned, ao);
     G.d_cl_off = upload_int(G.owned, co);
     G.d_lmax = upload_int(G.owned, lm);
+    {
+        std::vector<int32_t> pt = pack_tiles(p);
+        G.n_pack_tiles = int(pt.size() / 2);
+        G.d_pack_tiles = upload_int(G.owned, pt);
+    }
 
     // workspace sizes (FP64 elements; FP32 stages alias the same bytes)
     const int K = 2 * G.nside + 1;
@@ -348,7 +357,8 @@ void upload_list(Group& G, std::vector<GemmProblem<T>>& v, GemmList<T>& out) {
     out.tmap = upload_int(G.owned, tm);
 }
 
-template <class T>
+// TB: storage type of the Dsym rows the GEMM reads (B offsets in TB elements)
+template <class T, class TB = T>
 void staged_analysis_list(Group& G, const DevTables<T>& t, GemmList<T>& out) {
     const GroupDims& d = G.dims;
     std::vector<GemmProblem<T>> v;
@@ -360,7 +370,7 @@ void staged_analysis_list(Group& G, const DevTables<T>& t, GemmList<T>& out) {
         P.N = int(d.N[kpar]);
         P.K = 2 * G.nside + 1;
         P.lda = d.nl[b];
-        P.boff = int64_t(G.blk_off_D[b] / sizeof(T));
+        P.boff = int64_t(G.blk_off_D[b] / sizeof(TB));
         P.ldb = d.N[kpar];
         P.bps = 2;
         P.coff = int64_t(G.blk_off_U[b] / sizeof(T));
@@ -443,7 +453,7 @@ void build_order_tables(hp2sph_plan_t plan, Group& G) {
     const int K = 2 * G.nside + 1;
     const bool want_syn = (plan->mode == HP2SPH_F32_REFINE);
     std::vector<GemmProblem<double>> la64, ls64;
-    std::vector<GemmProblem<float>> la32;
+    std::vector<GemmProblem<float>> la32, la32b;
     // temporary buffer for the virtual batch (chains replicated over k')
     size_t per_v = 0;
     for (int b = 0; b < 4; ++b) per_v = std::max(per_v, size_t(d.nl[b]) * 2 * d.nk[b] * sizeof(double));
@@ -542,6 +552,8 @@ void build_order_tables(hp2sph_plan_t plan, Group& G) {
                 Q.boff = int64_t(G.blk_off_D[b] / 4) + int64_t(h0) * d.N[kpar] + kcol;
                 Q.coff = int64_t(G.blk_off_U[b] / 4) + int64_t(kk) * d.N[kpar] + kcol;
                 la32.push_back(Q);
+                Q.boff = int64_t(G.blk_off_D[b] / 8) + int64_t(h0) * d.N[kpar] + kcol;
+                la32b.push_back(Q);
             }
             if (want_syn) {
                 GemmProblem<double> S{};
@@ -564,6 +576,7 @@ void build_order_tables(hp2sph_plan_t plan, Group& G) {
     }
     if (plan->mode == HP2SPH_F64) upload_list(G, la64, G.ana64);
     else upload_list(G, la32, G.ana32);
+    if (plan->mode == HP2SPH_F32_REFINE) upload_list(G, la32b, G.ana32_b64);
     if (want_syn) upload_list(G, ls64, G.syn64);
 }
 
@@ -599,7 +612,7 @@ DevTables<float>& tabs<float>(Group& G) { return G.t32; }
 
 // One analysis pass of one group in precision T: maps_in -> alm (write or add).
 template <class T>
-int analysis_pass(Group& G, const double* maps_in, double* alm, void* ws, bool accumulate, hipStream_t s) {
+int analysis_pass(Group& G, const double* maps_in, double* alm, void* ws, hipStream_t s) {
     DevTables<T>& t = tabs<T>(G);
     Blocks4<T> D = blocks_at<T>(ws, G.off_D, G, G.rows_D);
     Blocks4<T> U = blocks_at<T>(ws, G.off_U, G, G.rows_U);
@@ -610,7 +623,8 @@ int analysis_pass(Group& G, const double* maps_in, double* alm, void* ws, bool a
     Blocks4<const T> Gv;
     for (int b = 0; b < 4; ++b) Gv.p[b] = t.givens[b];
     if (!G.tables) STAGE(3, launch_sweep_fwd<T>(U, Gv, G.dims, s));
-    STAGE(4, launch_pack<T>(cblocks(U), alm, G.d_alm_off, G.d_lmax, G.dims, accumulate, s));
+    STAGE(4, launch_pack<T>(cblocks(U), Blocks4<const T>{}, alm, G.d_alm_off, G.d_lmax, G.d_pack_tiles,
+                            G.n_pack_tiles, G.dims, s));
     return HP2SPH_OK;
 }
 
@@ -645,23 +659,24 @@ int synthesis_pass(Group& G, const double* alm, double* out, const double* minus
 // give, without the two transforms.  The residual enters the FP32 stages
 // rounded to FP32 (FP32 colatitude fit and Legendre conversion).
 int refine_pass(hp2sph_plan_t plan, Group& G, const double* maps, double* alm, void* ws, hipStream_t s) {
-    Blocks4<float> D32 = blocks_at<float>(ws, G.off_D, G, G.rows_D);
-    Blocks4<float> U32 = blocks_at<float>(ws, G.off_U, G, G.rows_U);
-    Blocks4<double> Gs = blocks_at<double>(ws, G.off_D, G, G.rows_D);   // after the first GEMM, D32 is dead
+    Blocks4<float> Ua = blocks_at<float>(ws, plan->off_Ua, G, G.rows_U);   // a0, kept to the end
+    Blocks4<float> Ub = blocks_at<float>(ws, G.off_U, G, G.rows_U);        // the correction
     Blocks4<double> U64 = blocks_at<double>(ws, G.off_U, G, G.rows_U);
+    Blocks4<double> Gs = blocks_at<double>(ws, G.off_D, G, G.rows_D);
     Blocks4<double> Df = blocks_at<double>(ws, plan->off_Df, G, G.rows_D);
     Blocks4<float> Dr = blocks_at<float>(ws, plan->off_Dr, G, G.rows_D);
     const GemmList<float>& ga = G.ana32;
+    const GemmList<float>& gb = G.ana32_b64;
     Blocks4<const float> Gv32;
     for (int b = 0; b < 4; ++b) Gv32.p[b] = G.t32.givens[b];
-    // a0 = A32 f
-    STAGE(0, launch_ring_forward_dual(maps, G.d_map_off, G.rings, G.t64.fft, Df, D32, G.dims, s));
-    STAGE(1, launch_pole<float>(D32, G.dims, G.pole_w[0], G.pole_w[1], G.pole_w[2], s));
-    STAGE(2, launch_gemm<float>(ga.dev, ga.tmap, ga.slots, D32.p[0], U32.p[0], s));
-    if (!G.tables) STAGE(3, launch_sweep_fwd<float>(U32, Gv32, G.dims, s));
-    STAGE(4, launch_pack<float>(cblocks(U32), alm, G.d_alm_off, G.d_lmax, G.dims, false, s));
-    // S a0 up to the inverse ring transform (FP64)
-    STAGE(5, launch_unpack(alm, G.d_alm_off, G.d_lmax, U64, G.dims, s));
+    // a0 = A32 f: FP64 ring coefficients, rounded to FP32 as the GEMM stages them
+    STAGE(0, launch_ring_forward<double>(maps, G.d_map_off, G.rings, G.t64.fft, Df, G.dims, s));
+    STAGE(1, launch_pole<double>(Df, G.dims, G.pole_w[0], G.pole_w[1], G.pole_w[2], s));
+    STAGE(2, (launch_gemm<float, double>(gb.dev, gb.tmap, gb.slots, Df.p[0], Ua.p[0], s)));
+    if (!G.tables) STAGE(3, launch_sweep_fwd<float>(Ua, Gv32, G.dims, s));
+    // S a0 up to the inverse ring transform (FP64): a0 widened to FP64 (and
+    // truncated at each map's lmax), then the synthesis GEMM
+    STAGE(5, launch_widen(cblocks(Ua), U64, G.d_lmax, G.dims, s));
     if (!G.tables) {
         Blocks4<const double> Gv;
         for (int b = 0; b < 4; ++b) Gv.p[b] = G.t64.givens[b];
@@ -669,12 +684,13 @@ int refine_pass(hp2sph_plan_t plan, Group& G, const double* maps, double* alm, v
     }
     const GemmList<double>& gs = G.tables ? G.syn64 : G.syn64_staged;
     STAGE(7, launch_gemm<double>(gs.dev, gs.tmap, gs.slots, U64.p[0], Gs.p[0], s));
-    // residual ring coefficients, then a0 + A32 r
+    // residual ring coefficients, the correction A32 r, and a1 = a0 + A32 r
     STAGE(10, launch_residual_fold(cblocks(Df), cblocks(Gs), Dr, G.rings, G.t64.fft, G.dims, s));
     STAGE(1, launch_pole<float>(Dr, G.dims, G.pole_w[0], G.pole_w[1], G.pole_w[2], s));
-    STAGE(2, launch_gemm<float>(ga.dev, ga.tmap, ga.slots, Dr.p[0], U32.p[0], s));
-    if (!G.tables) STAGE(3, launch_sweep_fwd<float>(U32, Gv32, G.dims, s));
-    STAGE(4, launch_pack<float>(cblocks(U32), alm, G.d_alm_off, G.d_lmax, G.dims, true, s));
+    STAGE(2, launch_gemm<float>(ga.dev, ga.tmap, ga.slots, Dr.p[0], Ub.p[0], s));
+    if (!G.tables) STAGE(3, launch_sweep_fwd<float>(Ub, Gv32, G.dims, s));
+    STAGE(4, launch_pack<float>(cblocks(Ua), cblocks(Ub), alm, G.d_alm_off, G.d_lmax, G.d_pack_tiles,
+                                G.n_pack_tiles, G.dims, s));
     return HP2SPH_OK;
 }
 
@@ -761,17 +777,22 @@ int hp2sph_plan_create_ex(const int32_t* nside, const int32_t* lmax, int32_t bat
                 staged_analysis_list<double>(*G, G->t64, G->ana64);
             } else {
                 staged_analysis_list<float>(*G, G->t32, G->ana32);
+                if (mode == HP2SPH_F32_REFINE) staged_analysis_list<float, double>(*G, G->t32, G->ana32_b64);
             }
             max_group = std::max(max_group, G->off_U + align_up(G->bytes_U));
             plan->groups.push_back(std::move(G));
         }
         ws = max_group;   // groups run one after another and share the buffers
         if (mode == HP2SPH_F32_REFINE) {
-            size_t max_D = 0;
-            for (auto& g : plan->groups) max_D = std::max(max_D, align_up(g->bytes_D));
+            size_t max_D = 0, max_U = 0;
+            for (auto& g : plan->groups) {
+                max_D = std::max(max_D, align_up(g->bytes_D));
+                max_U = std::max(max_U, align_up(g->bytes_U));
+            }
             plan->off_Df = ws;
             plan->off_Dr = ws + max_D;
-            ws += 2 * max_D;
+            plan->off_Ua = ws + 2 * max_D;
+            ws += 2 * max_D + max_U;
         }
         plan->ws_bytes = ws;
         // kernels with more than 64 KB of dynamic LDS
@@ -812,9 +833,9 @@ int hp2sph_analyze(hp2sph_plan_t plan, const double* maps, double* alm, void* wo
     for (auto& gp : plan->groups) {
         Group& G = *gp;
         if (plan->mode == HP2SPH_F64) {
-            if (int e = analysis_pass<double>(G, maps, alm, workspace, false, s)) return e;
+            if (int e = analysis_pass<double>(G, maps, alm, workspace, s)) return e;
         } else if (plan->mode == HP2SPH_F32) {
-            if (int e = analysis_pass<float>(G, maps, alm, workspace, false, s)) return e;
+            if (int e = analysis_pass<float>(G, maps, alm, workspace, s)) return e;
         } else {
             if (int e = refine_pass(plan, G, maps, alm, workspace, s)) return e;
         }

@@ -94,10 +94,6 @@ template <class T>
 hipError_t launch_ring_forward(const double* maps, const int64_t* map_off, RingTab rt, FftTab<T> ft,
                                Blocks4<T> D, const GroupDims& g, hipStream_t s);
 
-// S1 in FP64 writing the rows twice: FP64 into D and rounded to FP32 into D32.
-hipError_t launch_ring_forward_dual(const double* maps, const int64_t* map_off, RingTab rt, FftTab<double> ft,
-                                    Blocks4<double> D, Blocks4<float> D32, const GroupDims& g, hipStream_t s);
-
 // Refinement residual in ring-Fourier space: Dr = Df - Ring(Synth(Gs)) for
 // Dsym rows 1 .. 2 nside (Gs: synthesis GEMM output, Df: FP64 forward ring
 // coefficients of the maps), written in FP32.
@@ -110,8 +106,9 @@ template <class T>
 hipError_t launch_pole(Blocks4<T> D, const GroupDims& g, double w0, double w1, double w2, hipStream_t s);
 
 // Grouped GEMM over a device-resident problem list (finalized), one launch.
-template <class T>
-hipError_t launch_gemm(const GemmProblem<T>* probs_dev, const int32_t* tmap_dev, int nslots, const T* Bbase,
+// B is stored as TB (offsets boff in TB elements) and rounded to T.
+template <class T, class TB = T>
+hipError_t launch_gemm(const GemmProblem<T>* probs_dev, const int32_t* tmap_dev, int nslots, const TB* Bbase,
                        T* Cbase, hipStream_t s);
 
 // Set-up helpers for the per-order tables (see api.cpp):
@@ -137,10 +134,18 @@ hipError_t launch_sweep_fwd(Blocks4<T> U, Blocks4<const T> G, const GroupDims& g
 template <class T>
 hipError_t launch_sweep_bwd(Blocks4<T> U, Blocks4<const T> G, const GroupDims& g, hipStream_t s);
 
-// U (a_l^m after the sweeps) -> packed complex128 alm; accumulate adds.
+// U (a_l^m after the sweeps) -> packed complex128 alm; with Ub.p[0] non-null
+// writes Ua + Ub (added in FP64).  `tiles`: the device copy of pack_tiles(p),
+// `ntiles` its number of (m, l0) pairs.
 template <class T>
-hipError_t launch_pack(Blocks4<const T> U, double* alm, const int64_t* alm_off, const int32_t* lmax,
-                       const GroupDims& g, bool accumulate, hipStream_t s);
+hipError_t launch_pack(Blocks4<const T> Ua, Blocks4<const T> Ub, double* alm, const int64_t* alm_off,
+                       const int32_t* lmax, const int32_t* tiles, int ntiles, const GroupDims& g, hipStream_t s);
+// (m, l0) of every pack tile: orders m = 0..p, l0 = m, m + 64, ... <= p.
+std::vector<int32_t> pack_tiles(int p);
+
+// FP32 U -> FP64 U in the same layout, zero outside m <= l <= lmax(map).
+hipError_t launch_widen(Blocks4<const float> Ua, Blocks4<double> U, const int32_t* lmax, const GroupDims& g,
+                        hipStream_t s);
 
 // packed complex128 alm -> U (zeros outside 0 <= m <= l <= lmax).
 hipError_t launch_unpack(const double* alm, const int64_t* alm_off, const int32_t* lmax, Blocks4<double> U,

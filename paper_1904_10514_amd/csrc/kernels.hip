@@ -276,12 +276,10 @@ __device__ __forceinline__ void ring_spectrum(const double* x, int n, bool shift
     // The next transform's first pass synchronises before it writes the buffer.
 }
 
-// DUAL: also write the rows rounded to FP32 into D2 (the FP32 analysis input
-// of the refinement, whose FP64 rows form the residual).
-template <class T, int NT, bool DUAL>
+template <class T, int NT>
 __global__ __launch_bounds__(NT) void k_ring_forward(const double* __restrict__ maps,
                                                      const int64_t* __restrict__ map_off, RingTab rt, FftTab<T> ft,
-                                                     Blocks4<T> D, Blocks4<float> D2, GroupDims g) {
+                                                     Blocks4<T> D, GroupDims g) {
     extern __shared__ unsigned char smem_raw[];
     C2<T>* buf = reinterpret_cast<C2<T>*>(smem_raw);
     int b, h;
@@ -319,14 +317,6 @@ __global__ __launch_bounds__(NT) void k_ring_forward(const double* __restrict__ 
         bp[row + col + 1] = dp.y;
         bm[row + col] = dm.x;
         bm[row + col + 1] = dm.y;
-        if constexpr (DUAL) {
-            float* fp = D2.p[2 * kpar + 0];
-            float* fm = D2.p[2 * kpar + 1];
-            fp[row + col] = float(dp.x);
-            fp[row + col + 1] = float(dp.y);
-            fm[row + col] = float(dm.x);
-            fm[row + col + 1] = float(dm.y);
-        }
     }
 }
 
@@ -339,24 +329,10 @@ hipError_t launch_ring_forward(const double* maps, const int64_t* map_off, RingT
                                const GroupDims& g, hipStream_t s) {
     dim3 grid(g.nmaps, 2 * g.nside);
     const size_t shm = ring_lds_bytes(ft.fft_max, sizeof(C2<T>));
-    const Blocks4<float> none{};
     if (ring_threads(ft.fft_max) == 256)
-        hipLaunchKernelGGL((k_ring_forward<T, 256, false>), grid, dim3(256), shm, s, maps, map_off, rt, ft, D, none, g);
+        hipLaunchKernelGGL((k_ring_forward<T, 256>), grid, dim3(256), shm, s, maps, map_off, rt, ft, D, g);
     else
-        hipLaunchKernelGGL((k_ring_forward<T, 512, false>), grid, dim3(512), shm, s, maps, map_off, rt, ft, D, none, g);
-    return hipGetLastError();
-}
-
-hipError_t launch_ring_forward_dual(const double* maps, const int64_t* map_off, RingTab rt, FftTab<double> ft,
-                                    Blocks4<double> D, Blocks4<float> D32, const GroupDims& g, hipStream_t s) {
-    dim3 grid(g.nmaps, 2 * g.nside);
-    const size_t shm = ring_lds_bytes(ft.fft_max, sizeof(C2<double>));
-    if (ring_threads(ft.fft_max) == 256)
-        hipLaunchKernelGGL((k_ring_forward<double, 256, true>), grid, dim3(256), shm, s, maps, map_off, rt, ft, D, D32,
-                           g);
-    else
-        hipLaunchKernelGGL((k_ring_forward<double, 512, true>), grid, dim3(512), shm, s, maps, map_off, rt, ft, D, D32,
-                           g);
+        hipLaunchKernelGGL((k_ring_forward<T, 512>), grid, dim3(512), shm, s, maps, map_off, rt, ft, D, g);
     return hipGetLastError();
 }
 
@@ -444,9 +420,10 @@ struct alignas(2 * sizeof(T)) V2 {
 // through double-buffered LDS tiles, the next step's global loads in flight
 // while the current one is multiplied.  B and C columns come in (re, im)
 // pairs: column n lives at (n >> 1) * pair_stride + (n & 1).
-template <class T>
+// TB: storage type of B (FP64 B is rounded to T as it is staged).
+template <class T, class TB>
 __global__ __launch_bounds__(256) void k_gemm(const GemmProblem<T>* __restrict__ probs,
-                                              const int32_t* __restrict__ tmap, const T* __restrict__ Bbase,
+                                              const int32_t* __restrict__ tmap, const TB* __restrict__ Bbase,
                                               T* __restrict__ Cbase) {
     __shared__ T As[2][GBK][GBM + GPAD];
     __shared__ T Bs[2][GBK][GBN + GPAD];
@@ -456,7 +433,7 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmProblem<T>* __restrict__
     const int tile = tmap[2 * blockIdx.x + 1];
     const int tm = tile / P.tiles_n, tn = tile % P.tiles_n;
     const int m0 = tm * GBM, n0 = tn * GBN;
-    const T* B = Bbase + P.boff;
+    const TB* B = Bbase + P.boff;
     T* C = Cbase + P.coff;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
@@ -494,14 +471,14 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmProblem<T>* __restrict__
                 ra[e] = (krow && mm < P.M) ? arow[mm] : T(0);
             }
         }
-        const T* brow = B + int64_t(k) * P.ldb;
+        const TB* brow = B + int64_t(k) * P.ldb;
 #pragma unroll
         for (int e = 0; e < 8; e += 2) {
             const int nn = n0 + lc + e;
-            V2<T> v{};
-            if (krow && nn < P.N) v = *reinterpret_cast<const V2<T>*>(brow + int64_t(nn >> 1) * P.bps);
-            rb[e] = v.v[0];
-            rb[e + 1] = v.v[1];
+            V2<TB> v{};
+            if (krow && nn < P.N) v = *reinterpret_cast<const V2<TB>*>(brow + int64_t(nn >> 1) * P.bps);
+            rb[e] = T(v.v[0]);
+            rb[e + 1] = T(v.v[1]);
         }
     };
     auto lstore = [&](int buf) {
@@ -589,11 +566,11 @@ std::vector<int32_t> xcd_tile_map(const GemmProblem<T>* p, int n) {
     return out;
 }
 
-template <class T>
-hipError_t launch_gemm(const GemmProblem<T>* probs_dev, const int32_t* tmap_dev, int nslots, const T* Bbase,
+template <class T, class TB>
+hipError_t launch_gemm(const GemmProblem<T>* probs_dev, const int32_t* tmap_dev, int nslots, const TB* Bbase,
                        T* Cbase, hipStream_t s) {
     if (nslots == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_gemm<T>, dim3(nslots), dim3(256), 0, s, probs_dev, tmap_dev, Bbase, Cbase);
+    hipLaunchKernelGGL((k_gemm<T, TB>), dim3(nslots), dim3(256), 0, s, probs_dev, tmap_dev, Bbase, Cbase);
     return hipGetLastError();
 }
 
@@ -979,39 +956,108 @@ __device__ __forceinline__ bool pack_index(const GroupDims& g, int blk, int64_t 
     return true;
 }
 
+// Pack through an LDS tile: one workgroup per (order m, 64 consecutive l,
+// 32 consecutive maps).  The two parity blocks of m (even and odd l) are
+// read row by row (each row a contiguous run of maps in the mode-major
+// layout) and every map's 64 a_l^m are written as one contiguous run of
+// alm.  With Ub given, writes Ua + Ub (the refined a_lm), added in FP64.
+constexpr int kPackL = 64, kPackMaps = 32;
+
 template <class T>
-__global__ void k_pack(Blocks4<const T> U, double* __restrict__ alm, const int64_t* __restrict__ alm_off,
-                       const int32_t* __restrict__ lmaxv, GroupDims g, int accumulate) {
-    const int blk = blockIdx.y;
-    const int kpar = blk >> 1;
-    int map, lp, kk;
-    if (!pack_index(g, blk, int64_t(blockIdx.x) * blockDim.x + threadIdx.x, map, lp, kk)) return;
-    const int l = g.lmin[blk] + 2 * lp, m = 2 * kk + kpar;
-    const int L = lmaxv[map];
-    if (l < m || l > L) return;
-    const T* src = U.p[blk] + int64_t(lp) * g.N[kpar] + int64_t(map) * g.cm[kpar] + int64_t(kk) * g.ck[kpar];
-    const int64_t o = 2 * (alm_off[map] + int64_t(m) * (2 * L + 1 - m) / 2 + l);
-    const double re = double(src[0]), im = double(src[1]);
-    if (accumulate) {
-        alm[o] += re;
-        alm[o + 1] += im;
-    } else {
-        alm[o] = re;
-        alm[o + 1] = im;
+__global__ __launch_bounds__(256) void k_pack(Blocks4<const T> Ua, Blocks4<const T> Ub, double* __restrict__ alm,
+                                              const int64_t* __restrict__ alm_off, const int32_t* __restrict__ lmaxv,
+                                              const int32_t* __restrict__ tiles, GroupDims g) {
+    __shared__ C2<double> tile[kPackL][kPackMaps + 1];
+    const int m = tiles[2 * blockIdx.x], l0 = tiles[2 * blockIdx.x + 1];
+    const int v0 = blockIdx.y * kPackMaps;
+    const int kpar = m & 1, kk = m >> 1;
+    const bool two = Ub.p[0] != nullptr;
+    for (int i = threadIdx.x; i < kPackL * kPackMaps; i += 256) {
+        const int vi = i % kPackMaps, li = i / kPackMaps;
+        const int v = v0 + vi, l = l0 + li;
+        C2<double> z = {0.0, 0.0};
+        if (v < g.nmaps && l <= g.p) {
+            // the block of order parity kpar whose l have the parity of l
+            const int blk = 2 * kpar + ((l & 1) == (g.lmin[2 * kpar] & 1) ? 0 : 1);
+            const int lp = (l - g.lmin[blk]) >> 1;
+            const int64_t o = int64_t(lp) * g.N[kpar] + int64_t(v) * g.cm[kpar] + int64_t(kk) * g.ck[kpar];
+            const T* pa = Ua.p[blk] + o;
+            z = {double(pa[0]), double(pa[1])};
+            if (two) {
+                const T* pb = Ub.p[blk] + o;
+                z = {z.x + double(pb[0]), z.y + double(pb[1])};
+            }
+        }
+        tile[li][vi] = z;
     }
+    __syncthreads();
+    for (int i = threadIdx.x; i < kPackL * kPackMaps; i += 256) {
+        const int li = i % kPackL, vi = i / kPackL;
+        const int v = v0 + vi, l = l0 + li;
+        if (v >= g.nmaps) continue;
+        const int L = lmaxv[v];
+        if (l > L) continue;
+        const int64_t o = 2 * (alm_off[v] + int64_t(m) * (2 * L + 1 - m) / 2 + l);
+        const C2<double> z = tile[li][vi];
+        *reinterpret_cast<D2*>(alm + o) = D2{z.x, z.y};
+    }
+}
+
+std::vector<int32_t> pack_tiles(int p) {
+    std::vector<int32_t> t;
+    for (int m = 0; m <= p; ++m)
+        for (int l0 = m; l0 <= p; l0 += kPackL) {
+            t.push_back(m);
+            t.push_back(l0);
+        }
+    return t;
+}
+
+template <class T>
+hipError_t launch_pack(Blocks4<const T> Ua, Blocks4<const T> Ub, double* alm, const int64_t* alm_off,
+                       const int32_t* lmax, const int32_t* tiles, int ntiles, const GroupDims& g, hipStream_t s) {
+    dim3 grid(unsigned(ntiles), unsigned((g.nmaps + kPackMaps - 1) / kPackMaps));
+    hipLaunchKernelGGL(k_pack<T>, grid, dim3(256), 0, s, Ua, Ub, alm, alm_off, lmax, tiles, g);
+    return hipGetLastError();
+}
+
+// U (FP32) -> U (FP64) in the same layout, zero where l < m or l > lmax of
+// the column's map (what unpacking the packed a_lm would give).
+__global__ void k_widen(Blocks4<const float> Ua, Blocks4<double> U, const int32_t* __restrict__ lmaxv, GroupDims g) {
+    const int blk = blockIdx.y, kpar = blk >> 1;
+    const int64_t pairs = g.N[kpar] >> 1;
+    const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= int64_t(g.nl[blk]) * pairs) return;
+    const int lp = int(e / pairs);
+    const int64_t q = e % pairs;
+    int map, kk;
+    if (g.modemajor) {
+        kk = int(q / g.nmaps);
+        map = int(q % g.nmaps);
+    } else {
+        const int per = g.Npm[kpar] >> 1;
+        map = int(q / per);
+        kk = int(q % per);
+    }
+    const int l = g.lmin[blk] + 2 * lp, m = 2 * kk + kpar;
+    const int64_t o = int64_t(lp) * g.N[kpar] + 2 * q;
+    D2 v = {0.0, 0.0};
+    if (kk < g.nk[blk] && l >= m && l <= lmaxv[map]) v = {double(Ua.p[blk][o]), double(Ua.p[blk][o + 1])};
+    *reinterpret_cast<D2*>(U.p[blk] + o) = v;
+}
+
+hipError_t launch_widen(Blocks4<const float> Ua, Blocks4<double> U, const int32_t* lmax, const GroupDims& g,
+                        hipStream_t s) {
+    int64_t most = 0;
+    for (int b = 0; b < 4; ++b) most = std::max<int64_t>(most, int64_t(g.nl[b]) * (g.N[b >> 1] >> 1));
+    hipLaunchKernelGGL(k_widen, dim3(unsigned((most + 255) / 256), 4), dim3(256), 0, s, Ua, U, lmax, g);
+    return hipGetLastError();
 }
 
 static dim3 pack_grid(const GroupDims& g) {
     int64_t most = 0;
     for (int b = 0; b < 4; ++b) most = std::max<int64_t>(most, int64_t(g.nk[b]) * g.nl[b] * g.nmaps);
     return dim3(unsigned((most + 255) / 256), 4);
-}
-
-template <class T>
-hipError_t launch_pack(Blocks4<const T> U, double* alm, const int64_t* alm_off, const int32_t* lmax,
-                       const GroupDims& g, bool accumulate, hipStream_t s) {
-    hipLaunchKernelGGL(k_pack<T>, pack_grid(g), dim3(256), 0, s, U, alm, alm_off, lmax, g, accumulate ? 1 : 0);
-    return hipGetLastError();
 }
 
 __global__ void k_unpack(const double* __restrict__ alm, const int64_t* __restrict__ alm_off,
@@ -1370,12 +1416,10 @@ hipError_t launch_cl(const double* alm, const int64_t* alm_off, const int32_t* l
 hipError_t configure_kernels() {
     const int bytes = 160 * 1024;
     const void* fns[] = {
-        reinterpret_cast<const void*>(&k_ring_forward<double, 256, false>),
-        reinterpret_cast<const void*>(&k_ring_forward<double, 512, false>),
-        reinterpret_cast<const void*>(&k_ring_forward<double, 256, true>),
-        reinterpret_cast<const void*>(&k_ring_forward<double, 512, true>),
-        reinterpret_cast<const void*>(&k_ring_forward<float, 256, false>),
-        reinterpret_cast<const void*>(&k_ring_forward<float, 512, false>),
+        reinterpret_cast<const void*>(&k_ring_forward<double, 256>),
+        reinterpret_cast<const void*>(&k_ring_forward<double, 512>),
+        reinterpret_cast<const void*>(&k_ring_forward<float, 256>),
+        reinterpret_cast<const void*>(&k_ring_forward<float, 512>),
         reinterpret_cast<const void*>(&k_ring_inverse<256>),
         reinterpret_cast<const void*>(&k_ring_inverse<512>),
 
@@ -1394,10 +1438,12 @@ template hipError_t launch_ring_forward<float>(const double*, const int64_t*, Ri
                                                Blocks4<float>, const GroupDims&, hipStream_t);
 template hipError_t launch_pole<double>(Blocks4<double>, const GroupDims&, double, double, double, hipStream_t);
 template hipError_t launch_pole<float>(Blocks4<float>, const GroupDims&, double, double, double, hipStream_t);
-template hipError_t launch_gemm<double>(const GemmProblem<double>*, const int32_t*, int, const double*, double*,
-                                       hipStream_t);
-template hipError_t launch_gemm<float>(const GemmProblem<float>*, const int32_t*, int, const float*, float*,
-                                      hipStream_t);
+template hipError_t launch_gemm<double, double>(const GemmProblem<double>*, const int32_t*, int, const double*,
+                                               double*, hipStream_t);
+template hipError_t launch_gemm<float, float>(const GemmProblem<float>*, const int32_t*, int, const float*, float*,
+                                             hipStream_t);
+template hipError_t launch_gemm<float, double>(const GemmProblem<float>*, const int32_t*, int, const double*, float*,
+                                              hipStream_t);
 template std::vector<int32_t> xcd_tile_map<double>(const GemmProblem<double>*, int);
 template std::vector<int32_t> xcd_tile_map<float>(const GemmProblem<float>*, int);
 template int finalize_gemm_problems<double>(GemmProblem<double>*, int);
@@ -1409,9 +1455,9 @@ template hipError_t launch_scatter_tables<double>(const double*, int, int, int, 
 template hipError_t launch_sweep_fwd<double>(Blocks4<double>, Blocks4<const double>, const GroupDims&, hipStream_t);
 template hipError_t launch_sweep_fwd<float>(Blocks4<float>, Blocks4<const float>, const GroupDims&, hipStream_t);
 template hipError_t launch_sweep_bwd<double>(Blocks4<double>, Blocks4<const double>, const GroupDims&, hipStream_t);
-template hipError_t launch_pack<double>(Blocks4<const double>, double*, const int64_t*, const int32_t*,
-                                        const GroupDims&, bool, hipStream_t);
-template hipError_t launch_pack<float>(Blocks4<const float>, double*, const int64_t*, const int32_t*,
-                                       const GroupDims&, bool, hipStream_t);
+template hipError_t launch_pack<double>(Blocks4<const double>, Blocks4<const double>, double*, const int64_t*,
+                                        const int32_t*, const int32_t*, int, const GroupDims&, hipStream_t);
+template hipError_t launch_pack<float>(Blocks4<const float>, Blocks4<const float>, double*, const int64_t*,
+                                       const int32_t*, const int32_t*, int, const GroupDims&, hipStream_t);
 
 }  // namespace hp2sph
