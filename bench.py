@@ -70,7 +70,7 @@ def order_gemm_flops(nside, nmaps, synthesis):
     return tot
 
 
-def stage_work(stage, nside, nmaps, tsize, strategy="staged"):
+def stage_work(stage, nside, nmaps, tsize, strategy="staged", mode="f64"):
     """(kind, amount) algorithmic work of one launch: ('flop', n) or ('byte', n)."""
     p, nl, nk = block_dims(nside)
     K = 2 * nside + 1
@@ -91,10 +91,17 @@ def stage_work(stage, nside, nmaps, tsize, strategy="staged"):
         return "byte", rows * 8 + npix * 8
     if stage == "residual_fold":
         return "byte", rows * (8 + 8 + 4)
+    u_vals = sum(nl[b] * N[b >> 1] for b in range(4))   # values of the U blocks (rectangle)
+    n_alm = (p + 1) * (p + 2) // 2 * nmaps                # a_l^m, m <= l <= p: the live U entries
+    alm_bytes = n_alm * 16
     if stage == "pack":
-        return "byte", sum(nl[b] * N[b >> 1] for b in range(4)) * tsize + (p + 1) * (p + 2) // 2 * 16 * nmaps
+        # the refinement packs a0 + correction: two FP32 U reads
+        n_in = 2 if mode == "f32_refine" else 1
+        return "byte", n_in * n_alm * 2 * tsize + alm_bytes
     if stage == "unpack":
-        return "byte", sum(nl[b] * N[b >> 1] for b in range(4)) * 8 + (p + 1) * (p + 2) // 2 * 16 * nmaps
+        if mode == "f32_refine":   # FP32 a0 widened to FP64 (the whole U rectangle is written)
+            return "byte", n_alm * 2 * 4 + u_vals * 8
+        return "byte", alm_bytes + u_vals * 8
     if stage == "cl":
         return "byte", (p + 1) * (p + 2) // 2 * 16 * nmaps
     return "byte", 0
@@ -119,7 +126,7 @@ def stage_dtype(stage, mode):
 
 def roofline(stage, mode, nside, nmaps, ms_total, launches, strategy="staged"):
     dt = stage_dtype(stage, mode)
-    kind, amount = stage_work(stage, nside, nmaps, 4 if dt == "f32" else 8, strategy)
+    kind, amount = stage_work(stage, nside, nmaps, 4 if dt == "f32" else 8, strategy, mode)
     avg_s = ms_total / launches / 1e3
     bound = stage_bound(stage)
     if bound == "hbm":
