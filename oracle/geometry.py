@@ -34,7 +34,8 @@ def ring_table(nside):
 
     Returns a dict of numpy arrays:
       z      cos(theta_r)
-      theta  theta_r = arccos(z) (colatitude)
+      one_minus_abs_z  1 - |z| (exact form j^2 / (3 Nside^2) on the caps)
+      theta  theta_r (colatitude), 2 arcsin(sqrt((1 - |z|)/2)) or pi minus it
       n      number of points on the ring
       phi0   longitude of the first point
       start  index of the first pixel of the ring in the RING-ordered map
@@ -43,27 +44,35 @@ def ring_table(nside):
         raise ValueError("nside must be a power of two >= 2")
     nr = 4 * nside - 1
     z = np.empty(nr)
+    omz = np.empty(nr)                     # 1 - |z|, from its exact form (no cancellation)
     n = np.empty(nr, dtype=np.int64)
     phi0 = np.empty(nr)
     ns2 = 3.0 * nside * nside
     for r in range(1, nr + 1):
         if r < nside:                      # north polar cap, j = r
             j = r
-            z[r - 1] = 1.0 - j * j / ns2
+            omz[r - 1] = j * j / ns2
+            z[r - 1] = 1.0 - omz[r - 1]
             n[r - 1] = 4 * j
             phi0[r - 1] = np.pi * 0.5 / (2 * j)
         elif r <= 3 * nside:               # equatorial belt
             z[r - 1] = 2.0 * (2 * nside - r) / (3.0 * nside)
+            omz[r - 1] = 1.0 - abs(z[r - 1])
             n[r - 1] = 4 * nside
             phi0[r - 1] = np.pi * (((r + 1) % 2) / 2.0) / (2 * nside)
         else:                              # south polar cap, j = 4 Nside - r
             j = 4 * nside - r
-            z[r - 1] = -(1.0 - j * j / ns2)
+            omz[r - 1] = j * j / ns2
+            z[r - 1] = -(1.0 - omz[r - 1])
             n[r - 1] = 4 * j
             phi0[r - 1] = np.pi * 0.5 / (2 * j)
     start = np.zeros(nr, dtype=np.int64)
     start[1:] = np.cumsum(n)[:-1]
-    return {"z": z, "theta": np.arccos(z), "n": n, "phi0": phi0, "start": start}
+    # theta from 1 - |z| (2 arcsin sqrt((1 - |z|) / 2) is well conditioned at
+    # the poles, where arccos of the rounded z loses most digits)
+    half = 2.0 * np.arcsin(np.sqrt(omz / 2.0))
+    theta = np.where(z >= 0.0, half, np.pi - half)
+    return {"z": z, "one_minus_abs_z": omz, "theta": theta, "n": n, "phi0": phi0, "start": start}
 
 
 def pixel_angles(nside):

@@ -106,7 +106,7 @@ def upsampled_grid(f, nside):
 # Pole values
 # --------------------------------------------------------------------------
 
-def _quadratic_basis(xyz, pole_z):
+def _quadratic_basis(xyz, t):
     """Polynomials of degree <= 2 in x, y, z restricted to the sphere.
 
     With t = 1 - z * pole_z (the distance in z from the pole) the
@@ -114,9 +114,9 @@ def _quadratic_basis(xyz, pole_z):
     x^2 - y^2, x y} (on the sphere x^2 + y^2 = 2t - t^2 and z = pole_z (1 - t)),
     a basis free of the near-collinear columns that monomials in z have close
     to the pole.  Every function except the constant vanishes at the pole.
+    t is passed in from the exact ring geometry (1 - |z| of the cap rings).
     """
     x, y = xyz[:, 0], xyz[:, 1]
-    t = 1.0 - xyz[:, 2] * pole_z
     return np.stack([np.ones_like(x), t, t * t, x, y, x * t, y * t, x * x - y * y, x * y], axis=1)
 
 
@@ -132,9 +132,10 @@ def pole_values(f, nside):
     f = np.asarray(f, dtype=np.float64)
     nr = len(rt["n"])
     res = []
-    for rings, pole_z in (((0, 1, 2), 1.0), ((nr - 1, nr - 2, nr - 3), -1.0)):
+    for rings in ((0, 1, 2), (nr - 1, nr - 2, nr - 3)):
         idx = np.concatenate([np.arange(rt["start"][r], rt["start"][r] + rt["n"][r]) for r in rings])
-        M = _quadratic_basis(xyz[idx], pole_z)
+        t = np.concatenate([np.full(rt["n"][r], rt["one_minus_abs_z"][r]) for r in rings])
+        M = _quadratic_basis(xyz[idx], t)
         scale = np.max(np.abs(M), axis=0)
         coef, *_ = np.linalg.lstsq(M / scale[None, :], f[idx], rcond=None)
         res.append(float(coef[0] / scale[0]))
