@@ -242,6 +242,55 @@ def cpu_baseline(f_host, nside, nsample=16):
             "seconds_timed": t_cols + t_rings}
 
 
+def uneven_main(args):
+    """The batching form: 256 maps of seeded uneven nside in {64, 128, 256, 512},
+    lmax = 2 nside, C_l = l^-2 exp(-l(l+1) s^2), one plan for the whole batch.
+    Prints its own JSON line (a secondary measurement, not the headline)."""
+    import numpy as np
+    import torch
+    import workloads as W
+    import paper_1904_10514_amd as P
+    nsides = [int(v) for v in W.uneven_nsides(256, 3)]
+    lmaxs = [2 * v for v in nsides]
+    alm = np.concatenate([W.draw_alm(W.spectrum(3, L), L, W.rng_for(3, i)) for i, L in enumerate(lmaxs)])
+    syn = P.Plan(nsides, lmaxs, mode="f64", strategy="staged")
+    maps = syn.synthesize(torch.from_numpy(alm).cuda())
+    torch.cuda.synchronize()
+    syn.close()
+    del syn
+    res = {}
+    for mode in [m for m in args.modes.split(",") if m]:
+        t0 = time.perf_counter()
+        plan = P.Plan(nsides, lmaxs, mode=mode, strategy=args.strategy)
+        setup = time.perf_counter() - t0
+        out = torch.empty(plan.alm_total, dtype=torch.complex128, device="cuda")
+        cl = torch.empty(plan.cl_total, dtype=torch.float64, device="cuda")
+        for _ in range(args.warmup):
+            plan.analyze(maps, out=out)
+            plan.power_spectrum(out, out=cl)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            plan.analyze(maps, out=out)
+            plan.power_spectrum(out, out=cl)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        res[mode] = {"maps_per_s": len(nsides) * args.steps / dt, "ms_per_step": 1e3 * dt / args.steps,
+                     "setup_s": setup, "strategy": plan.strategy}
+        print(f"[bench] uneven {mode}: {1e3 * dt / args.steps:.2f} ms/step", file=sys.stderr, flush=True)
+        plan.close()
+        del plan
+    counts = {int(n): nsides.count(n) for n in sorted(set(nsides))}
+    head = res.get("f32_refine") or next(iter(res.values()))
+    print(json.dumps({"metric": "maps analysed/s, uneven batch (batching form)", "value": head["maps_per_s"],
+                      "unit": "maps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+                      "ms_per_step": head["ms_per_step"], "higher_is_better": True, "data": "synthetic",
+                      "config": {"workload": "uneven_b256_nside64-512", "batch": len(nsides), "nside_counts": counts,
+                                 "lmax": "2 nside",
+                                 "input": "seeded Gaussian a_lm, C_l=l^-2 exp(-l(l+1)s^2), s=0.005, GPU FP64 synthesis"},
+                      "modes": res}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -253,11 +302,16 @@ def main():
     ap.add_argument("--strategy", default="auto", choices=["auto", "staged", "tables"])
     ap.add_argument("--modes", default="f32_refine,f64",
                     help="precision modes to time; the headline is f32_refine (profiling runs may pick one)")
+    ap.add_argument("--workload", default="headline", choices=["headline", "uneven"],
+                    help="headline: 64 maps of nside 1024; uneven: 256 maps of nside 64..512 (secondary)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (maps of a batch "
               "are independent and would be sharded across GPUs with no communication).", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "uneven":
+        uneven_main(args)
+        return
 
     import numpy as np
     import torch
