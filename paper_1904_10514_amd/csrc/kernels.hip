@@ -417,24 +417,15 @@ struct alignas(2 * sizeof(T)) V2 {
 
 // C[m][n] = sum_k A[k][m] B[k][n] for a list of problems; one 128 x 128 tile
 // of one problem per workgroup (4 waves of 64 x 64 each), k in steps of 16
-// through double-buffered LDS tiles, the next step's global loads in flight
-// while the current one is multiplied.  B and C columns come in (re, im)
-// pairs: column n lives at (n >> 1) * pair_stride + (n & 1).
-// TB: storage type of B (FP64 B is rounded to T as it is staged).
-template <class T, class TB>
-__global__ __launch_bounds__(256) void k_gemm(const GemmProblem<T>* __restrict__ probs,
-                                              const int32_t* __restrict__ tmap, const TB* __restrict__ Bbase,
-                                              T* __restrict__ Cbase) {
-    __shared__ T As[2][GBK][GBM + GPAD];
-    __shared__ T Bs[2][GBK][GBN + GPAD];
-    const int pi = tmap[2 * blockIdx.x];
-    if (pi < 0) return;
-    const GemmProblem<T> P = probs[pi];
-    const int tile = tmap[2 * blockIdx.x + 1];
-    const int tm = tile / P.tiles_n, tn = tile % P.tiles_n;
-    const int m0 = tm * GBM, n0 = tn * GBN;
-    const TB* B = Bbase + P.boff;
-    T* C = Cbase + P.coff;
+// through double-buffered LDS tiles, global loads issued ahead of use.  B and C columns come in (re, im)
+// pairs: column n lives at (n >> 1) * pair_stride + (n & 1).  A wave whose
+// 16-row blocks lie past the problem's last row skips their MFMAs (NI = number
+// of live 16-row blocks of the wave, a template argument so that the block
+// loops stay unrolled).
+template <class T, class TB, int NI>
+__device__ __forceinline__ void gemm_tile(const GemmProblem<T>& P, int m0, int n0, const TB* __restrict__ B,
+                                          T* __restrict__ C, T (*As)[GBK][GBM + GPAD],
+                                          T (*Bs)[GBK][GBN + GPAD]) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
     using Acc = MfmaAcc<T>;
@@ -445,43 +436,78 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmProblem<T>* __restrict__
         for (int j = 0; j < 4; ++j) acc[i][j] = typename Acc::V{0, 0, 0, 0};
 
     // Each thread stages 8 consecutive elements of one k row of each tile.
+    // FP32 loads are unconditional (a row or column outside the problem reads
+    // the problem's first element and is zeroed after the load), so they issue
+    // back to back without branches.
     constexpr int VE = 16 / sizeof(T);   // elements per 16-byte vector
     const int lr = tid >> 4;             // 0..15
     const int lc = (tid & 15) * 8;       // 0..120
     // A rows are read as 16-byte vectors when the row stride and base allow it
     const bool avec = (P.lda % VE) == 0 && (reinterpret_cast<uintptr_t>(P.A) % 16) == 0;
-    T ra[8], rb[8];
-    auto gload = [&](int k0) {
+    auto gload = [&](int k0, T (&ra)[8], T (&rb)[8]) {
         const int k = k0 + lr;
         const bool krow = k < P.K;
-        const T* arow = P.A + int64_t(k) * P.lda;
-        if (avec) {
+        if constexpr (sizeof(T) == 4) {
+            // unconditional loads (measured faster for the FP32 tiles)
+            const T* arow = P.A + int64_t(krow ? k : 0) * P.lda;
+            if (avec) {
 #pragma unroll
-            for (int e = 0; e < 8; e += VE) {
-                const int mm = m0 + lc + e;
-                V16<T> v{};
-                if (krow && mm < P.lda) v = *reinterpret_cast<const V16<T>*>(arow + mm);
+                for (int e = 0; e < 8; e += VE) {
+                    const int mm = m0 + lc + e;
+                    const bool ok = krow && mm < P.lda;
+                    V16<T> v = *reinterpret_cast<const V16<T>*>(ok ? arow + mm : P.A);
 #pragma unroll
-                for (int q = 0; q < VE; ++q) ra[e + q] = v.v[q];
+                    for (int q = 0; q < VE; ++q) ra[e + q] = ok ? v.v[q] : T(0);
+                }
+            } else {
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const int mm = m0 + lc + e;
+                    const bool ok = krow && mm < P.M;
+                    const T v = *(ok ? arow + mm : P.A);
+                    ra[e] = ok ? v : T(0);
+                }
+            }
+            const TB* brow = B + int64_t(krow ? k : 0) * P.ldb;
+#pragma unroll
+            for (int e = 0; e < 8; e += 2) {
+                const int nn = n0 + lc + e;
+                const bool ok = krow && nn < P.N;
+                const V2<TB> v = *reinterpret_cast<const V2<TB>*>(ok ? brow + int64_t(nn >> 1) * P.bps : B);
+                rb[e] = ok ? T(v.v[0]) : T(0);
+                rb[e + 1] = ok ? T(v.v[1]) : T(0);
             }
         } else {
+            // loads only where the tile overlaps the problem
+            const T* arow = P.A + int64_t(k) * P.lda;
+            if (avec) {
 #pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const int mm = m0 + lc + e;
-                ra[e] = (krow && mm < P.M) ? arow[mm] : T(0);
+                for (int e = 0; e < 8; e += VE) {
+                    const int mm = m0 + lc + e;
+                    V16<T> v{};
+                    if (krow && mm < P.lda) v = *reinterpret_cast<const V16<T>*>(arow + mm);
+#pragma unroll
+                    for (int q = 0; q < VE; ++q) ra[e + q] = v.v[q];
+                }
+            } else {
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const int mm = m0 + lc + e;
+                    ra[e] = (krow && mm < P.M) ? arow[mm] : T(0);
+                }
+            }
+            const TB* brow = B + int64_t(k) * P.ldb;
+#pragma unroll
+            for (int e = 0; e < 8; e += 2) {
+                const int nn = n0 + lc + e;
+                V2<TB> v{};
+                if (krow && nn < P.N) v = *reinterpret_cast<const V2<TB>*>(brow + int64_t(nn >> 1) * P.bps);
+                rb[e] = T(v.v[0]);
+                rb[e + 1] = T(v.v[1]);
             }
         }
-        const TB* brow = B + int64_t(k) * P.ldb;
-#pragma unroll
-        for (int e = 0; e < 8; e += 2) {
-            const int nn = n0 + lc + e;
-            V2<TB> v{};
-            if (krow && nn < P.N) v = *reinterpret_cast<const V2<TB>*>(brow + int64_t(nn >> 1) * P.bps);
-            rb[e] = T(v.v[0]);
-            rb[e + 1] = T(v.v[1]);
-        }
     };
-    auto lstore = [&](int buf) {
+    auto lstore = [&](int buf, const T (&ra)[8], const T (&rb)[8]) {
 #pragma unroll
         for (int e = 0; e < 8; e += VE) {
             V16<T> va, vb;
@@ -494,31 +520,61 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmProblem<T>* __restrict__
             *reinterpret_cast<V16<T>*>(&Bs[buf][lr][lc + e]) = vb;
         }
     };
-    const int nk = (P.K + GBK - 1) / GBK;
-    gload(0);
-    lstore(0);
-    __syncthreads();
-    for (int kt = 0; kt < nk; ++kt) {
-        const int cur = kt & 1;
-        if (kt + 1 < nk) gload((kt + 1) * GBK);
+    auto compute = [&](int cur) {
+        if constexpr (NI > 0) {
 #pragma unroll
-        for (int kk = 0; kk < GBK / 4; ++kk) {
-            const int kr = kk * 4 + (lane >> 4);
-            T a[4], b[4];
+            for (int kk = 0; kk < GBK / 4; ++kk) {
+                const int kr = kk * 4 + (lane >> 4);
+                T a[NI], b[4];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) a[i] = As[cur][kr][wm * 64 + i * 16 + (lane & 15)];
+                for (int i = 0; i < NI; ++i) a[i] = As[cur][kr][wm * 64 + i * 16 + (lane & 15)];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) b[j] = Bs[cur][kr][wn * 64 + j * 16 + (lane & 15)];
+                for (int j = 0; j < 4; ++j) b[j] = Bs[cur][kr][wn * 64 + j * 16 + (lane & 15)];
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+                for (int i = 0; i < NI; ++i)
 #pragma unroll
-                for (int j = 0; j < 4; ++j) acc[i][j] = Acc::mma(a[i], b[j], acc[i][j]);
+                    for (int j = 0; j < 4; ++j) acc[i][j] = Acc::mma(a[i], b[j], acc[i][j]);
+            }
         }
-        if (kt + 1 < nk) lstore(cur ^ 1);
+    };
+    // Step s of 16 k rows lives in LDS buffer s & 1.  FP32 stages it through
+    // register set s & 1 with its global loads issued two steps ahead; FP64
+    // (twice the accumulator registers) through one set, one step ahead.
+    const int nk = (P.K + GBK - 1) / GBK;
+    T ra0[8], rb0[8];
+    if constexpr (sizeof(T) == 4) {
+        T ra1[8], rb1[8];
+        gload(0, ra0, rb0);
+        lstore(0, ra0, rb0);
+        if (nk > 1) gload(GBK, ra1, rb1);
+        if (nk > 2) gload(2 * GBK, ra0, rb0);
         __syncthreads();
+        int kt = 0;
+        for (; kt + 1 < nk; kt += 2) {
+            compute(0);
+            lstore(1, ra1, rb1);
+            if (kt + 3 < nk) gload((kt + 3) * GBK, ra1, rb1);
+            __syncthreads();
+            compute(1);
+            if (kt + 2 < nk) lstore(0, ra0, rb0);
+            if (kt + 4 < nk) gload((kt + 4) * GBK, ra0, rb0);
+            __syncthreads();
+        }
+        if (kt < nk) compute(0);
+    } else {
+        gload(0, ra0, rb0);
+        lstore(0, ra0, rb0);
+        __syncthreads();
+        for (int kt = 0; kt < nk; ++kt) {
+            const int cur = kt & 1;
+            if (kt + 1 < nk) gload((kt + 1) * GBK, ra0, rb0);
+            compute(cur);
+            if (kt + 1 < nk) lstore(cur ^ 1, ra0, rb0);
+            __syncthreads();
+        }
     }
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < NI; ++i) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int nn = n0 + wn * 64 + j * 16 + (lane & 15);
@@ -529,6 +585,34 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmProblem<T>* __restrict__
                     C[int64_t(mm) * P.ldc + int64_t(nn >> 1) * P.cps + (nn & 1)] = acc[i][j][r];
             }
         }
+    }
+}
+
+// TB: storage type of B (FP64 B is rounded to T as it is staged).
+template <class T, class TB>
+__global__ __launch_bounds__(256, sizeof(T) == 8 ? 1 : 3) void k_gemm(const GemmProblem<T>* __restrict__ probs,
+                                              const int32_t* __restrict__ tmap, const TB* __restrict__ Bbase,
+                                              T* __restrict__ Cbase) {
+    __shared__ T As[2][GBK][GBM + GPAD];
+    __shared__ T Bs[2][GBK][GBN + GPAD];
+    const int pi = tmap[2 * blockIdx.x];
+    if (pi < 0) return;
+    const GemmProblem<T> P = probs[pi];
+    const int tile = tmap[2 * blockIdx.x + 1];
+    const int tm = tile / P.tiles_n, tn = tile % P.tiles_n;
+    const int m0 = tm * GBM, n0 = tn * GBN;
+    const TB* B = Bbase + P.boff;
+    T* C = Cbase + P.coff;
+    // live 16-row blocks of this wave's 64 rows (wave-uniform)
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int rows = P.M - m0 - (wave >> 1) * 64;
+    const int ni = rows <= 0 ? 0 : (rows >= 64 ? 4 : (rows + 15) / 16);
+    switch (ni) {
+        case 4: gemm_tile<T, TB, 4>(P, m0, n0, B, C, As, Bs); break;
+        case 3: gemm_tile<T, TB, 3>(P, m0, n0, B, C, As, Bs); break;
+        case 2: gemm_tile<T, TB, 2>(P, m0, n0, B, C, As, Bs); break;
+        case 1: gemm_tile<T, TB, 1>(P, m0, n0, B, C, As, Bs); break;
+        default: gemm_tile<T, TB, 0>(P, m0, n0, B, C, As, Bs); break;
     }
 }
 
