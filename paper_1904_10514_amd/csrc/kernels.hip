@@ -127,9 +127,27 @@ __device__ __forceinline__ void stockham_pass(C2<T>* buf, int M, int lgNs, const
 #pragma unroll
             for (int r = 0; r < R; ++r) v[i * R + r] = load(j + r * G);
             if (lgNs > 0) {
+                // w^r, r = 1..R-1, w = e^{-2 pi i (j mod Ns) / (Ns R)}: the
+                // powers 1, 2, 4, 8 from the table, the others as products of
+                // two or three of them (a few ulp)
                 const int st = (fft_max >> lgNs) / R * (j & (Ns - 1));
+                C2<T> w[R];
+                w[1] = ldc(tw, st);
+                if constexpr (R > 2) w[2] = ldc(tw, 2 * st);
+                if constexpr (R > 4) w[4] = ldc(tw, 4 * st);
+                if constexpr (R > 8) w[8] = ldc(tw, 8 * st);
+                if constexpr (R > 3) w[3] = cmul(w[2], w[1]);
+                if constexpr (R > 4) {
+                    w[5] = cmul(w[4], w[1]);
+                    w[6] = cmul(w[4], w[2]);
+                    w[7] = cmul(w[4], w[3]);
+                }
+                if constexpr (R > 8) {
 #pragma unroll
-                for (int r = 1; r < R; ++r) v[i * R + r] = cmul(v[i * R + r], ldc(tw, int64_t(st) * r));
+                    for (int r = 9; r < 16; ++r) w[r] = cmul(w[8], w[r - 8]);
+                }
+#pragma unroll
+                for (int r = 1; r < R; ++r) v[i * R + r] = cmul(v[i * R + r], w[r]);
             }
             dft_regs<T, R>(v + i * R);
         }
