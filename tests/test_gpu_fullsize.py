@@ -26,7 +26,7 @@ import torch
 import oracle as O
 import workloads as W
 import paper_1904_10514_amd as P
-from gpu_util import rel_err
+from gpu_util import order_one_fields, rel_err
 
 pytestmark = pytest.mark.gpu
 
@@ -92,30 +92,9 @@ def test_fullsize_f32_single_pass_sampled_orders(noise_batch):
     plan.close()
 
 
-def _order_one_fields():
-    """Real fields f = 2 Re(sum_l c_l Y_l^1), one per map, with seeded c_l."""
-    rt = O.ring_table(NSIDE)
-    pt = O.plm_orthonormal(LMAX, 1, rt["z"])                  # (LMAX, rings), l = 1 .. LMAX
-    l = np.arange(1, LMAX + 1)
-    coef = np.empty((BATCH, LMAX), dtype=np.complex128)
-    for v in range(BATCH):
-        rng = W.rng_for(10, v)
-        coef[v] = (rng.standard_normal(LMAX) + 1j * rng.standard_normal(LMAX)) / np.sqrt(2.0) / l
-    F = coef @ pt                                              # (BATCH, rings)
-    maps = np.empty((BATCH, _npix()))
-    for r in range(len(rt["n"])):
-        n, s0 = int(rt["n"][r]), int(rt["start"][r])
-        lam = rt["phi0"][r] + 2.0 * np.pi * np.arange(n) / n
-        maps[:, s0:s0 + n] = 2.0 * np.real(F[:, r:r + 1] * np.exp(1j * lam)[None, :]) / np.sqrt(2.0 * np.pi)
-    expect = np.zeros((BATCH, O.alm_size(LMAX)), dtype=np.complex128)
-    idx = np.array([O.alm_index(ll, 1, LMAX) for ll in range(1, LMAX + 1)])
-    expect[:, idx] = coef
-    return maps, expect
-
-
 @pytest.fixture(scope="module")
 def order_one_batch():
-    maps, expect = _order_one_fields()
+    maps, expect = order_one_fields(NSIDE, BATCH, 10)
     return torch.from_numpy(maps.reshape(-1)).cuda(), expect
 
 
