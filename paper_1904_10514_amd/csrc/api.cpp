@@ -676,7 +676,7 @@ int refine_pass(hp2sph_plan_t plan, Group& G, const double* maps, double* alm, v
     if (!G.tables) STAGE(3, launch_sweep_fwd<float>(Ua, Gv32, G.dims, s));
     // S a0 up to the inverse ring transform (FP64): a0 widened to FP64 (and
     // truncated at each map's lmax), then the synthesis GEMM
-    STAGE(5, launch_widen(cblocks(Ua), U64, G.d_lmax, G.dims, s));
+    STAGE(5, launch_widen(cblocks(Ua), U64, G.d_lmax, G.dims, G.tables, s));
     if (!G.tables) {
         Blocks4<const double> Gv;
         for (int b = 0; b < 4; ++b) Gv.p[b] = G.t64.givens[b];

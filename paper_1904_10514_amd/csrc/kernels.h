@@ -143,9 +143,10 @@ hipError_t launch_pack(Blocks4<const T> Ua, Blocks4<const T> Ub, double* alm, co
 // (m, l0) of every pack tile: orders m = 0..p, l0 = m, m + 64, ... <= p.
 std::vector<int32_t> pack_tiles(int p);
 
-// FP32 U -> FP64 U in the same layout, zero outside m <= l <= lmax(map).
+// FP32 U -> FP64 U in the same layout, zero outside m <= l <= lmax(map);
+// live_only leaves the rows l < m (never read by the per-order GEMMs) unwritten.
 hipError_t launch_widen(Blocks4<const float> Ua, Blocks4<double> U, const int32_t* lmax, const GroupDims& g,
-                        hipStream_t s);
+                        bool live_only, hipStream_t s);
 
 // packed complex128 alm -> U (zeros outside 0 <= m <= l <= lmax).
 hipError_t launch_unpack(const double* alm, const int64_t* alm_off, const int32_t* lmax, Blocks4<double> U,

@@ -1125,7 +1125,8 @@ hipError_t launch_pack(Blocks4<const T> Ua, Blocks4<const T> Ub, double* alm, co
 
 // U (FP32) -> U (FP64) in the same layout, zero where l < m or l > lmax of
 // the column's map (what unpacking the packed a_lm would give).
-__global__ void k_widen(Blocks4<const float> Ua, Blocks4<double> U, const int32_t* __restrict__ lmaxv, GroupDims g) {
+__global__ void k_widen(Blocks4<const float> Ua, Blocks4<double> U, const int32_t* __restrict__ lmaxv, GroupDims g,
+                        int live_only) {
     const int blk = blockIdx.y, kpar = blk >> 1;
     const int64_t pairs = g.N[kpar] >> 1;
     const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -1142,6 +1143,7 @@ __global__ void k_widen(Blocks4<const float> Ua, Blocks4<double> U, const int32_
         kk = int(q % per);
     }
     const int l = g.lmin[blk] + 2 * lp, m = 2 * kk + kpar;
+    if (live_only && l < m) return;   // rows below the order are never read
     const int64_t o = int64_t(lp) * g.N[kpar] + 2 * q;
     D2 v = {0.0, 0.0};
     if (kk < g.nk[blk] && l >= m && l <= lmaxv[map]) v = {double(Ua.p[blk][o]), double(Ua.p[blk][o + 1])};
@@ -1149,10 +1151,11 @@ __global__ void k_widen(Blocks4<const float> Ua, Blocks4<double> U, const int32_
 }
 
 hipError_t launch_widen(Blocks4<const float> Ua, Blocks4<double> U, const int32_t* lmax, const GroupDims& g,
-                        hipStream_t s) {
+                        bool live_only, hipStream_t s) {
     int64_t most = 0;
     for (int b = 0; b < 4; ++b) most = std::max<int64_t>(most, int64_t(g.nl[b]) * (g.N[b >> 1] >> 1));
-    hipLaunchKernelGGL(k_widen, dim3(unsigned((most + 255) / 256), 4), dim3(256), 0, s, Ua, U, lmax, g);
+    hipLaunchKernelGGL(k_widen, dim3(unsigned((most + 255) / 256), 4), dim3(256), 0, s, Ua, U, lmax, g,
+                       live_only ? 1 : 0);
     return hipGetLastError();
 }
 
@@ -1491,27 +1494,46 @@ hipError_t launch_residual_fold(Blocks4<const double> Df, Blocks4<const double> 
 // S5: C_l
 // ---------------------------------------------------------------------------
 
-__global__ void k_cl(const double* __restrict__ alm, const int64_t* __restrict__ alm_off,
-                     const int32_t* __restrict__ lmaxv, double* __restrict__ cl, const int64_t* __restrict__ cl_off) {
+// One workgroup per (32 consecutive l, map); 8 groups of 32 lanes split the
+// orders m = 0..l into 8 contiguous ranges (lanes of a group read 32
+// consecutive a_l^m of one order), and the 8 partial sums are added in a
+// fixed order, so C_l is bitwise reproducible.
+constexpr int kClL = 32, kClParts = 8;
+
+__global__ __launch_bounds__(kClL * kClParts) void k_cl(const double* __restrict__ alm,
+                                                        const int64_t* __restrict__ alm_off,
+                                                        const int32_t* __restrict__ lmaxv, double* __restrict__ cl,
+                                                        const int64_t* __restrict__ cl_off) {
+    __shared__ double part[kClParts][kClL];
     const int map = blockIdx.y;
     const int L = lmaxv[map];
-    const int l = blockIdx.x * blockDim.x + threadIdx.x;
-    if (l > L) return;
-    const double* a = alm + 2 * alm_off[map];
+    const int li = threadIdx.x % kClL, c = threadIdx.x / kClL;
+    const int l = blockIdx.x * kClL + li;
+    const int span = (L + kClParts) / kClParts;            // ceil((L + 1) / parts)
     double s = 0.0;
-    for (int m = 0; m <= l; ++m) {
-        const int64_t o = 2 * (int64_t(m) * (2 * L + 1 - m) / 2 + l);
-        const double re = a[o], im = a[o + 1];
-        const double v = re * re + im * im;
-        s += (m == 0) ? v : 2.0 * v;
+    if (l <= L) {
+        const double* a = alm + 2 * alm_off[map];
+        const int m_end = min(l, (c + 1) * span - 1);
+        for (int m = c * span; m <= m_end; ++m) {
+            const int64_t o = 2 * (int64_t(m) * (2 * L + 1 - m) / 2 + l);
+            const double re = a[o], im = a[o + 1];
+            const double v = re * re + im * im;
+            s += (m == 0) ? v : 2.0 * v;
+        }
     }
-    cl[cl_off[map] + l] = s / (2.0 * l + 1.0);
+    part[c][li] = s;
+    __syncthreads();
+    if (c == 0 && l <= L) {
+        double t = part[0][li];
+        for (int q = 1; q < kClParts; ++q) t += part[q][li];
+        cl[cl_off[map] + l] = t / (2.0 * l + 1.0);
+    }
 }
 
 hipError_t launch_cl(const double* alm, const int64_t* alm_off, const int32_t* lmax, double* cl,
                      const int64_t* cl_off, int nmaps, int lmax_max, hipStream_t s) {
-    dim3 grid(unsigned((lmax_max + 1 + 127) / 128), nmaps);
-    hipLaunchKernelGGL(k_cl, grid, dim3(128), 0, s, alm, alm_off, lmax, cl, cl_off);
+    dim3 grid(unsigned((lmax_max + kClL) / kClL), nmaps);
+    hipLaunchKernelGGL(k_cl, grid, dim3(kClL * kClParts), 0, s, alm, alm_off, lmax, cl, cl_off);
     return hipGetLastError();
 }
 
