@@ -37,6 +37,9 @@ __device__ __forceinline__ int bitrev(int v, int lg) { return lg == 0 ? 0 : int(
 struct alignas(16) D2 {
     double x, y;
 };
+struct alignas(8) F2 {
+    float x, y;
+};
 
 // LDS slot of FFT entry i: one pad slot every 16 entries, so that the
 // strided accesses of the Stockham passes spread over the banks.
@@ -1372,11 +1375,11 @@ hipError_t launch_ring_inverse(Blocks4<const double> D, RingTab rt, FftTab<doubl
 // The N and S rings of a pair share n and the shift, and D_k = D+ +- D-, so
 // one pass over the aliases gives both.
 //
-// A workgroup takes one ring pair of 8 consecutive maps; lane bits 0..2 pick
+// A workgroup takes one ring pair of 16 consecutive maps; lane bits 0..3 pick
 // the map, so that in the mode-major layout every access to one (row, mode)
 // is one contiguous run of 8 maps.
 
-constexpr int kFoldMaps = 8;
+constexpr int kFoldMaps = 16;
 
 template <int NT>
 __global__ __launch_bounds__(NT) void k_residual_fold(Blocks4<const double> Df, Blocks4<const double> Gs,
@@ -1469,7 +1472,27 @@ __global__ __launch_bounds__(NT) void k_residual_fold(Blocks4<const double> Df, 
         }
         for (int k = T1 + slot; k <= p; k += SL) emit(k, zero, zero);
     } else {
-        for (int k = slot; k <= p; k += SL) {
+        // Bins with a single alias and no mirror term (n > p, k < min(L, n - p)):
+        // X_k = D_k on both rings, so Dr = Df - Gs element by element (on the
+        // equator Gs- and Df- are zero).  This covers most of every row.
+        const int k_simple = (n > p) ? min(L, n - p) : 0;
+        int k = slot;
+        if (valid) {
+#pragma unroll 4
+            for (; k < k_simple; k += SL) {
+                const int64_t o = offs(k);
+                const int kp = k & 1;
+                const D2 gp = *reinterpret_cast<const D2*>(Gs.p[2 * kp] + o);
+                const D2 gm = *reinterpret_cast<const D2*>(Gs.p[2 * kp + 1] + o);
+                const D2 fp = *reinterpret_cast<const D2*>(Df.p[2 * kp] + o);
+                const D2 fm = *reinterpret_cast<const D2*>(Df.p[2 * kp + 1] + o);
+                *reinterpret_cast<F2*>(Dr.p[2 * kp] + o) = F2{float(fp.x - gp.x), float(fp.y - gp.y)};
+                *reinterpret_cast<F2*>(Dr.p[2 * kp + 1] + o) = F2{float(fm.x - gm.x), float(fm.y - gm.y)};
+            }
+        } else {
+            while (k < k_simple) k += SL;
+        }
+        for (; k <= p; k += SL) {
             if (k <= L) {
                 C2<double> SN, SS;
                 chains(k, 0, 1, SN, SS);
