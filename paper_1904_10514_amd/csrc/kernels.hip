@@ -1377,7 +1377,7 @@ hipError_t launch_ring_inverse(Blocks4<const double> D, RingTab rt, FftTab<doubl
 //
 // A workgroup takes one ring pair of 16 consecutive maps; lane bits 0..3 pick
 // the map, so that in the mode-major layout every access to one (row, mode)
-// is one contiguous run of 8 maps.
+// is one contiguous run of 16 maps.
 
 constexpr int kFoldMaps = 16;
 
