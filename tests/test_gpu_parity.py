@@ -17,6 +17,15 @@ import paper_1904_10514_amd as P   # noqa: E402
 # (FFT vs direct sums, QR-built tables vs QR lstsq, sweeps vs quadrature);
 # 1e-12 leaves ~100x headroom over the measured ~1e-14.
 TOL64 = 1e-12
+# FP32 + one FP64 refinement round vs the same recipe in FP64: the round
+# leaves the FP32 error of the first pass (eps32 = 6e-8 times the growth of the
+# p-term sums, measured 1.5-2.2e-7 for one pass) times I - A S, the method's own
+# error on the residual, whose norm reaches ~1 on white noise at small nside
+# (polar rings alias most modes), plus the FP32 error of the correction: 1e-6.
+# (Smooth maps land at 4e-10 - 1.5e-8.)  That the residual itself is formed in
+# FP64 is checked at full size on exactly recovered fields
+# (tests/test_gpu_fullsize.py), where the refined error must fall to 1e-10.
+TOL_REFINE = 1e-6
 
 
 def _dev(x):
@@ -129,7 +138,7 @@ def test_f32_refine_vs_refined_oracle(nside):
     e_plain = rel_err(a, plain)
     e_cl = float(np.max(np.abs(cl[2:] - clr[2:]) / clr[2:]))
     print(f"nside {nside}: vs O_ref {e_ref:.3e}, vs O_plain {e_plain:.3e}, rel C_l {e_cl:.3e}")
-    assert e_ref < 1e-5
+    assert e_ref < TOL_REFINE
 
 
 @pytest.mark.parametrize("nside", [16, 64])
@@ -174,7 +183,7 @@ def test_tables_f32_refine_vs_refined_oracle(nside):
     a = plan.analyze(_dev(f)).cpu().numpy()
     e = rel_err(a, O.analyze_refined(f, nside))
     print(f"tables f32+refine nside {nside}: vs O_ref {e:.3e}")
-    assert e < 1e-5
+    assert e < TOL_REFINE
 
 
 def test_tables_synthesis_path_in_refinement_matches_staged():
@@ -206,3 +215,31 @@ def test_tables_f64_plan_synthesis_uses_staged_path_correctly():
     for i in range(nb):
         ref = O.synthesize(a[i * sz:(i + 1) * sz], nside, lmax)
         assert rel_err(f[i * npx:(i + 1) * npx], ref) < TOL64
+
+
+@pytest.mark.parametrize("strategy", ["staged", "tables"])
+def test_f32_refine_truncated_lmax_vs_refined_oracle(strategy):
+    """lmax < p: the refinement synthesises a0 truncated at lmax (reading R15)."""
+    nside, lmax = 16, 25
+    f, _ = cmb_map(1, 700, nside)
+    plan = P.Plan(nside, lmax, batch=1, mode="f32_refine", strategy=strategy)
+    a = plan.analyze(_dev(f)).cpu().numpy()
+    e = rel_err(a, O.analyze_refined(f, nside, lmax))
+    print(f"f32+refine nside {nside} lmax {lmax} ({strategy}): vs O_ref {e:.3e}")
+    assert e < TOL_REFINE
+
+
+def test_f32_refine_uneven_batch_vs_refined_oracle():
+    """Uneven nside and lmax in one refinement plan, each map against O_ref."""
+    nsides = [8, 16, 8, 32]
+    lmaxs = [16, 30, 13, 64]
+    maps = [white_map(n, 800 + i) for i, n in enumerate(nsides)]
+    plan = P.Plan(nsides, lmaxs, mode="f32_refine")
+    a = plan.analyze(_dev(np.concatenate(maps))).cpu().numpy()
+    off = 0
+    for f, n, L in zip(maps, nsides, lmaxs):
+        sz = O.alm_size(L)
+        e = rel_err(a[off:off + sz], O.analyze_refined(f, n, L))
+        print(f"uneven f32+refine nside {n} lmax {L}: vs O_ref {e:.3e}")
+        assert e < TOL_REFINE
+        off += sz
