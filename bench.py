@@ -208,7 +208,7 @@ def time_mode(torch, P, maps, nside, nmaps, mode, steps, warmup, strategy):
     return plan, alm, cl, dt, setup_s, prof
 
 
-def cpu_baseline(f_host, nside, nsample=16):
+def cpu_baseline(f_host, nside, nsample=48):
     """The oracle on a bounded sample: one map through the Fourier-space route
     of Algorithm 1 for `nsample` evenly spaced orders m, scaled to a map."""
     import numpy as np
