@@ -456,13 +456,18 @@ __device__ __forceinline__ void gemm_tile(const GemmProblem<T>& P, int m0, int n
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = typename Acc::V{0, 0, 0, 0};
 
-    // Each thread stages 8 consecutive elements of one k row of each tile.
+    // Each thread stages 8 elements of one k row of each tile: 16-byte vector
+    // q of the thread sits at column 16 VE q + VE (tid % 16), so the 16 lanes
+    // of a row write one contiguous 256-byte run per store (every LDS bank
+    // once) and read contiguous 256-byte runs from memory.
     // FP32 loads are unconditional (a row or column outside the problem reads
     // the problem's first element and is zeroed after the load), so they issue
     // back to back without branches.
     constexpr int VE = 16 / sizeof(T);   // elements per 16-byte vector
     const int lr = tid >> 4;             // 0..15
-    const int lc = (tid & 15) * 8;       // 0..120
+    const int lc = (tid & 15) * VE;      // column of the thread's first element
+    // column of the thread's staged element e (0..7)
+    auto ecol = [&](int e) { return lc + (e / VE) * (16 * VE) + (e % VE); };
     // A rows are read as 16-byte vectors when the row stride and base allow it
     const bool avec = (P.lda % VE) == 0 && (reinterpret_cast<uintptr_t>(P.A) % 16) == 0;
     auto gload = [&](int k0, T (&ra)[8], T (&rb)[8]) {
@@ -474,7 +479,7 @@ __device__ __forceinline__ void gemm_tile(const GemmProblem<T>& P, int m0, int n
             if (avec) {
 #pragma unroll
                 for (int e = 0; e < 8; e += VE) {
-                    const int mm = m0 + lc + e;
+                    const int mm = m0 + ecol(e);
                     const bool ok = krow && mm < P.lda;
                     V16<T> v = *reinterpret_cast<const V16<T>*>(ok ? arow + mm : P.A);
 #pragma unroll
@@ -483,7 +488,7 @@ __device__ __forceinline__ void gemm_tile(const GemmProblem<T>& P, int m0, int n
             } else {
 #pragma unroll
                 for (int e = 0; e < 8; ++e) {
-                    const int mm = m0 + lc + e;
+                    const int mm = m0 + ecol(e);
                     const bool ok = krow && mm < P.M;
                     const T v = *(ok ? arow + mm : P.A);
                     ra[e] = ok ? v : T(0);
@@ -492,7 +497,7 @@ __device__ __forceinline__ void gemm_tile(const GemmProblem<T>& P, int m0, int n
             const TB* brow = B + int64_t(krow ? k : 0) * P.ldb;
 #pragma unroll
             for (int e = 0; e < 8; e += 2) {
-                const int nn = n0 + lc + e;
+                const int nn = n0 + ecol(e);
                 const bool ok = krow && nn < P.N;
                 const V2<TB> v = *reinterpret_cast<const V2<TB>*>(ok ? brow + int64_t(nn >> 1) * P.bps : B);
                 rb[e] = ok ? T(v.v[0]) : T(0);
@@ -504,7 +509,7 @@ __device__ __forceinline__ void gemm_tile(const GemmProblem<T>& P, int m0, int n
             if (avec) {
 #pragma unroll
                 for (int e = 0; e < 8; e += VE) {
-                    const int mm = m0 + lc + e;
+                    const int mm = m0 + ecol(e);
                     V16<T> v{};
                     if (krow && mm < P.lda) v = *reinterpret_cast<const V16<T>*>(arow + mm);
 #pragma unroll
@@ -513,14 +518,14 @@ __device__ __forceinline__ void gemm_tile(const GemmProblem<T>& P, int m0, int n
             } else {
 #pragma unroll
                 for (int e = 0; e < 8; ++e) {
-                    const int mm = m0 + lc + e;
+                    const int mm = m0 + ecol(e);
                     ra[e] = (krow && mm < P.M) ? arow[mm] : T(0);
                 }
             }
             const TB* brow = B + int64_t(k) * P.ldb;
 #pragma unroll
             for (int e = 0; e < 8; e += 2) {
-                const int nn = n0 + lc + e;
+                const int nn = n0 + ecol(e);
                 V2<TB> v{};
                 if (krow && nn < P.N) v = *reinterpret_cast<const V2<TB>*>(brow + int64_t(nn >> 1) * P.bps);
                 rb[e] = T(v.v[0]);
@@ -537,8 +542,8 @@ __device__ __forceinline__ void gemm_tile(const GemmProblem<T>& P, int m0, int n
                 va.v[q] = ra[e + q];
                 vb.v[q] = rb[e + q];
             }
-            *reinterpret_cast<V16<T>*>(&As[buf][lr][lc + e]) = va;
-            *reinterpret_cast<V16<T>*>(&Bs[buf][lr][lc + e]) = vb;
+            *reinterpret_cast<V16<T>*>(&As[buf][lr][ecol(e)]) = va;
+            *reinterpret_cast<V16<T>*>(&Bs[buf][lr][ecol(e)]) = vb;
         }
     };
     auto compute = [&](int cur) {
