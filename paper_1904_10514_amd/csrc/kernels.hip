@@ -563,42 +563,27 @@ __device__ __forceinline__ void gemm_tile(const GemmProblem<T>& P, int m0, int n
             }
         }
     };
-    // Step s of 16 k rows lives in LDS buffer s & 1.  FP32 stages it through
-    // register set s & 1 with its global loads issued two steps ahead; FP64
-    // (twice the accumulator registers) through one set, one step ahead.
+    // Step s of 16 k rows lives in LDS buffer s & 1 and is staged through
+    // register set s & 1, its global loads issued two steps ahead.
     const int nk = (P.K + GBK - 1) / GBK;
-    T ra0[8], rb0[8];
-    if constexpr (sizeof(T) == 4) {
-        T ra1[8], rb1[8];
-        gload(0, ra0, rb0);
-        lstore(0, ra0, rb0);
-        if (nk > 1) gload(GBK, ra1, rb1);
-        if (nk > 2) gload(2 * GBK, ra0, rb0);
+    T ra0[8], rb0[8], ra1[8], rb1[8];
+    gload(0, ra0, rb0);
+    lstore(0, ra0, rb0);
+    if (nk > 1) gload(GBK, ra1, rb1);
+    if (nk > 2) gload(2 * GBK, ra0, rb0);
+    __syncthreads();
+    int kt = 0;
+    for (; kt + 1 < nk; kt += 2) {
+        compute(0);
+        lstore(1, ra1, rb1);
+        if (kt + 3 < nk) gload((kt + 3) * GBK, ra1, rb1);
         __syncthreads();
-        int kt = 0;
-        for (; kt + 1 < nk; kt += 2) {
-            compute(0);
-            lstore(1, ra1, rb1);
-            if (kt + 3 < nk) gload((kt + 3) * GBK, ra1, rb1);
-            __syncthreads();
-            compute(1);
-            if (kt + 2 < nk) lstore(0, ra0, rb0);
-            if (kt + 4 < nk) gload((kt + 4) * GBK, ra0, rb0);
-            __syncthreads();
-        }
-        if (kt < nk) compute(0);
-    } else {
-        gload(0, ra0, rb0);
-        lstore(0, ra0, rb0);
+        compute(1);
+        if (kt + 2 < nk) lstore(0, ra0, rb0);
+        if (kt + 4 < nk) gload((kt + 4) * GBK, ra0, rb0);
         __syncthreads();
-        for (int kt = 0; kt < nk; ++kt) {
-            const int cur = kt & 1;
-            if (kt + 1 < nk) gload((kt + 1) * GBK, ra0, rb0);
-            compute(cur);
-            if (kt + 1 < nk) lstore(cur ^ 1, ra0, rb0);
-            __syncthreads();
-        }
     }
+    if (kt < nk) compute(0);
 #pragma unroll
     for (int i = 0; i < NI; ++i) {
 #pragma unroll
@@ -616,7 +601,7 @@ __device__ __forceinline__ void gemm_tile(const GemmProblem<T>& P, int m0, int n
 
 // TB: storage type of B (FP64 B is rounded to T as it is staged).
 template <class T, class TB>
-__global__ __launch_bounds__(256, sizeof(T) == 8 ? 1 : 3) void k_gemm(const GemmProblem<T>* __restrict__ probs,
+__global__ __launch_bounds__(256, sizeof(T) == 8 ? 2 : 3) void k_gemm(const GemmProblem<T>* __restrict__ probs,
                                               const int32_t* __restrict__ tmap, const TB* __restrict__ Bbase,
                                               T* __restrict__ Cbase) {
     __shared__ T As[2][GBK][GBM + GPAD];
