@@ -158,7 +158,8 @@ def measured_traffic(stage, dtype, nside, nmaps, strategy):
         if js["workload"] != {"nside": nside, "lmax": 2 * nside, "batch": nmaps, "strategy": strategy}:
             return None
         e = js["stages"].get(f"{stage}/{dtype}")
-        return None if e is None else e["read_bytes"] + e["write_bytes"]
+        # the counter runs sum a stage's dispatches (two FP32 analysis GEMMs)
+        return None if e is None else (e["read_bytes"] + e["write_bytes"]) / e["dispatches"]
     except (OSError, KeyError, ValueError):
         return None
 
