@@ -17,6 +17,8 @@ Analysis on HEALPix Grids ...", arXiv:1904.10514) by eye:
   dense      -- O_dense: least squares against the dense Y matrix, and the
                 Richardson matrix of eq. (richardson) (Table 1)
   refine     -- O_ref: one step of eq. (uzawa) with A := HP2SPH
+  healpix    -- the equal-weight analysis of eq. (healsph) and its Jacobi
+                iteration, eq. (uzawa) with A := (4 pi / N) S^*, Sec. 2.2
   spectrum   -- the angular power spectrum, eq. (APS), Sec. 1
 
 Parity status of each function is stated in its docstring.
@@ -28,6 +30,7 @@ from .hp2sph import analyze, analyze_full, analyze_columns, ring_coefficients, p
 from .synth import synthesize
 from .dense import synthesis_matrix, analyze_dense, richardson_radius_readings
 from .refine import analyze_refined
+from .healpix import analyze_equal_weight, analyze_jacobi, ring_longitude_sums
 from .spectrum import power_spectrum, alm_index, alm_size
 
 __all__ = [
@@ -37,5 +40,6 @@ __all__ = [
     "synthesize",
     "synthesis_matrix", "analyze_dense", "richardson_radius_readings",
     "analyze_refined",
+    "analyze_equal_weight", "analyze_jacobi", "ring_longitude_sums",
     "power_spectrum", "alm_index", "alm_size",
 ]
