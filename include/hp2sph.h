@@ -36,6 +36,12 @@
  *                      coefficients by folding aliased modes, and rounded to
  *                      FP32 for the second FP32 pass.
  *   HP2SPH_F32         one FP32 analysis, no refinement (diagnostic).
+ *   HP2SPH_EQUAL_WEIGHT
+ *                      not HP2SPH: the equal-weight quadrature analysis of
+ *                      eq. (healsph) (Sec. 2.2), a = (4 pi / N) S^* f, and its
+ *                      Jacobi iteration, eq. (uzawa) with that A, in FP64 --
+ *                      the method the paper compares HP2SPH with.  See
+ *                      hp2sph_analyze_iterative.
  *
  * Conventions of every call:
  *   - All functions return an int status: HP2SPH_OK (0) or a negative code;
@@ -73,7 +79,8 @@ typedef struct hp2sph_plan_s* hp2sph_plan_t;
 enum {
     HP2SPH_F64 = 0,
     HP2SPH_F32_REFINE = 1,
-    HP2SPH_F32 = 2
+    HP2SPH_F32 = 2,
+    HP2SPH_EQUAL_WEIGHT = 3
 };
 
 enum {
@@ -140,10 +147,32 @@ int hp2sph_workspace_size(hp2sph_plan_t plan, size_t* bytes);
  * Analysis, Algorithm 1: maps (device, FP64, read only) -> alm (device,
  * complex128, written).  workspace: device, >= hp2sph_workspace_size bytes,
  * 256-byte aligned, contents need not be initialised and are clobbered.
+ * For an HP2SPH_EQUAL_WEIGHT plan this is hp2sph_analyze_iterative with
+ * niter = 3, the iteration count the paper gives as HEALPix's default.
  * Errors: EINVAL (null/misaligned maps or alm), EWORKSPACE, ESTATE, EDEVICE.
  */
 int hp2sph_analyze(hp2sph_plan_t plan, const double* maps, double* alm,
                    void* workspace, void* stream);
+
+/*
+ * Equal-weight analysis with Jacobi iterations (Sec. 2.2, eqs. healsph,
+ * uzawa, richardson), for plans created with HP2SPH_EQUAL_WEIGHT:
+ *   a(0) = A f,  a(k+1) = a(k) + A (f - S a(k)),  k < niter,
+ * A = (4 pi / N) S^* (eq. healsph: a_l^m = (4 pi / N) sum_i conj(Y_l^m) f_i
+ * over the N pixels), S the exact synthesis (hp2sph_synthesize), everything in
+ * FP64.  A is the synthesis transposed: per ring the longitude sums
+ * sum_q f_q e^{-i m lambda_q} for every m <= lmax (modes beyond the ring's
+ * Nyquist mode alias), then the transposed evaluation of the orthonormal
+ * Legendre functions at the ring colatitudes.  The iteration converges to the
+ * least-squares a_lm (eq. richardson) at the rate of the spectral radius of
+ * I - (4 pi / N) S^* S.  Degrees l <= lmax <= 2 nside (the plan's band).
+ * maps, alm, workspace as for hp2sph_analyze; 0 <= niter <= HP2SPH_MAX_JACOBI.
+ * Errors: EINVAL (plan of another mode, niter out of range, null/misaligned
+ * pointers), EWORKSPACE, ESTATE, EDEVICE.
+ */
+#define HP2SPH_MAX_JACOBI 1000
+int hp2sph_analyze_iterative(hp2sph_plan_t plan, const double* maps, double* alm,
+                             int32_t niter, void* workspace, void* stream);
 
 /*
  * Exact synthesis, eq. (synthesis) (Sec. 2.2): alm (device, complex128,
@@ -183,10 +212,11 @@ const char* hp2sph_last_error(void);
  * 3 analysis Givens sweeps (S4), 4 pack a_lm, 5 unpack a_lm (in the
  * refinement: FP32 a0 widened to FP64 in place of an unpack), 6 synthesis
  * sweeps, 7 synthesis GEMM, 8 inverse ring transform, 9 C_l (S5),
- * 10 refinement residual in ring-Fourier space.
+ * 10 refinement residual in ring-Fourier space, 11 longitude sums of the
+ * equal-weight analysis, 12 its transposed-evaluation GEMM.
  * Errors: ESTATE, EINVAL, EDEVICE.
  */
-#define HP2SPH_NSTAGES 11
+#define HP2SPH_NSTAGES 13
 int hp2sph_profile(hp2sph_plan_t plan, int32_t enable);
 int hp2sph_profile_read(hp2sph_plan_t plan, double* ms, int32_t* launches, int32_t nstages);
 

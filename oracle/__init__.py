@@ -30,7 +30,7 @@ from .hp2sph import analyze, analyze_full, analyze_columns, ring_coefficients, p
 from .synth import synthesize
 from .dense import synthesis_matrix, analyze_dense, richardson_radius_readings
 from .refine import analyze_refined
-from .healpix import analyze_equal_weight, analyze_jacobi, ring_longitude_sums
+from .healpix import analyze_equal_weight, analyze_jacobi, ring_longitude_sums, equal_weight_columns
 from .spectrum import power_spectrum, alm_index, alm_size
 
 __all__ = [
@@ -40,6 +40,6 @@ __all__ = [
     "synthesize",
     "synthesis_matrix", "analyze_dense", "richardson_radius_readings",
     "analyze_refined",
-    "analyze_equal_weight", "analyze_jacobi", "ring_longitude_sums",
+    "analyze_equal_weight", "analyze_jacobi", "ring_longitude_sums", "equal_weight_columns",
     "power_spectrum", "alm_index", "alm_size",
 ]

@@ -69,3 +69,19 @@ def analyze_jacobi(f, nside, lmax, niter):
     for _ in range(int(niter)):
         a = a + analyze_equal_weight(f - synthesize(a, nside, lmax), nside, lmax)
     return a
+
+
+def equal_weight_columns(f, nside, ms, lmax):
+    """{m: a_l^m for l = m..lmax} of eq. (healsph) for the listed orders only
+    (the same sums, with the order-m Legendre functions evaluated directly at
+    the ring heights): affordable at large nside for a few orders."""
+    from .legendre import plm_orthonormal
+    rt = ring_table(nside)
+    N = int(np.sum(rt["n"]))
+    F = ring_longitude_sums(f, nside, lmax)
+    scale = 4.0 * np.pi / N / np.sqrt(2.0 * np.pi)
+    out = {}
+    for m in ms:
+        P = plm_orthonormal(lmax, int(m), rt["z"])    # [l - m][ring]
+        out[int(m)] = scale * (P @ F[:, int(m)])
+    return out

@@ -31,8 +31,10 @@ if not os.path.exists(LIB_PATH):
 
 _lib = ctypes.CDLL(LIB_PATH)
 
-HP2SPH_F64, HP2SPH_F32_REFINE, HP2SPH_F32 = 0, 1, 2
-MODES = {"f64": HP2SPH_F64, "f32_refine": HP2SPH_F32_REFINE, "f32": HP2SPH_F32}
+HP2SPH_F64, HP2SPH_F32_REFINE, HP2SPH_F32, HP2SPH_EQUAL_WEIGHT = 0, 1, 2, 3
+MODES = {"f64": HP2SPH_F64, "f32_refine": HP2SPH_F32_REFINE, "f32": HP2SPH_F32,
+         "equal_weight": HP2SPH_EQUAL_WEIGHT}
+MAX_JACOBI = 1000
 ERRORS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "EWORKSPACE", -5: "ESTATE"}
 TABLE_RINGS, TABLE_POLE, TABLE_ANALYSIS, TABLE_SYNTHESIS, TABLE_GIVENS = 0, 1, 2, 3, 4
 MAX_NSIDE = 2048
@@ -41,11 +43,13 @@ EXPORTED = [
     "hp2sph_plan_create", "hp2sph_workspace_size", "hp2sph_analyze", "hp2sph_synthesize",
     "hp2sph_power_spectrum", "hp2sph_plan_destroy", "hp2sph_last_error", "hp2sph_host_table",
     "hp2sph_profile", "hp2sph_profile_read", "hp2sph_plan_create_ex", "hp2sph_plan_strategy",
+    "hp2sph_analyze_iterative",
 ]
 STRATEGIES = {"auto": 0, "staged": 1, "tables": 2}
-NSTAGES = 11
+NSTAGES = 13
 STAGES = ["ring_forward", "pole", "gemm_analysis", "sweep_analysis", "pack", "unpack",
-          "sweep_synthesis", "gemm_synthesis", "ring_inverse", "cl", "residual_fold"]
+          "sweep_synthesis", "gemm_synthesis", "ring_inverse", "cl", "residual_fold",
+          "ring_adjoint", "gemm_adjoint"]
 
 _vp = ctypes.c_void_p
 _i32 = ctypes.c_int32
@@ -53,6 +57,7 @@ _lib.hp2sph_plan_create.argtypes = [ctypes.POINTER(_i32), ctypes.POINTER(_i32), 
 _lib.hp2sph_workspace_size.argtypes = [_vp, ctypes.POINTER(ctypes.c_size_t)]
 _lib.hp2sph_analyze.argtypes = [_vp, _vp, _vp, _vp, _vp]
 _lib.hp2sph_synthesize.argtypes = [_vp, _vp, _vp, _vp, _vp]
+_lib.hp2sph_analyze_iterative.argtypes = [_vp, _vp, _vp, _i32, _vp, _vp]
 _lib.hp2sph_power_spectrum.argtypes = [_vp, _vp, _vp, _vp]
 _lib.hp2sph_plan_destroy.argtypes = [_vp]
 _lib.hp2sph_last_error.restype = ctypes.c_char_p
@@ -165,6 +170,19 @@ class Plan:
             out = torch.empty(self.alm_total, dtype=torch.complex128, device=maps.device)
         _check(_lib.hp2sph_analyze(self._h, maps.data_ptr(), out.data_ptr(), self._ws_ptr, self._stream()),
                "analyze")
+        return out
+
+    def analyze_iterative(self, maps, niter, out=None):
+        """Equal-weight analysis with `niter` Jacobi iterations (mode="equal_weight")."""
+        torch = _torch()
+        if maps.dtype != torch.float64 or not maps.is_cuda or not maps.is_contiguous():
+            raise ValueError("maps must be a contiguous float64 CUDA tensor")
+        if maps.numel() != self.npix_total:
+            raise ValueError(f"maps has {maps.numel()} values, plan expects {self.npix_total}")
+        if out is None:
+            out = torch.empty(self.alm_total, dtype=torch.complex128, device=maps.device)
+        _check(_lib.hp2sph_analyze_iterative(self._h, maps.data_ptr(), out.data_ptr(), int(niter), self._ws_ptr,
+                                             self._stream()), "analyze_iterative")
         return out
 
     def synthesize(self, alm, out=None):

@@ -83,6 +83,7 @@ struct Group {
     DevTables<double> t64;
     DevTables<float> t32;
     double* syn[4] = {};              // synthesis matrices (FP64)
+    double* synT[4] = {};             // their transposes [h][l'] (equal-weight analysis, staged)
     int64_t* d_map_off = nullptr;     // per member: offset of its map (doubles)
     int64_t* d_alm_off = nullptr;     // per member: offset of its alm (complex)
     int64_t* d_cl_off = nullptr;
@@ -101,6 +102,7 @@ struct Group {
     GemmList<double> ana64, syn64, syn64_staged;
     GemmList<float> ana32;
     GemmList<float> ana32_b64;   // FP32 analysis reading FP64 Dsym (first pass of the refinement)
+    GemmList<double> adj64;      // equal-weight analysis: transposed evaluation (adjoint of the synthesis GEMM)
 };
 
 template <class T>
@@ -174,7 +176,8 @@ struct hp2sph_plan_s {
     std::vector<std::unique_ptr<hp2sph::Group>> groups;
     size_t ws_bytes = 0;
     size_t off_Df = 0, off_Dr = 0;    // refinement: FP64 ring coefficients, FP32 residual coefficients
-    size_t off_Ua = 0;                // refinement: FP32 a0 in the U layout
+    size_t off_Ua = 0;                // refinement: FP32 a0 in the U layout; equal weight: FP64 a in the U layout
+    size_t off_R = 0;                 // equal weight: residual maps f - S a (FP64, all maps)
     int strategy = 0;                 // requested HP2SPH_STRATEGY_*
     uint32_t magic = 0x48503253u;
 };
@@ -184,6 +187,7 @@ using namespace hp2sph;
 namespace {
 
 constexpr size_t kAlign = 256;
+constexpr int kDefaultJacobi = 3;   // the iteration count HEALPix uses by default (Sec. 2.2)
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
@@ -259,7 +263,7 @@ void build_group(hp2sph_plan_t plan, Group& G) {
     G.rings.shifted = upload_int(G.owned, sh);
 
     const bool need64 = true;   // FP64 tables: analysis in F64 mode, always for synthesis
-    const bool need32 = (plan->mode != HP2SPH_F64);
+    const bool need32 = (plan->mode == HP2SPH_F32_REFINE || plan->mode == HP2SPH_F32);
     for (int b = 0; b < 4; ++b) {
         const int T = std::max(block_shape(G.nside, b).nsweep, 1);
         std::vector<double> gp = pad_givens(h.givens[b], d.nl[b], T, d.tpad[b]);
@@ -272,6 +276,14 @@ void build_group(hp2sph_plan_t plan, Group& G) {
             G.t32.givens[b] = G.t32.upload(gp);
         }
         G.syn[b] = G.t64.upload(h.syn[b]);
+        if (plan->mode == HP2SPH_EQUAL_WEIGHT) {
+            // [l'][h] (2 nside + 1 columns) -> [h][l']
+            const int K = 2 * G.nside + 1, nl = d.nl[b];
+            std::vector<double> t(size_t(K) * nl);
+            for (int lp = 0; lp < nl; ++lp)
+                for (int hh = 0; hh < K; ++hh) t[size_t(hh) * nl + lp] = h.syn[b][size_t(lp) * K + hh];
+            G.synT[b] = G.t64.upload(t);
+        }
     }
     fill_fft(G.t64, h, G.owned);
     if (need32) fill_fft(G.t32, h, G.owned);
@@ -403,11 +415,37 @@ void staged_synthesis_list(Group& G, GemmList<double>& out) {
     upload_list(G, v, out);
 }
 
+// Equal-weight analysis, staged: per block, the transposed evaluation matrix
+// (rows h = 1 .. 2 nside, the rings; the pole row carries no pixel) applied to
+// the weighted longitude sums, then the analysis sweeps (the transpose of the
+// synthesis sweeps: the rotations are orthogonal).
+void staged_adjoint_list(Group& G, GemmList<double>& out) {
+    const GroupDims& d = G.dims;
+    std::vector<GemmProblem<double>> v;
+    for (int b = 0; b < 4; ++b) {
+        const int kpar = b >> 1;
+        GemmProblem<double> P{};
+        P.A = G.synT[b] + d.nl[b];   // row h = 1
+        P.M = d.nl[b];
+        P.N = int(d.N[kpar]);
+        P.K = 2 * G.nside;
+        P.lda = d.nl[b];
+        P.boff = int64_t(G.blk_off_D[b] / sizeof(double)) + d.N[kpar];
+        P.ldb = d.N[kpar];
+        P.bps = 2;
+        P.coff = int64_t(G.blk_off_U[b] / sizeof(double));
+        P.ldc = d.N[kpar];
+        P.cps = 2;
+        v.push_back(P);
+    }
+    upload_list(G, v, out);
+}
+
 // Element offsets and sizes of the per-order tables of one block.
 struct OrderLayout {
-    std::vector<int64_t> ana_off, syn_off;
+    std::vector<int64_t> ana_off, syn_off, adj_off;
     std::vector<int32_t> h0;
-    int64_t ana_size = 0, syn_size = 0;
+    int64_t ana_size = 0, syn_size = 0, adj_size = 0;
 };
 
 OrderLayout order_layout(const Group& G, int b) {
@@ -421,17 +459,21 @@ OrderLayout order_layout(const Group& G, int b) {
         L.ana_size += int64_t(K - h0) * order_table_lda(d.nl[b] - kk);
         L.syn_off.push_back(L.syn_size);
         L.syn_size += int64_t(d.nl[b] - kk) * (2 * G.nside);
+        L.adj_off.push_back(L.adj_size);
+        L.adj_size += int64_t(2 * G.nside) * order_table_lda(d.nl[b] - kk);
     }
     return L;
 }
 
 size_t order_table_bytes(const Group& G, int mode) {
-    size_t ana = 0, syn = 0;
+    size_t ana = 0, syn = 0, adj = 0;
     for (int b = 0; b < 4; ++b) {
         OrderLayout L = order_layout(G, b);
         ana += size_t(L.ana_size);
         syn += size_t(L.syn_size);
+        adj += size_t(L.adj_size);
     }
+    if (mode == HP2SPH_EQUAL_WEIGHT) return (syn + adj) * 8;
     if (mode == HP2SPH_F64) return ana * 8;
     if (mode == HP2SPH_F32) return ana * 4;
     return ana * 4 + syn * 8;
@@ -447,12 +489,16 @@ size_t order_table_bytes(const Group& G, int mode) {
 // analysis matrix is the analysis sweeps of column k' applied to every
 // half-ring column of the fused colatitude-fit matrix; the synthesis matrix
 // is the same sweeps applied to every ring row of the evaluation matrix
-// (the transpose of the synthesis sweeps).  Runs once per plan.
+// (the transpose of the synthesis sweeps); the adjoint matrix of the
+// equal-weight analysis is the synthesis matrix transposed.  Runs once per
+// plan.
 void build_order_tables(hp2sph_plan_t plan, Group& G) {
     const GroupDims& d = G.dims;
     const int K = 2 * G.nside + 1;
-    const bool want_syn = (plan->mode == HP2SPH_F32_REFINE);
-    std::vector<GemmProblem<double>> la64, ls64;
+    const bool want_ana = (plan->mode != HP2SPH_EQUAL_WEIGHT);
+    const bool want_syn = (plan->mode == HP2SPH_F32_REFINE || plan->mode == HP2SPH_EQUAL_WEIGHT);
+    const bool want_adj = (plan->mode == HP2SPH_EQUAL_WEIGHT);
+    std::vector<GemmProblem<double>> la64, ls64, lj64;
     std::vector<GemmProblem<float>> la32, la32b;
     // temporary buffer for the virtual batch (chains replicated over k')
     size_t per_v = 0;
@@ -465,10 +511,13 @@ void build_order_tables(hp2sph_plan_t plan, Group& G) {
     for (int b = 0; b < 4; ++b) {
         const int kpar = b >> 1;
         OrderLayout L = order_layout(G, b);
-        auto ana64 = std::make_unique<DevBuf>();
-        ana64->bytes = size_t(L.ana_size) * 8;
-        HIPTHROW(hipMalloc(&ana64->p, ana64->bytes));
-        HIPTHROW(hipMemset(ana64->p, 0, ana64->bytes));   // row padding reads as zero
+        std::unique_ptr<DevBuf> ana64;
+        if (want_ana) {
+            ana64 = std::make_unique<DevBuf>();
+            ana64->bytes = size_t(L.ana_size) * 8;
+            HIPTHROW(hipMalloc(&ana64->p, ana64->bytes));
+            HIPTHROW(hipMemset(ana64->p, 0, ana64->bytes));   // row padding reads as zero
+        }
         std::unique_ptr<DevBuf> syn64;
         if (want_syn) {
             syn64 = std::make_unique<DevBuf>();
@@ -491,8 +540,9 @@ void build_order_tables(hp2sph_plan_t plan, Group& G) {
         Ub.p[b] = Uv;
         Blocks4<const double> Gv{};
         Gv.p[b] = G.t64.givens[b];
-        for (int pass = 0; pass < (want_syn ? 2 : 1); ++pass) {
+        for (int pass = 0; pass < 2; ++pass) {
             const bool syn = (pass == 1);
+            if (syn ? !want_syn : !want_ana) continue;
             const int h_lo = syn ? 1 : 0, h_hi = K - 1;
             for (int hf = h_lo; hf <= h_hi; hf += 2 * nv_max) {
                 if (syn) {
@@ -508,10 +558,22 @@ void build_order_tables(hp2sph_plan_t plan, Group& G) {
             }
         }
         HIPTHROW(hipDeviceSynchronize());
+        std::unique_ptr<DevBuf> adj64;
+        if (want_adj) {
+            adj64 = std::make_unique<DevBuf>();
+            adj64->bytes = size_t(L.adj_size) * 8;
+            HIPTHROW(hipMalloc(&adj64->p, adj64->bytes));
+            HIPTHROW(hipMemset(adj64->p, 0, adj64->bytes));   // row padding reads as zero
+            const int64_t* d_adj_off = upload_int(scratch, L.adj_off);
+            HIPTHROW(launch_transpose_orders(static_cast<const double*>(syn64->p), d_syn_off,
+                                             static_cast<double*>(adj64->p), d_adj_off, d.nl[b], d.nk[b],
+                                             2 * G.nside, nullptr));
+            HIPTHROW(hipDeviceSynchronize());
+        }
         // problem lists of this block
-        const double* tana64 = static_cast<const double*>(ana64->p);
+        const double* tana64 = want_ana ? static_cast<const double*>(ana64->p) : nullptr;
         float* tana32 = nullptr;
-        if (plan->mode != HP2SPH_F64) {
+        if (want_ana && plan->mode != HP2SPH_F64) {
             auto a32 = std::make_unique<DevBuf>();
             a32->bytes = size_t(L.ana_size) * 4;
             HIPTHROW(hipMalloc(&a32->p, a32->bytes));
@@ -533,7 +595,9 @@ void build_order_tables(hp2sph_plan_t plan, Group& G) {
             P.bps = 2;
             P.ldc = d.N[kpar];
             P.cps = 2;
-            if (plan->mode == HP2SPH_F64) {
+            if (!want_ana) {
+                // no HP2SPH analysis tables in an equal-weight plan
+            } else if (plan->mode == HP2SPH_F64) {
                 P.A = tana64 + L.ana_off[kk];
                 P.boff = int64_t(G.blk_off_D[b] / 8) + int64_t(h0) * d.N[kpar] + kcol;
                 P.coff = int64_t(G.blk_off_U[b] / 8) + int64_t(kk) * d.N[kpar] + kcol;
@@ -570,14 +634,35 @@ void build_order_tables(hp2sph_plan_t plan, Group& G) {
                 S.cps = 2;
                 ls64.push_back(S);
             }
+            if (want_adj) {
+                // a_l^m = sum_h Tsyn[l][h] W[h]: the transposed synthesis table
+                // over the ring rows h = 1 .. 2 nside
+                GemmProblem<double> Q{};
+                Q.A = static_cast<const double*>(adj64->p) + L.adj_off[kk];
+                Q.M = d.nl[b] - kk;
+                Q.K = 2 * G.nside;
+                Q.N = 2 * d.nmaps;
+                Q.lda = order_table_lda(Q.M);
+                Q.boff = int64_t(G.blk_off_D[b] / 8) + int64_t(1) * d.N[kpar] + kcol;
+                Q.ldb = d.N[kpar];
+                Q.bps = 2;
+                Q.coff = int64_t(G.blk_off_U[b] / 8) + int64_t(kk) * d.N[kpar] + kcol;
+                Q.ldc = d.N[kpar];
+                Q.cps = 2;
+                lj64.push_back(Q);
+            }
         }
-        if (plan->mode == HP2SPH_F64) G.owned.push_back(std::move(ana64));
+        if (want_ana && plan->mode == HP2SPH_F64) G.owned.push_back(std::move(ana64));
         if (want_syn) G.owned.push_back(std::move(syn64));
+        if (want_adj) G.owned.push_back(std::move(adj64));
     }
-    if (plan->mode == HP2SPH_F64) upload_list(G, la64, G.ana64);
-    else upload_list(G, la32, G.ana32);
+    if (want_ana) {
+        if (plan->mode == HP2SPH_F64) upload_list(G, la64, G.ana64);
+        else upload_list(G, la32, G.ana32);
+    }
     if (plan->mode == HP2SPH_F32_REFINE) upload_list(G, la32b, G.ana32_b64);
     if (want_syn) upload_list(G, ls64, G.syn64);
+    if (want_adj) upload_list(G, lj64, G.adj64);
 }
 
 // Launch `expr` as stage `st`, bracketed by events when profiling is on.
@@ -694,6 +779,47 @@ int refine_pass(hp2sph_plan_t plan, Group& G, const double* maps, double* alm, v
     return HP2SPH_OK;
 }
 
+// Equal-weight analysis of one group, eq. (healsph) (Sec. 2.2):
+// a = (4 pi / N) S^* x for the maps x, i.e. the transposed stages of the
+// synthesis: longitude sums of every ring (aliased modes kept), the
+// transposed evaluation tables, and (staged) the analysis sweeps.  Written
+// to alm, or added to it (the update of the Jacobi iteration).
+int equal_weight_pass(hp2sph_plan_t plan, Group& G, const double* x, double* alm, bool add, void* ws,
+                      hipStream_t s) {
+    Blocks4<double> W = blocks_at<double>(ws, G.off_D, G, G.rows_D);
+    Blocks4<double> U = blocks_at<double>(ws, G.off_U, G, G.rows_U);
+    const double scale = 4.0 * 3.14159265358979323846 / (12.0 * double(G.nside) * double(G.nside));
+    STAGE(11, launch_ring_adjoint(x, G.d_map_off, G.rings, G.t64.fft, W, G.dims, scale, s));
+    STAGE(12, launch_gemm<double>(G.adj64.dev, G.adj64.tmap, G.adj64.slots, W.p[0], U.p[0], s));
+    if (!G.tables) {
+        Blocks4<const double> Gv;
+        for (int b = 0; b < 4; ++b) Gv.p[b] = G.t64.givens[b];
+        STAGE(3, launch_sweep_fwd<double>(U, Gv, G.dims, s));
+    }
+    if (add) {
+        Blocks4<double> Ua = blocks_at<double>(ws, plan->off_Ua, G, G.rows_U);
+        STAGE(5, launch_unpack(alm, G.d_alm_off, G.d_lmax, Ua, G.dims, s));
+        STAGE(4, launch_pack<double>(cblocks(Ua), cblocks(U), alm, G.d_alm_off, G.d_lmax, G.d_pack_tiles,
+                                     G.n_pack_tiles, G.dims, s));
+    } else {
+        STAGE(4, launch_pack<double>(cblocks(U), Blocks4<const double>{}, alm, G.d_alm_off, G.d_lmax,
+                                     G.d_pack_tiles, G.n_pack_tiles, G.dims, s));
+    }
+    return HP2SPH_OK;
+}
+
+// The Jacobi iteration of eq. (uzawa) with A = (4 pi / N) S^* (Sec. 2.2):
+// a0 = A f, then niter times r = f - S a, a = a + A r (all FP64).
+int jacobi_pass(hp2sph_plan_t plan, Group& G, const double* maps, double* alm, int niter, void* ws, hipStream_t s) {
+    if (int e = equal_weight_pass(plan, G, maps, alm, false, ws, s)) return e;
+    double* R = reinterpret_cast<double*>(static_cast<char*>(ws) + plan->off_R);
+    for (int it = 0; it < niter; ++it) {
+        if (int e = synthesis_pass(G, alm, R, maps, ws, s)) return e;
+        if (int e = equal_weight_pass(plan, G, R, alm, true, ws, s)) return e;
+    }
+    return HP2SPH_OK;
+}
+
 bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
 
 int check_plan(hp2sph_plan_t plan) {
@@ -718,7 +844,7 @@ int hp2sph_plan_create_ex(const int32_t* nside, const int32_t* lmax, int32_t bat
     *out = nullptr;
     if (!nside || !lmax) return fail(HP2SPH_EINVAL, "nside/lmax is null");
     if (batch <= 0) return fail(HP2SPH_EINVAL, "batch must be positive");
-    if (mode != HP2SPH_F64 && mode != HP2SPH_F32_REFINE && mode != HP2SPH_F32)
+    if (mode != HP2SPH_F64 && mode != HP2SPH_F32_REFINE && mode != HP2SPH_F32 && mode != HP2SPH_EQUAL_WEIGHT)
         return fail(HP2SPH_EINVAL, "unknown precision mode");
     if (strategy != HP2SPH_STRATEGY_AUTO && strategy != HP2SPH_STRATEGY_STAGED && strategy != HP2SPH_STRATEGY_TABLES)
         return fail(HP2SPH_EINVAL, "unknown strategy");
@@ -773,6 +899,8 @@ int hp2sph_plan_create_ex(const int32_t* nside, const int32_t* lmax, int32_t bat
             staged_synthesis_list(*G, G->syn64_staged);
             if (tables) {
                 build_order_tables(plan.get(), *G);
+            } else if (mode == HP2SPH_EQUAL_WEIGHT) {
+                staged_adjoint_list(*G, G->adj64);
             } else if (mode == HP2SPH_F64) {
                 staged_analysis_list<double>(*G, G->t64, G->ana64);
             } else {
@@ -793,6 +921,12 @@ int hp2sph_plan_create_ex(const int32_t* nside, const int32_t* lmax, int32_t bat
             plan->off_Dr = ws + max_D;
             plan->off_Ua = ws + 2 * max_D;
             ws += 2 * max_D + max_U;
+        } else if (mode == HP2SPH_EQUAL_WEIGHT) {
+            size_t max_U = 0;
+            for (auto& g : plan->groups) max_U = std::max(max_U, align_up(g->bytes_U));
+            plan->off_Ua = ws;
+            plan->off_R = ws + max_U;
+            ws += max_U + align_up(size_t(plan->total_pix) * sizeof(double));
         }
         plan->ws_bytes = ws;
         // kernels with more than 64 KB of dynamic LDS
@@ -836,10 +970,27 @@ int hp2sph_analyze(hp2sph_plan_t plan, const double* maps, double* alm, void* wo
             if (int e = analysis_pass<double>(G, maps, alm, workspace, s)) return e;
         } else if (plan->mode == HP2SPH_F32) {
             if (int e = analysis_pass<float>(G, maps, alm, workspace, s)) return e;
+        } else if (plan->mode == HP2SPH_EQUAL_WEIGHT) {
+            if (int e = jacobi_pass(plan, G, maps, alm, kDefaultJacobi, workspace, s)) return e;
         } else {
             if (int e = refine_pass(plan, G, maps, alm, workspace, s)) return e;
         }
     }
+    return HP2SPH_OK;
+}
+
+int hp2sph_analyze_iterative(hp2sph_plan_t plan, const double* maps, double* alm, int32_t niter, void* workspace,
+                             void* stream) {
+    if (int e = check_plan(plan)) return e;
+    g_prof = &plan->prof;
+    if (plan->mode != HP2SPH_EQUAL_WEIGHT) return fail(HP2SPH_EINVAL, "plan was not created with HP2SPH_EQUAL_WEIGHT");
+    if (niter < 0 || niter > HP2SPH_MAX_JACOBI) return fail(HP2SPH_EINVAL, "niter out of range");
+    if (!maps || !alm) return fail(HP2SPH_EINVAL, "maps/alm is null");
+    if (!aligned(maps, 16) || !aligned(alm, 16)) return fail(HP2SPH_EINVAL, "maps/alm not 16-byte aligned");
+    if (!workspace || !aligned(workspace, kAlign)) return fail(HP2SPH_EWORKSPACE, "workspace null or not 256-byte aligned");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    for (auto& gp : plan->groups)
+        if (int e = jacobi_pass(plan, *gp, maps, alm, niter, workspace, s)) return e;
     return HP2SPH_OK;
 }
 

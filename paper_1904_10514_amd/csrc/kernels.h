@@ -94,6 +94,13 @@ template <class T>
 hipError_t launch_ring_forward(const double* maps, const int64_t* map_off, RingTab rt, FftTab<T> ft,
                                Blocks4<T> D, const GroupDims& g, hipStream_t s);
 
+// Equal-weight analysis, eq. (healsph): longitude sums of every ring for all
+// modes m = 0..p (aliased beyond each ring's Nyquist mode), combined per ring
+// pair as W+- = scale (F_N +- F_S) into Dsym rows 1 .. 2 nside (row 0 is not
+// written).
+hipError_t launch_ring_adjoint(const double* maps, const int64_t* map_off, RingTab rt, FftTab<double> ft,
+                               Blocks4<double> W, const GroupDims& g, double scale, hipStream_t s);
+
 // Refinement residual in ring-Fourier space: Dr = Df - Ring(Synth(Gs)) for
 // Dsym rows 1 .. 2 nside (Gs: synthesis GEMM output, Df: FP64 forward ring
 // coefficients of the maps), written in FP32.
@@ -125,6 +132,10 @@ hipError_t launch_scatter_tables(const T* Uv, int nl, int nk, int nv, int h_firs
                                  const int64_t* off, const int32_t* h0, int ldm_syn, bool synthesis, T* tab,
                                  hipStream_t s);
 hipError_t launch_convert(const double* in, float* out, int64_t n, hipStream_t s);
+// Per-order adjoint tables: adj[aoff[k']][h][l] = syn[soff[k']][l][h], h < H,
+// l < nl - k', adjoint row stride order_table_lda(nl - k') (padding untouched).
+hipError_t launch_transpose_orders(const double* syn, const int64_t* soff, double* adj, const int64_t* aoff, int nl,
+                                   int nk, int H, hipStream_t s);
 
 // S4 analysis sweeps (Givens, order 0/1 -> order m), in place on U.
 template <class T>

@@ -341,6 +341,114 @@ __global__ __launch_bounds__(NT) void k_ring_forward(const double* __restrict__ 
     }
 }
 
+// ---------------------------------------------------------------------------
+// Equal-weight analysis, eq. (healsph): per-ring longitude sums
+// ---------------------------------------------------------------------------
+
+// F(m) = sum_q x_q e^{-i m lambda_q}, lambda_q = phi0 + 2 pi q / n, for the
+// modes m = threadIdx.x + i NT <= p of one ring.  With the DFT of the real
+// ring, X_t = sum_q x_q e^{-2 pi i q t / n} (X_{n-t} = conj X_t),
+// F(m) = e^{-i m phi0} X_{m mod n}: unlike the interpolation of Step 1, modes
+// at and beyond the ring's Nyquist mode n/2 repeat its spectrum (the sum over
+// the ring's points aliases them), which is what the adjoint of the synthesis
+// needs.
+template <int NT>
+__device__ __forceinline__ void ring_longitude_sums(const double* x, int n, bool shifted, int p, FftTab<double> ft,
+                                                    C2<double>* buf, C2<double> (&F)[kRingKPT]) {
+    const int L = n >> 1, j = n >> 2;
+    const int Mb = ft.chirpm[j];
+    const double* chirp = ft.chirp + 2 * ft.chirpoff[j];
+    const double* chirpfft = ft.chirpfft + 2 * ft.chirpfftoff[j];
+    const double* roots = ft.roots + 2 * ft.rootoff[j];   // e^{-i pi k / n}, k = 0..n
+    auto src = [x](int q) -> C2<double> {
+        const D2 v = *reinterpret_cast<const D2*>(x + 2 * q);
+        return {v.x, v.y};
+    };
+    const DftOut<double> R = ring_dft<double, NT, kRingMaxV>(buf, L, Mb, chirp, chirpfft, ft.twiddle, ft.fft_max, src);
+#pragma unroll
+    for (int i = 0; i < kRingKPT; ++i) {
+        const int m = threadIdx.x + i * NT;
+        C2<double> X = {0.0, 0.0};
+        if (m <= p) {
+            int t = m % n;
+            const bool upper = t > L;   // X_t = conj X_{n-t}
+            if (upper) t = n - t;
+            if (t == L) {
+                const C2<double> z0 = R.Z(0);
+                X = {z0.x - z0.y, 0.0};   // sum_q x_q (-1)^q
+            } else {
+                // X_t = E_t + e^{-2 pi i t / n} O_t from the L-point DFT of
+                // z_q = x_{2q} + i x_{2q+1}
+                const C2<double> zk = R.Z(t), zl = R.Z(t == 0 ? 0 : L - t);
+                const C2<double> e = cscale(cadd(zk, cconj(zl)), 0.5);
+                const C2<double> dlt = csub(zk, cconj(zl));
+                const C2<double> o = {0.5 * dlt.y, -0.5 * dlt.x};
+                X = cadd(e, cmul(ldc(roots, 2 * t), o));
+            }
+            if (upper) X = cconj(X);
+            if (shifted) {
+                // e^{-i pi m / n}, m mod 2n: the table holds k = 0..n
+                const int u = m % (2 * n);
+                const C2<double> ph = u <= n ? ldc(roots, u) : cscale(ldc(roots, u - n), -1.0);
+                X = cmul(X, ph);
+            }
+        }
+        F[i] = X;
+    }
+    // The next transform's first pass synchronises before it writes the buffer.
+}
+
+// Rows h = 1 .. 2 nside of Dsym for the equal-weight analysis: with the
+// longitude sums F_N, F_S of the ring pair h, writes
+//   W+ = scale (F_N + F_S),  W- = scale (F_N - F_S)
+// (equator: W+ = scale F_N, W- = 0), scale = 4 pi / (12 nside^2), for every
+// mode m = 0..p.  Since Pt_l^m(-z) = (-1)^{l+m} Pt_l^m(z), the order-m
+// evaluation table of the synthesis, transposed, maps W to a_l^m.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_ring_adjoint(const double* __restrict__ maps,
+                                                     const int64_t* __restrict__ map_off, RingTab rt,
+                                                     FftTab<double> ft, Blocks4<double> W, GroupDims g,
+                                                     double scale) {
+    extern __shared__ unsigned char smem_raw[];
+    C2<double>* buf = reinterpret_cast<C2<double>*>(smem_raw);
+    int b, h;
+    ring_block(g.nmaps, 2 * g.nside, b, h);
+    const int ns = g.nside, p = g.p;
+    const double* m = maps + map_off[b];
+    C2<double> FN[kRingKPT], FS[kRingKPT];
+    {
+        const int r0 = h - 1;
+        ring_longitude_sums<NT>(m + rt.start[r0], rt.n[r0], rt.shifted[r0] != 0, p, ft, buf, FN);
+    }
+    const bool equator = (h == 2 * ns);
+    if (!equator) {
+        const int r0 = 4 * ns - h - 1;
+        ring_longitude_sums<NT>(m + rt.start[r0], rt.n[r0], rt.shifted[r0] != 0, p, ft, buf, FS);
+    }
+#pragma unroll
+    for (int i = 0; i < kRingKPT; ++i) {
+        const int k = threadIdx.x + i * NT;
+        if (k > p) continue;
+        C2<double> wp, wm;
+        if (equator) {
+            wp = cscale(FN[i], scale);
+            wm = {0.0, 0.0};
+        } else {
+            wp = cscale(cadd(FN[i], FS[i]), scale);
+            wm = cscale(csub(FN[i], FS[i]), scale);
+        }
+        const int kpar = k & 1, kk = k >> 1;
+        const int64_t col = int64_t(b) * g.cm[kpar] + int64_t(kk) * g.ck[kpar];
+        const int64_t row = int64_t(h) * g.N[kpar];
+        double* bp = W.p[2 * kpar + 0];
+        double* bm = W.p[2 * kpar + 1];
+        bp[row + col] = wp.x;
+        bp[row + col + 1] = wp.y;
+        bm[row + col] = wm.x;
+        bm[row + col + 1] = wm.y;
+    }
+}
+
 static size_t lds_slots_bytes(int slots, size_t elem) { return size_t(slots + slots / 16 + 1) * elem; }
 
 static size_t ring_lds_bytes(int fft_max, size_t elem) { return lds_slots_bytes(std::max(fft_max, 256), elem); }
@@ -354,6 +462,17 @@ hipError_t launch_ring_forward(const double* maps, const int64_t* map_off, RingT
         hipLaunchKernelGGL((k_ring_forward<T, 256>), grid, dim3(256), shm, s, maps, map_off, rt, ft, D, g);
     else
         hipLaunchKernelGGL((k_ring_forward<T, 512>), grid, dim3(512), shm, s, maps, map_off, rt, ft, D, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_ring_adjoint(const double* maps, const int64_t* map_off, RingTab rt, FftTab<double> ft,
+                               Blocks4<double> W, const GroupDims& g, double scale, hipStream_t s) {
+    dim3 grid(g.nmaps, 2 * g.nside);
+    const size_t shm = ring_lds_bytes(ft.fft_max, sizeof(C2<double>));
+    if (ring_threads(ft.fft_max) == 256)
+        hipLaunchKernelGGL(k_ring_adjoint<256>, grid, dim3(256), shm, s, maps, map_off, rt, ft, W, g, scale);
+    else
+        hipLaunchKernelGGL(k_ring_adjoint<512>, grid, dim3(512), shm, s, maps, map_off, rt, ft, W, g, scale);
     return hipGetLastError();
 }
 
@@ -741,6 +860,43 @@ __global__ void k_convert(const double* __restrict__ in, float* __restrict__ out
 hipError_t launch_convert(const double* in, float* out, int64_t n, hipStream_t s) {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_convert, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, in, out, n);
+    return hipGetLastError();
+}
+
+// adj[aoff[k']] [h][l] = syn[soff[k']] [l][h] for h < H, l < M = nl - k'
+// (adjoint row stride order_table_lda(M)); one 32 x 32 tile through LDS per
+// workgroup, blockIdx.y = k'.
+__global__ __launch_bounds__(256) void k_transpose_orders(const double* __restrict__ syn,
+                                                          const int64_t* __restrict__ soff,
+                                                          double* __restrict__ adj,
+                                                          const int64_t* __restrict__ aoff, int nl, int H) {
+    __shared__ double tile[32][33];
+    const int kk = blockIdx.y;
+    const int M = nl - kk;
+    const int tiles_h = (H + 31) / 32;
+    const int th = blockIdx.x % tiles_h, tl = blockIdx.x / tiles_h;
+    const int l0 = tl * 32, h0 = th * 32;
+    if (l0 >= M) return;   // whole workgroup: no barrier is skipped by part of it
+    const int lda = order_table_lda(M);
+    const double* S = syn + soff[kk];
+    double* A = adj + aoff[kk];
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
+    for (int r = ty; r < 32; r += 8) {
+        const int l = l0 + r, h = h0 + tx;
+        tile[r][tx] = (l < M && h < H) ? S[int64_t(l) * H + h] : 0.0;
+    }
+    __syncthreads();
+    for (int r = ty; r < 32; r += 8) {
+        const int h = h0 + r, l = l0 + tx;
+        if (h < H && l < M) A[int64_t(h) * lda + l] = tile[tx][r];
+    }
+}
+
+hipError_t launch_transpose_orders(const double* syn, const int64_t* soff, double* adj, const int64_t* aoff, int nl,
+                                   int nk, int H, hipStream_t s) {
+    if (nk == 0 || nl == 0) return hipSuccess;
+    dim3 grid(unsigned(((H + 31) / 32) * ((nl + 31) / 32)), unsigned(nk));
+    hipLaunchKernelGGL(k_transpose_orders, grid, dim3(256), 0, s, syn, soff, adj, aoff, nl, H);
     return hipGetLastError();
 }
 
@@ -1559,6 +1715,8 @@ hipError_t configure_kernels() {
         reinterpret_cast<const void*>(&k_ring_forward<float, 512>),
         reinterpret_cast<const void*>(&k_ring_inverse<256>),
         reinterpret_cast<const void*>(&k_ring_inverse<512>),
+        reinterpret_cast<const void*>(&k_ring_adjoint<256>),
+        reinterpret_cast<const void*>(&k_ring_adjoint<512>),
 
     };
     for (const void* f : fns) {

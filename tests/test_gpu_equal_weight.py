@@ -1,0 +1,174 @@
+"""GPU parity of the equal-weight analysis and its Jacobi iteration
+(hp2sph_analyze_iterative, HP2SPH_EQUAL_WEIGHT plans) against the FP64 oracle
+(oracle/healpix.py: eq. healsph and eq. uzawa with A = (4 pi / N) S^*)."""
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from gpu_util import white_map, cmb_map, rel_err
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+import paper_1904_10514_amd as P   # noqa: E402
+
+# Both sides are FP64 and differ in rounding order only: the longitude sums
+# (FFT of each ring here and in the oracle, aliased modes read off the same
+# DFT bins), the Legendre sums (GEMM against the synthesis tables vs the
+# oracle's recurrence), and per iteration one exact synthesis on each side.
+# Every term is a plain sum of at most N products of unit-size factors, so
+# the rounding stays ~p eps ~ 1e-14 relative to the largest coefficient.
+TOL = 1e-12
+
+
+def _dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def _oracle_batch(maps, nsides, lmaxs, niter):
+    return np.concatenate([O.analyze_jacobi(f, ns, lm, niter) for f, ns, lm in zip(maps, nsides, lmaxs)])
+
+
+@pytest.mark.parametrize("strategy", ["staged", "tables"])
+@pytest.mark.parametrize("nside", [4, 8, 16])
+def test_equal_weight_jacobi_vs_oracle(strategy, nside):
+    batch = 2
+    maps = [white_map(nside, 500 + 10 * nside + v) for v in range(batch)]
+    plan = P.Plan(nside, batch=batch, mode="equal_weight", strategy=strategy)
+    assert plan.strategy == strategy
+    dev = _dev(np.concatenate(maps))
+    for niter in (0, 1, 3):
+        a = plan.analyze_iterative(dev, niter)
+        torch.cuda.synchronize()
+        ref = _oracle_batch(maps, [nside] * batch, [2 * nside] * batch, niter)
+        err = rel_err(a.cpu().numpy(), ref)
+        print(f"{strategy} nside {nside} niter {niter}: {err:.3e}")
+        assert err < TOL
+    plan.close()
+
+
+@pytest.mark.parametrize("strategy", ["staged", "tables"])
+def test_equal_weight_truncated_lmax(strategy):
+    nside, lmax = 16, 25
+    maps = [cmb_map(0, v, nside, lmax)[0] for v in range(2)]
+    plan = P.Plan(nside, lmax, batch=2, mode="equal_weight", strategy=strategy)
+    a = plan.analyze_iterative(_dev(np.concatenate(maps)), 2)
+    torch.cuda.synchronize()
+    ref = _oracle_batch(maps, [nside] * 2, [lmax] * 2, 2)
+    assert rel_err(a.cpu().numpy(), ref) < TOL
+    plan.close()
+
+
+@pytest.mark.parametrize("strategy", ["auto", "tables"])
+def test_equal_weight_uneven_batch(strategy):
+    nsides, lmaxs = [8, 16, 8, 32], [16, 30, 13, 64]
+    maps = [white_map(ns, 700 + i) for i, ns in enumerate(nsides)]
+    plan = P.Plan(nsides, lmaxs, mode="equal_weight", strategy=strategy)
+    a = plan.analyze_iterative(_dev(np.concatenate(maps)), 2)
+    torch.cuda.synchronize()
+    ref = _oracle_batch(maps, nsides, lmaxs, 2)
+    a = a.cpu().numpy()
+    for i in range(len(nsides)):
+        s = slice(plan.alm_offsets[i], plan.alm_offsets[i + 1])
+        assert rel_err(a[s], ref[s]) < TOL
+    plan.close()
+
+
+def test_equal_weight_constant_map():
+    """a_0^0 = sqrt(4 pi) c; orders not divisible by 4 vanish (quarter-turn
+    symmetry of every ring)."""
+    nside, c = 32, 1.25
+    plan = P.Plan(nside, mode="equal_weight")
+    a = plan.analyze_iterative(_dev(np.full(O.npix(nside), c)), 0).cpu().numpy()
+    lmax = 2 * nside
+    assert a[0] == pytest.approx(np.sqrt(4 * np.pi) * c, rel=1e-14)
+    for m in range(lmax + 1):
+        if m % 4:
+            idx = [O.alm_index(l, m, lmax) for l in range(m, lmax + 1)]
+            assert np.max(np.abs(a[idx])) < 1e-13
+    plan.close()
+
+
+def test_analyze_runs_three_iterations():
+    nside = 8
+    f = _dev(white_map(nside, 42))
+    plan = P.Plan(nside, mode="equal_weight")
+    a3 = plan.analyze_iterative(f, 3).cpu().numpy()
+    a = plan.analyze(f).cpu().numpy()
+    assert np.array_equal(a, a3)
+    plan.close()
+
+
+def test_iterative_needs_an_equal_weight_plan():
+    plan = P.Plan(8, mode="f64")
+    with pytest.raises(P.HP2SPHError):
+        plan.analyze_iterative(_dev(white_map(8, 1)), 1)
+    plan.close()
+    plan = P.Plan(8, mode="equal_weight")
+    with pytest.raises(P.HP2SPHError):
+        plan.analyze_iterative(_dev(white_map(8, 1)), P.MAX_JACOBI + 1)
+    plan.close()
+
+
+# --- the benchmark size: 64 maps of nside 1024, lmax 2048 -------------------
+
+NSIDE, BATCH = 1024, 64
+SAMPLE_MAPS = (0, 63)
+# At p = 2048 the per-order synthesis tables the GPU contracts with carry the
+# rounding of up to p/2 Givens sweeps (their construction at plan set-up) and
+# every coefficient sums 2 nside rows of them: p eps sqrt(2 nside) =
+# 2048 * 1.1e-16 * 45 = 1.0e-11 relative to the largest coefficient.
+TOL_FULL = 1.0e-11
+SAMPLE_ORDERS = (0, 1, 2, 511, 1023, 1024, 2047, 2048)
+
+
+@pytest.fixture(scope="module")
+def fullsize():
+    npx = O.npix(NSIDE)
+    maps = np.empty((BATCH, npx))
+    for v in range(BATCH):
+        maps[v] = W.random_map(npx, W.rng_for(11, v))
+    dev = torch.from_numpy(maps.reshape(-1)).cuda()
+    plan = P.Plan(NSIDE, 2 * NSIDE, batch=BATCH, mode="equal_weight")
+    yield maps, dev, plan
+    plan.close()
+
+
+def test_fullsize_equal_weight_sampled_orders(fullsize):
+    """niter = 0 (eq. healsph) on sampled maps and orders, all l of each."""
+    maps, dev, plan = fullsize
+    assert plan.strategy == "tables"
+    a = plan.analyze_iterative(dev, 0)
+    torch.cuda.synchronize()
+    a = a.cpu().numpy().reshape(BATCH, -1)
+    lmax = 2 * NSIDE
+    worst = 0.0
+    for v in SAMPLE_MAPS:
+        ref = O.equal_weight_columns(maps[v], NSIDE, SAMPLE_ORDERS, lmax)
+        scale = max(np.max(np.abs(r)) for r in ref.values())
+        for m, r in ref.items():
+            idx = np.array([O.alm_index(l, m, lmax) for l in range(m, lmax + 1)])
+            worst = max(worst, np.max(np.abs(a[v, idx] - r)) / scale)
+    print(f"equal weight nside 1024 x 64, sampled: {worst:.3e}")
+    assert worst < TOL_FULL
+
+
+def test_fullsize_jacobi_residual_decreases(fullsize):
+    """Richardson on the normal equations with step 4 pi / N: the residual
+    r(k) = f - S a(k) obeys r(k+1) = (I - (4 pi / N) S S^*) r(k), whose
+    eigenvalues lie in (-1, 1] while lambda_max((4 pi / N) S^* S) < 2, so
+    |r(k)| cannot grow; on white noise it falls towards the least-squares
+    residual."""
+    _, dev, plan = fullsize
+    norms = []
+    for k in range(4):
+        a = plan.analyze_iterative(dev, k)
+        r = dev - plan.synthesize(a)
+        norms.append(float(torch.linalg.vector_norm(r)))
+        del a, r
+    print("residual norms:", norms)
+    for k in range(3):
+        assert norms[k + 1] <= norms[k] * (1 + 1e-12)
+    assert norms[1] < norms[0]

@@ -116,3 +116,15 @@ def test_jacobi_fixed_point_is_least_squares():
     assert np.max(np.abs(got - ref)) < 1e-12 * np.max(np.abs(ref))
     # a single equal-weight pass is visibly off (the quadrature is not exact)
     assert np.max(np.abs(analyze_equal_weight(f, nside, lmax) - ref)) > 1e-3 * np.max(np.abs(ref))
+
+
+def test_per_order_route_matches_full_analysis():
+    """equal_weight_columns (order-m Legendre functions evaluated directly)
+    equals analyze_equal_weight (the l-recurrence of all orders)."""
+    nside, lmax = 8, 16
+    f = W.random_map(O.npix(nside), W.rng_for(34, 0))
+    full = analyze_equal_weight(f, nside, lmax)
+    cols = O.equal_weight_columns(f, nside, [0, 1, 5, 15, 16], lmax)
+    for m, v in cols.items():
+        ref = np.array([full[O.alm_index(l, m, lmax)] for l in range(m, lmax + 1)])
+        assert np.max(np.abs(v - ref)) < 1e-14 * np.max(np.abs(full))
