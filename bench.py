@@ -76,17 +76,21 @@ def stage_work(stage, nside, nmaps, tsize, strategy="staged", mode="f64"):
     K = 2 * nside + 1
     N = [nmaps * 2 * nk[0], nmaps * 2 * nk[2]]
     npix = 12 * nside * nside * nmaps
-    if stage in ("gemm_analysis", "gemm_synthesis") and strategy == "tables":
-        return "flop", order_gemm_flops(nside, nmaps, stage == "gemm_synthesis")
+    if stage in ("gemm_analysis", "gemm_synthesis", "gemm_adjoint") and strategy == "tables":
+        return "flop", order_gemm_flops(nside, nmaps, stage != "gemm_analysis")
     if stage == "gemm_analysis":
         return "flop", sum(2 * nl[b] * K * N[b >> 1] for b in range(4))
     if stage == "gemm_synthesis":
         return "flop", sum(2 * nl[b] * K * N[b >> 1] for b in range(4))
+    if stage == "gemm_adjoint":
+        return "flop", sum(2 * nl[b] * (K - 1) * N[b >> 1] for b in range(4))
     if stage in ("sweep_analysis", "sweep_synthesis"):
         return "flop", 6 * sweep_rotations(nside, nmaps)
     rows = 2 * nside * (N[0] + N[1]) * 2   # values of Dsym rows 1..2 nside, both D+ and D-
     if stage == "ring_forward":
         return "byte", npix * 8 + rows * tsize
+    if stage == "ring_adjoint":
+        return "byte", npix * 8 + rows * 8
     if stage == "ring_inverse":
         return "byte", rows * 8 + npix * 8
     if stage == "residual_fold":
@@ -95,8 +99,9 @@ def stage_work(stage, nside, nmaps, tsize, strategy="staged", mode="f64"):
     n_alm = (p + 1) * (p + 2) // 2 * nmaps                # a_l^m, m <= l <= p: the live U entries
     alm_bytes = n_alm * 16
     if stage == "pack":
-        # the refinement packs a0 + correction: two FP32 U reads
-        n_in = 2 if mode == "f32_refine" else 1
+        # the refinement packs a0 + correction (two U reads); so does every
+        # Jacobi update of the equal-weight analysis but the first pack
+        n_in = 2 if mode in ("f32_refine", "equal_weight") else 1
         return "byte", n_in * n_alm * 2 * tsize + alm_bytes
     if stage == "unpack":
         if mode == "f32_refine":   # FP32 a0 widened to FP64 (the whole U rectangle is written)
@@ -116,6 +121,8 @@ def stage_bound(stage):
 
 
 def stage_dtype(stage, mode):
+    if mode == "equal_weight":
+        return "f64"
     if mode in ("f64", "f32_refine") and stage == "ring_forward":
         return "f64"
     if mode == "f64" or stage in ("sweep_synthesis", "gemm_synthesis", "ring_inverse", "unpack", "cl",
@@ -292,6 +299,56 @@ def uneven_main(args):
                       "modes": res}), flush=True)
 
 
+def equal_weight_main(args):
+    """The equal-weight analysis with Jacobi iterations (eqs. healsph, uzawa;
+    the method the paper compares HP2SPH with) on the headline inputs: 64 maps
+    of nside 1024, lmax 2048, niter = 3.  Prints its own JSON line (a secondary
+    measurement, not the headline)."""
+    import torch
+    import workloads as W
+    import paper_1904_10514_amd as P
+    nside, nmaps, niter = args.nside, args.batch, args.niter
+    lmax = 2 * nside
+    print(f"[bench] building inputs: {nmaps} maps, nside {nside}", file=sys.stderr, flush=True)
+    maps = make_inputs(torch, P, W, nside, nmaps)
+    t0 = time.perf_counter()
+    plan = P.Plan(nside, lmax, batch=nmaps, mode="equal_weight", strategy=args.strategy)
+    setup_s = time.perf_counter() - t0
+    alm = torch.empty(plan.alm_total, dtype=torch.complex128, device="cuda")
+    for _ in range(args.warmup):
+        plan.analyze_iterative(maps, niter, out=alm)
+    torch.cuda.synchronize()
+    plan.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plan.analyze_iterative(maps, niter, out=alm)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    plan.profile(False)
+    prof = plan.profile_read()
+    stages = {}
+    for st, (ms, n) in prof.items():
+        if n:
+            rl = roofline(st, "equal_weight", nside, nmaps, ms, n, plan.strategy)
+            stages[st] = {"ms_per_step": ms / args.steps, "launches": n, "achieved": rl["achieved"],
+                          "unit": rl["unit"], "frac": rl["frac"]}
+    dom = max((st for st in stages if st.startswith("gemm")), key=lambda st: stages[st]["ms_per_step"])
+    rl = roofline(dom, "equal_weight", nside, nmaps, prof[dom][0], prof[dom][1], plan.strategy)
+    rl["traffic"] = None
+    print(f"[bench] equal weight, {niter} Jacobi iterations: {1e3 * dt / args.steps:.2f} ms/step, "
+          f"set-up {setup_s:.1f} s", file=sys.stderr, flush=True)
+    print(json.dumps({"metric": f"maps analysed/s at nside={nside}, L={lmax}: equal-weight analysis + "
+                                f"{niter} Jacobi iterations (FP64)",
+                      "value": nmaps * args.steps / dt, "unit": "maps/s", "n_gpus": 1, "steps": args.steps,
+                      "warmup": args.warmup, "ms_per_step": 1e3 * dt / args.steps, "higher_is_better": True,
+                      "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+                      "config": {"workload": f"equal_weight_nside{nside}_L{lmax}_b{nmaps}", "nside": nside,
+                                 "lmax": lmax, "batch": nmaps, "niter": niter, "strategy": plan.strategy},
+                      "setup_s": setup_s, "roofline": rl, "stages": stages}), flush=True)
+    plan.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -303,8 +360,10 @@ def main():
     ap.add_argument("--strategy", default="auto", choices=["auto", "staged", "tables"])
     ap.add_argument("--modes", default="f32_refine,f64",
                     help="precision modes to time; the headline is f32_refine (profiling runs may pick one)")
-    ap.add_argument("--workload", default="headline", choices=["headline", "uneven"],
-                    help="headline: 64 maps of nside 1024; uneven: 256 maps of nside 64..512 (secondary)")
+    ap.add_argument("--workload", default="headline", choices=["headline", "uneven", "equal_weight"],
+                    help="headline: 64 maps of nside 1024; uneven: 256 maps of nside 64..512; equal_weight: "
+                         "the equal-weight analysis with Jacobi iterations on the headline inputs (secondary)")
+    ap.add_argument("--niter", type=int, default=3, help="Jacobi iterations of the equal_weight workload")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (maps of a batch "
@@ -312,6 +371,9 @@ def main():
         sys.exit(2)
     if args.workload == "uneven":
         uneven_main(args)
+        return
+    if args.workload == "equal_weight":
+        equal_weight_main(args)
         return
 
     import numpy as np
