@@ -94,7 +94,9 @@ def stage_work(stage, nside, nmaps, tsize, strategy="staged", mode="f64"):
     if stage == "ring_inverse":
         return "byte", rows * 8 + npix * 8
     if stage == "residual_fold":
-        return "byte", rows * (8 + 8 + 4)
+        # refinement: read Df and the synthesis output (FP64), write FP32;
+        # equal-weight iteration: read Wf and the synthesis output, write Wr (FP64)
+        return "byte", rows * (8 + 8 + (8 if mode == "equal_weight" else 4))
     u_vals = sum(nl[b] * N[b >> 1] for b in range(4))   # values of the U blocks (rectangle)
     n_alm = (p + 1) * (p + 2) // 2 * nmaps                # a_l^m, m <= l <= p: the live U entries
     alm_bytes = n_alm * 16

@@ -212,7 +212,8 @@ const char* hp2sph_last_error(void);
  * 3 analysis Givens sweeps (S4), 4 pack a_lm, 5 unpack a_lm (in the
  * refinement: FP32 a0 widened to FP64 in place of an unpack), 6 synthesis
  * sweeps, 7 synthesis GEMM, 8 inverse ring transform, 9 C_l (S5),
- * 10 refinement residual in ring-Fourier space, 11 longitude sums of the
+ * 10 residual in ring-Fourier space (the refinement's, and the Jacobi
+ * iteration's longitude sums of f - S a), 11 longitude sums of the
  * equal-weight analysis, 12 its transposed-evaluation GEMM.
  * Errors: ESTATE, EINVAL, EDEVICE.
  */

@@ -177,7 +177,7 @@ struct hp2sph_plan_s {
     size_t ws_bytes = 0;
     size_t off_Df = 0, off_Dr = 0;    // refinement: FP64 ring coefficients, FP32 residual coefficients
     size_t off_Ua = 0;                // refinement: FP32 a0 in the U layout; equal weight: FP64 a in the U layout
-    size_t off_R = 0;                 // equal weight: residual maps f - S a (FP64, all maps)
+    size_t off_Wf = 0, off_Wr = 0;   // equal weight: longitude sums of the maps and of the residual
     int strategy = 0;                 // requested HP2SPH_STRATEGY_*
     uint32_t magic = 0x48503253u;
 };
@@ -713,8 +713,9 @@ int analysis_pass(Group& G, const double* maps_in, double* alm, void* ws, hipStr
     return HP2SPH_OK;
 }
 
-// FP64 synthesis of one group: alm -> out (or minus_from - synthesis).
-int synthesis_pass(Group& G, const double* alm, double* out, const double* minus_from, void* ws, hipStream_t s) {
+// FP64 synthesis of one group up to the ring coefficients: alm -> Dsym rows
+// 1 .. 2 nside of the D region (D+- of every mode k = 0..p per ring pair).
+int synthesis_coefficients(Group& G, const double* alm, void* ws, hipStream_t s) {
     Blocks4<double> D = blocks_at<double>(ws, G.off_D, G, G.rows_D);
     Blocks4<double> U = blocks_at<double>(ws, G.off_U, G, G.rows_U);
     const bool tab = G.syn64.n > 0 && G.tables;
@@ -730,6 +731,15 @@ int synthesis_pass(Group& G, const double* alm, double* out, const double* minus
     }
     const GemmList<double>& gl = tab ? G.syn64 : G.syn64_staged;
     STAGE(7, launch_gemm<double>(gl.dev, gl.tmap, gl.slots, U.p[0], D.p[0], s));
+    return HP2SPH_OK;
+}
+
+// FP64 synthesis of one group: alm -> out (or minus_from - synthesis).
+int synthesis_pass(Group& G, const double* alm, double* out, const double* minus_from, void* ws, hipStream_t s) {
+    if (int e = synthesis_coefficients(G, alm, ws, s)) return e;
+    Blocks4<double> D = blocks_at<double>(ws, G.off_D, G, G.rows_D);
+    GroupDims dd = G.dims;
+    if (!(G.syn64.n > 0 && G.tables)) set_layout(dd, false);
     STAGE(8, launch_ring_inverse(cblocks(D), G.rings, G.t64.fft, out, minus_from, G.d_map_off, dd, s));
     return HP2SPH_OK;
 }
@@ -779,17 +789,14 @@ int refine_pass(hp2sph_plan_t plan, Group& G, const double* maps, double* alm, v
     return HP2SPH_OK;
 }
 
-// Equal-weight analysis of one group, eq. (healsph) (Sec. 2.2):
-// a = (4 pi / N) S^* x for the maps x, i.e. the transposed stages of the
-// synthesis: longitude sums of every ring (aliased modes kept), the
-// transposed evaluation tables, and (staged) the analysis sweeps.  Written
-// to alm, or added to it (the update of the Jacobi iteration).
-int equal_weight_pass(hp2sph_plan_t plan, Group& G, const double* x, double* alm, bool add, void* ws,
-                      hipStream_t s) {
-    Blocks4<double> W = blocks_at<double>(ws, G.off_D, G, G.rows_D);
+// Equal-weight analysis of one group, eq. (healsph) (Sec. 2.2), from weighted
+// longitude sums W (Dsym rows 1 .. 2 nside, see launch_ring_adjoint):
+// a = sum_h Tsyn[l][h] W[h], the synthesis transposed -- the transposed
+// evaluation tables and (staged) the analysis sweeps.  Written to alm, or
+// added to it (the update of the Jacobi iteration).
+int equal_weight_apply(hp2sph_plan_t plan, Group& G, Blocks4<double> W, double* alm, bool add, void* ws,
+                       hipStream_t s) {
     Blocks4<double> U = blocks_at<double>(ws, G.off_U, G, G.rows_U);
-    const double scale = 4.0 * 3.14159265358979323846 / (12.0 * double(G.nside) * double(G.nside));
-    STAGE(11, launch_ring_adjoint(x, G.d_map_off, G.rings, G.t64.fft, W, G.dims, scale, s));
     STAGE(12, launch_gemm<double>(G.adj64.dev, G.adj64.tmap, G.adj64.slots, W.p[0], U.p[0], s));
     if (!G.tables) {
         Blocks4<const double> Gv;
@@ -809,13 +816,21 @@ int equal_weight_pass(hp2sph_plan_t plan, Group& G, const double* x, double* alm
 }
 
 // The Jacobi iteration of eq. (uzawa) with A = (4 pi / N) S^* (Sec. 2.2):
-// a0 = A f, then niter times r = f - S a, a = a + A r (all FP64).
+// a0 = A f, then niter times r = f - S a, a = a + A r (all FP64).  A is
+// linear and starts with the longitude sums, so A r = A' (Wf - W(S a)) with
+// Wf = W(f) computed once and W(S a) formed from the synthesis coefficients
+// (k_adjoint_residual): the residual map is never materialised.
 int jacobi_pass(hp2sph_plan_t plan, Group& G, const double* maps, double* alm, int niter, void* ws, hipStream_t s) {
-    if (int e = equal_weight_pass(plan, G, maps, alm, false, ws, s)) return e;
-    double* R = reinterpret_cast<double*>(static_cast<char*>(ws) + plan->off_R);
+    Blocks4<double> Wf = blocks_at<double>(ws, plan->off_Wf, G, G.rows_D);
+    Blocks4<double> Wr = blocks_at<double>(ws, plan->off_Wr, G, G.rows_D);
+    Blocks4<double> Gs = blocks_at<double>(ws, G.off_D, G, G.rows_D);
+    const double scale = 4.0 * 3.14159265358979323846 / (12.0 * double(G.nside) * double(G.nside));
+    STAGE(11, launch_ring_adjoint(maps, G.d_map_off, G.rings, G.t64.fft, Wf, G.dims, scale, s));
+    if (int e = equal_weight_apply(plan, G, Wf, alm, false, ws, s)) return e;
     for (int it = 0; it < niter; ++it) {
-        if (int e = synthesis_pass(G, alm, R, maps, ws, s)) return e;
-        if (int e = equal_weight_pass(plan, G, R, alm, true, ws, s)) return e;
+        if (int e = synthesis_coefficients(G, alm, ws, s)) return e;
+        STAGE(10, launch_adjoint_residual(cblocks(Wf), cblocks(Gs), Wr, G.rings, G.dims, scale, s));
+        if (int e = equal_weight_apply(plan, G, Wr, alm, true, ws, s)) return e;
     }
     return HP2SPH_OK;
 }
@@ -922,11 +937,15 @@ int hp2sph_plan_create_ex(const int32_t* nside, const int32_t* lmax, int32_t bat
             plan->off_Ua = ws + 2 * max_D;
             ws += 2 * max_D + max_U;
         } else if (mode == HP2SPH_EQUAL_WEIGHT) {
-            size_t max_U = 0;
-            for (auto& g : plan->groups) max_U = std::max(max_U, align_up(g->bytes_U));
+            size_t max_D = 0, max_U = 0;
+            for (auto& g : plan->groups) {
+                max_D = std::max(max_D, align_up(g->bytes_D));
+                max_U = std::max(max_U, align_up(g->bytes_U));
+            }
             plan->off_Ua = ws;
-            plan->off_R = ws + max_U;
-            ws += max_U + align_up(size_t(plan->total_pix) * sizeof(double));
+            plan->off_Wf = ws + max_U;
+            plan->off_Wr = ws + max_U + max_D;
+            ws += max_U + 2 * max_D;
         }
         plan->ws_bytes = ws;
         // kernels with more than 64 KB of dynamic LDS

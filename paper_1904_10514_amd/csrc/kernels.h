@@ -101,6 +101,13 @@ hipError_t launch_ring_forward(const double* maps, const int64_t* map_off, RingT
 hipError_t launch_ring_adjoint(const double* maps, const int64_t* map_off, RingTab rt, FftTab<double> ft,
                                Blocks4<double> W, const GroupDims& g, double scale, hipStream_t s);
 
+// Equal-weight iteration: Wr = Wf - W(S a) for Dsym rows 1 .. 2 nside, with
+// W(S a) the weighted longitude sums (as launch_ring_adjoint writes them) of
+// the rings synthesized from the synthesis GEMM output Gs, formed from the
+// coefficients by alias-chain sums (no transform).
+hipError_t launch_adjoint_residual(Blocks4<const double> Wf, Blocks4<const double> Gs, Blocks4<double> Wr, RingTab rt,
+                                   const GroupDims& g, double scale, hipStream_t s);
+
 // Refinement residual in ring-Fourier space: Dr = Df - Ring(Synth(Gs)) for
 // Dsym rows 1 .. 2 nside (Gs: synthesis GEMM output, Df: FP64 forward ring
 // coefficients of the maps), written in FP32.

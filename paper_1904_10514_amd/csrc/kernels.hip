@@ -1660,6 +1660,117 @@ hipError_t launch_residual_fold(Blocks4<const double> Df, Blocks4<const double> 
 }
 
 // ---------------------------------------------------------------------------
+// Equal-weight iteration: the residual's longitude sums in ring-Fourier space
+// ---------------------------------------------------------------------------
+//
+// For the weighted longitude sums Wf of the maps (k_ring_adjoint) and the
+// synthesis GEMM output Gs (coefficients D_k, k = 0..p, of S a per ring pair,
+// D_{-k} = conj D_k), writes Wr = Wf - W(S a) for Dsym rows 1 .. 2 nside: the
+// longitude sums of the synthesized ring x_q = sum_{|k| <= p} D_k e^{i k
+// lambda_q} follow from the coefficients without a transform,
+//   F(m) = sum_q x_q e^{-i m lambda_q} = n sum_{k = m mod n} D_k e^{i (k-m) phi0}
+//        = n s^q (A_t + s conj B_t),   t = m mod n, q = m div n,
+//   A_t = sum_b s^b D_{t + b n},  B_t = sum_b s^b D_{n - t + b n}  (indices <= p),
+// s = -1 on a shifted ring (phi0 = pi / n), 1 otherwise.  Each bin t is
+// summed once and written to every m = t + q n <= p.  Rings with n > p need
+// only t = m, with at most one mirror term.  N and S rings share n and the
+// shift, and D_k = D+ +- D-, so one pass gives both; then
+// W+- = scale (F_N +- F_S) (equator: scale F_N, 0) as in k_ring_adjoint.
+// Layout and workgroup shape as k_residual_fold: one ring pair of 16
+// consecutive maps, lane bits 0..3 pick the map.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_adjoint_residual(Blocks4<const double> Wf, Blocks4<const double> Gs,
+                                                         Blocks4<double> Wr, RingTab rt, GroupDims g,
+                                                         double scale) {
+    constexpr int SL = NT / kFoldMaps;   // bin slots per map
+    const int mgroups = (g.nmaps + kFoldMaps - 1) / kFoldMaps;
+    int mg, h;
+    ring_block(mgroups, 2 * g.nside, mg, h);
+    const int m8 = threadIdx.x % kFoldMaps, slot = threadIdx.x / kFoldMaps;
+    const int map = mg * kFoldMaps + m8;
+    if (map >= g.nmaps) return;   // no barriers below
+    const int ns = g.nside, p = g.p;
+    const bool equator = (h == 2 * ns);
+    const int n = rt.n[h - 1];
+    const bool shifted = rt.shifted[h - 1] != 0;
+    const double s = shifted ? -1.0 : 1.0;
+    const double dn = double(n);
+    auto offs = [&](int k) -> int64_t {
+        const int kpar = k & 1, kk = k >> 1;
+        return int64_t(h) * g.N[kpar] + int64_t(map) * g.cm[kpar] + int64_t(kk) * g.ck[kpar];
+    };
+    // D_k of the north and south rings
+    auto coef = [&](int k, C2<double>& dN, C2<double>& dS) {
+        const int64_t o = offs(k);
+        const D2 vp = *reinterpret_cast<const D2*>(Gs.p[2 * (k & 1)] + o);
+        const D2 vm = *reinterpret_cast<const D2*>(Gs.p[2 * (k & 1) + 1] + o);
+        dN = {vp.x + vm.x, vp.y + vm.y};
+        dS = {vp.x - vm.x, vp.y - vm.y};
+    };
+    // Wr at mode m from the ring sums F_N, F_S
+    auto emit = [&](int m, C2<double> FN, C2<double> FS) {
+        C2<double> wp, wm;
+        if (equator) {
+            wp = cscale(FN, scale);
+            wm = {0.0, 0.0};
+        } else {
+            wp = cscale(cadd(FN, FS), scale);
+            wm = cscale(csub(FN, FS), scale);
+        }
+        const int64_t o = offs(m);
+        const int kpar = m & 1;
+        const D2 fp = *reinterpret_cast<const D2*>(Wf.p[2 * kpar] + o);
+        const D2 fm = *reinterpret_cast<const D2*>(Wf.p[2 * kpar + 1] + o);
+        *reinterpret_cast<D2*>(Wr.p[2 * kpar] + o) = D2{fp.x - wp.x, fp.y - wp.y};
+        *reinterpret_cast<D2*>(Wr.p[2 * kpar + 1] + o) = D2{fm.x - wm.x, fm.y - wm.y};
+    };
+    if (n > p) {
+        // t = m; A_m = D_m, B_m = D_{n - m} when n - m <= p
+        for (int m = slot; m <= p; m += SL) {
+            C2<double> XN, XS;
+            coef(m, XN, XS);
+            if (n - m <= p) {
+                C2<double> bN, bS;
+                coef(n - m, bN, bS);
+                XN = cadd(XN, cscale(cconj(bN), s));
+                XS = cadd(XS, cscale(cconj(bS), s));
+            }
+            emit(m, cscale(XN, dn), cscale(XS, dn));
+        }
+    } else {
+        for (int t = slot; t < n; t += SL) {
+            C2<double> AN = {0.0, 0.0}, AS = {0.0, 0.0}, BN = {0.0, 0.0}, BS = {0.0, 0.0};
+            double sg = 1.0;
+            for (int k = t; k <= p; k += n, sg *= s) {
+                C2<double> dN, dS;
+                coef(k, dN, dS);
+                AN = cadd(AN, cscale(dN, sg));
+                AS = cadd(AS, cscale(dS, sg));
+            }
+            sg = 1.0;
+            for (int k = n - t; k <= p; k += n, sg *= s) {
+                C2<double> dN, dS;
+                coef(k, dN, dS);
+                BN = cadd(BN, cscale(dN, sg));
+                BS = cadd(BS, cscale(dS, sg));
+            }
+            const C2<double> XN = cadd(AN, cscale(cconj(BN), s));
+            const C2<double> XS = cadd(AS, cscale(cconj(BS), s));
+            double sq = dn;
+            for (int m = t; m <= p; m += n, sq *= s) emit(m, cscale(XN, sq), cscale(XS, sq));
+        }
+    }
+}
+
+hipError_t launch_adjoint_residual(Blocks4<const double> Wf, Blocks4<const double> Gs, Blocks4<double> Wr, RingTab rt,
+                                   const GroupDims& g, double scale, hipStream_t s) {
+    const int mgroups = (g.nmaps + kFoldMaps - 1) / kFoldMaps;
+    dim3 grid(mgroups, 2 * g.nside);
+    hipLaunchKernelGGL(k_adjoint_residual<256>, grid, dim3(256), 0, s, Wf, Gs, Wr, rt, g, scale);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // S5: C_l
 // ---------------------------------------------------------------------------
 
