@@ -55,3 +55,40 @@ def test_nside2048_refinement_recovers_order_one_fields(fields):
     print(f"order-1 fields, nside 2048 x 2: FP32 + refinement {e1:.3e}, synthesis {ef:.3e}")
     assert e1 < 1e-10
     assert ef < 1e-12
+
+
+def test_nside2048_equal_weight_sampled_orders():
+    """Equal-weight analysis (eq. healsph) at nside 2048 (staged: transposed
+    evaluation + analysis sweeps, 8192-point longitude sums) on white noise,
+    sampled orders of both maps against the oracle's per-order route; and the
+    Jacobi residual |f - S a(k)| does not grow over two iterations."""
+    import oracle as O
+    import workloads as W
+    npx = O.npix(NSIDE)
+    maps = np.stack([W.random_map(npx, W.rng_for(12, v)) for v in range(BATCH)])
+    dev = torch.from_numpy(maps.reshape(-1)).cuda()
+    plan = P.Plan(NSIDE, LMAX, batch=BATCH, mode="equal_weight")
+    assert plan.strategy == "staged"
+    a = plan.analyze_iterative(dev, 0)
+    torch.cuda.synchronize()
+    a_h = a.cpu().numpy().reshape(BATCH, -1)
+    orders = (0, 1, 3, 2047, 2048, 4095, 4096)
+    worst = 0.0
+    for v in range(BATCH):
+        ref = O.equal_weight_columns(maps[v], NSIDE, orders, LMAX)
+        scale = max(np.max(np.abs(r)) for r in ref.values())
+        for m, r in ref.items():
+            idx = np.array([O.alm_index(l, m, LMAX) for l in range(m, LMAX + 1)])
+            worst = max(worst, np.max(np.abs(a_h[v, idx] - r)) / scale)
+    print(f"equal weight nside 2048 x 2, sampled: {worst:.3e}")
+    # staged: up to p/2 sweeps on each coefficient and 2 nside-term sums,
+    # p eps sqrt(2 nside) = 4096 * 1.1e-16 * 64 = 2.9e-11
+    assert worst < 2.9e-11
+    norms = []
+    for k in range(3):
+        ak = plan.analyze_iterative(dev, k)
+        norms.append(float(torch.linalg.vector_norm(dev - plan.synthesize(ak))))
+        del ak
+    print("residual norms:", norms)
+    assert norms[1] <= norms[0] * (1 + 1e-12) and norms[2] <= norms[1] * (1 + 1e-12)
+    plan.close()
