@@ -117,7 +117,10 @@ __device__ __forceinline__ void dft_regs(C2<T>* v) {
 // w = e^{-2 pi i (j mod Ns) / (Ns R)}, transforms, and stores output r at
 // (j / Ns) Ns R + (j mod Ns) + r Ns of the LDS buffer.  After the last pass
 // the buffer holds the DFT in natural order.  Reads complete (barrier) before
-// any thread writes, so the pass may read the buffer it writes.
+// any thread writes, so the pass may read the buffer it writes.  The NT
+// threads are threadIdx.x mod NT: a workgroup of 2 NT threads can run two
+// transforms of the same length side by side (every thread meets every
+// barrier).
 template <class T, int R, int NT, int MAXV, class Load>
 __device__ __forceinline__ void stockham_pass(C2<T>* buf, int M, int lgNs, const T* tw, int fft_max, Load load) {
     constexpr int NG = MAXV / R;
@@ -125,7 +128,7 @@ __device__ __forceinline__ void stockham_pass(C2<T>* buf, int M, int lgNs, const
     C2<T> v[MAXV];
 #pragma unroll
     for (int i = 0; i < NG; ++i) {
-        const int j = threadIdx.x + NT * i;
+        const int j = (threadIdx.x & (NT - 1)) + NT * i;
         if (j < G) {
 #pragma unroll
             for (int r = 0; r < R; ++r) v[i * R + r] = load(j + r * G);
@@ -158,7 +161,7 @@ __device__ __forceinline__ void stockham_pass(C2<T>* buf, int M, int lgNs, const
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < NG; ++i) {
-        const int j = threadIdx.x + NT * i;
+        const int j = (threadIdx.x & (NT - 1)) + NT * i;
         if (j < G) {
             const int base = ((j >> lgNs) << lgNs) * R + (j & (Ns - 1));
 #pragma unroll
@@ -257,6 +260,34 @@ constexpr int kRingKPT = 9;   // ceil((2 nside + 1) / NT) at the largest nside o
 
 __host__ __device__ constexpr int ring_threads(int fft_max) { return fft_max <= 4096 ? 256 : 512; }
 
+// D_k, k <= p, of one ring from the half-length DFT R of its points (Step 1):
+// the real DFT X_k = E_k + e^{-2 pi i k / n} O_k from the transform of
+// z_q = x_{2q} + i x_{2q+1}, shifted to lambda = 0 on a shifted ring, scaled
+// by 1/n; the Nyquist rule at k = n/2 (R3) and zero above.
+template <class T>
+__device__ __forceinline__ C2<T> ring_coeff(const DftOut<T>& R, int k, int n, bool shifted, int p, const T* roots) {
+    const int L = n >> 1;
+    const T invn = T(1) / T(n);
+    C2<T> d = {T(0), T(0)};
+    if (k <= p) {
+        if (k < L) {
+            const C2<T> zk = R.Z(k), zl = R.Z(k == 0 ? 0 : L - k);
+            const C2<T> e = cscale(cadd(zk, cconj(zl)), T(0.5));
+            const C2<T> dlt = csub(zk, cconj(zl));
+            const C2<T> o = {T(0.5) * dlt.y, -T(0.5) * dlt.x};   // (zk - conj zl) / (2i)
+            C2<T> X = cadd(e, cmul(ldc(roots, 2 * k), o));
+            if (shifted) X = cmul(X, ldc(roots, k));
+            d = cscale(X, invn);
+        } else if (k == L) {
+            const C2<T> z0 = R.Z(0);
+            const T alpha = (z0.x - z0.y) * invn;
+            if (L < p) d = {T(0), -T(0.5) * alpha};   // polar ring: alpha sin(L lambda)
+            else d = {shifted ? T(0) : T(0.5) * alpha, T(0)};
+        }
+    }
+    return d;
+}
+
 template <class T, int NT>
 __device__ __forceinline__ void ring_spectrum(const double* x, int n, bool shifted, int p, FftTab<T> ft, C2<T>* buf,
                               C2<T> (&D)[kRingKPT]) {
@@ -271,30 +302,18 @@ __device__ __forceinline__ void ring_spectrum(const double* x, int n, bool shift
         return {T(v.x), T(v.y)};
     };
     const DftOut<T> R = ring_dft<T, NT, kRingMaxV>(buf, L, Mb, chirp, chirpfft, ft.twiddle, ft.fft_max, src);
-    const T invn = T(1) / T(n);
 #pragma unroll
-    for (int i = 0; i < kRingKPT; ++i) {
-        const int k = threadIdx.x + i * NT;
-        C2<T> d = {T(0), T(0)};
-        if (k <= p) {
-            if (k < L) {
-                const C2<T> zk = R.Z(k), zl = R.Z(k == 0 ? 0 : L - k);
-                const C2<T> e = cscale(cadd(zk, cconj(zl)), T(0.5));
-                const C2<T> dlt = csub(zk, cconj(zl));
-                const C2<T> o = {T(0.5) * dlt.y, -T(0.5) * dlt.x};   // (zk - conj zl) / (2i)
-                C2<T> X = cadd(e, cmul(ldc(roots, 2 * k), o));
-                if (shifted) X = cmul(X, ldc(roots, k));
-                d = cscale(X, invn);
-            } else if (k == L) {
-                const C2<T> z0 = R.Z(0);
-                const T alpha = (z0.x - z0.y) * invn;
-                if (L < p) d = {T(0), -T(0.5) * alpha};   // polar ring: alpha sin(L lambda)
-                else d = {shifted ? T(0) : T(0.5) * alpha, T(0)};
-            }
-        }
-        D[i] = d;
-    }
+    for (int i = 0; i < kRingKPT; ++i) D[i] = ring_coeff(R, threadIdx.x + i * NT, n, shifted, p, roots);
     // The next transform's first pass synchronises before it writes the buffer.
+}
+
+// LDS slots of one half of the ring kernels' buffer (a transform of up to
+// fft_max / 2 points) and the whole buffer (one transform of fft_max points,
+// or two halves side by side).
+__host__ __device__ constexpr int ring_half_slots(int fft_max) { return fft_max / 2 + fft_max / 32 + 1; }
+__host__ __device__ constexpr int ring_buffer_slots(int fft_max) {
+    return (fft_max + fft_max / 16 + 1) > 2 * ring_half_slots(fft_max) ? fft_max + fft_max / 16 + 1
+                                                                         : 2 * ring_half_slots(fft_max);
 }
 
 template <class T, int NT>
@@ -307,28 +326,8 @@ __global__ __launch_bounds__(NT) void k_ring_forward(const double* __restrict__ 
     ring_block(g.nmaps, 2 * g.nside, b, h);
     const int ns = g.nside, p = g.p;
     const double* m = maps + map_off[b];
-    C2<T> DN[kRingKPT], DS[kRingKPT];
-    {
-        const int r0 = h - 1;
-        ring_spectrum<T, NT>(m + rt.start[r0], rt.n[r0], rt.shifted[r0] != 0, p, ft, buf, DN);
-    }
     const bool equator = (h == 2 * ns);
-    if (!equator) {
-        const int r0 = 4 * ns - h - 1;
-        ring_spectrum<T, NT>(m + rt.start[r0], rt.n[r0], rt.shifted[r0] != 0, p, ft, buf, DS);
-    }
-#pragma unroll
-    for (int i = 0; i < kRingKPT; ++i) {
-        const int k = threadIdx.x + i * NT;
-        if (k > p) continue;
-        C2<T> dp, dm;
-        if (equator) {
-            dp = DN[i];
-            dm = {T(0), T(0)};
-        } else {
-            dp = cscale(cadd(DN[i], DS[i]), T(0.5));
-            dm = cscale(csub(DN[i], DS[i]), T(0.5));
-        }
+    auto store = [&](int k, C2<T> dp, C2<T> dm) {
         const int kpar = k & 1, kk = k >> 1;
         const int64_t col = int64_t(b) * g.cm[kpar] + int64_t(kk) * g.ck[kpar];
         const int64_t row = int64_t(h) * g.N[kpar];
@@ -338,6 +337,60 @@ __global__ __launch_bounds__(NT) void k_ring_forward(const double* __restrict__ 
         bp[row + col + 1] = dp.y;
         bm[row + col] = dm.x;
         bm[row + col + 1] = dm.y;
+    };
+    {
+        // Both rings of a pair have n points and the same shift.  When their
+        // transforms fit in half the buffer (every ring but the large
+        // Bluestein ones and the equator), the two halves of the workgroup
+        // transform them side by side.
+        const int n = rt.n[h - 1], j = n >> 2, L = n >> 1;
+        const int Mfft = ft.chirpm[j] ? ft.chirpm[j] : L;
+        if (!equator && Mfft <= (ft.fft_max >> 1)) {
+            constexpr int NH = NT / 2;
+            const int half = threadIdx.x / NH;   // 0: ring h (north), 1: ring 4 nside - h
+            const int r0 = half ? 4 * ns - h - 1 : h - 1;
+            const bool shifted = rt.shifted[h - 1] != 0;
+            const double* x = m + rt.start[r0];
+            const T* chirp = ft.chirp + 2 * ft.chirpoff[j];
+            const T* chirpfft = ft.chirpfft + 2 * ft.chirpfftoff[j];
+            const T* roots = ft.roots + 2 * ft.rootoff[j];
+            auto src = [x](int q) -> C2<T> {
+                const D2 v = *reinterpret_cast<const D2*>(x + 2 * q);
+                return {T(v.x), T(v.y)};
+            };
+            const int hs = ring_half_slots(ft.fft_max);
+            DftOut<T> R = ring_dft<T, NH, kRingMaxV>(buf + half * hs, L, ft.chirpm[j], chirp, chirpfft, ft.twiddle,
+                                                     ft.fft_max, src);
+            __syncthreads();   // both spectra are in LDS
+            DftOut<T> RN = R, RS = R;
+            RN.buf = buf;
+            RS.buf = buf + hs;
+#pragma unroll
+            for (int i = 0; i < kRingKPT; ++i) {
+                const int k = threadIdx.x + i * NT;
+                if (k > p) continue;
+                const C2<T> dn = ring_coeff(RN, k, n, shifted, p, roots);
+                const C2<T> ds = ring_coeff(RS, k, n, shifted, p, roots);
+                store(k, cscale(cadd(dn, ds), T(0.5)), cscale(csub(dn, ds), T(0.5)));
+            }
+            return;
+        }
+    }
+    C2<T> DN[kRingKPT], DS[kRingKPT];
+    {
+        const int r0 = h - 1;
+        ring_spectrum<T, NT>(m + rt.start[r0], rt.n[r0], rt.shifted[r0] != 0, p, ft, buf, DN);
+    }
+    if (!equator) {
+        const int r0 = 4 * ns - h - 1;
+        ring_spectrum<T, NT>(m + rt.start[r0], rt.n[r0], rt.shifted[r0] != 0, p, ft, buf, DS);
+    }
+#pragma unroll
+    for (int i = 0; i < kRingKPT; ++i) {
+        const int k = threadIdx.x + i * NT;
+        if (k > p) continue;
+        if (equator) store(k, DN[i], C2<T>{T(0), T(0)});
+        else store(k, cscale(cadd(DN[i], DS[i]), T(0.5)), cscale(csub(DN[i], DS[i]), T(0.5)));
     }
 }
 
@@ -451,7 +504,9 @@ __global__ __launch_bounds__(NT) void k_ring_adjoint(const double* __restrict__ 
 
 static size_t lds_slots_bytes(int slots, size_t elem) { return size_t(slots + slots / 16 + 1) * elem; }
 
-static size_t ring_lds_bytes(int fft_max, size_t elem) { return lds_slots_bytes(std::max(fft_max, 256), elem); }
+static size_t ring_lds_bytes(int fft_max, size_t elem) {
+    return size_t(ring_buffer_slots(std::max(fft_max, 256))) * elem;
+}
 
 template <class T>
 hipError_t launch_ring_forward(const double* maps, const int64_t* map_off, RingTab rt, FftTab<T> ft, Blocks4<T> D,
