@@ -357,6 +357,11 @@ void upload_list(Group& G, std::vector<GemmProblem<T>>& v, GemmList<T>& out) {
     // the GEMM kernel reads B as aligned (re, im) pairs
     for (const auto& P : v)
         if ((P.boff | P.ldb | P.bps | P.N) & 1) throw std::runtime_error("GEMM problem with unpaired B columns");
+    // its buffer loads address one 16-row k step with 32-bit byte offsets
+    // (elements of up to 8 bytes)
+    for (const auto& P : v)
+        if (P.lda >= (int64_t(1) << 24) || P.ldb >= (int64_t(1) << 24))
+            throw std::runtime_error("GEMM row stride too large for the 32-bit offsets of the staging loads");
     // longest problems first, then tile ranges in that order
     std::stable_sort(v.begin(), v.end(), [](const GemmProblem<T>& x, const GemmProblem<T>& y) {
         return int64_t(x.M) * x.K > int64_t(y.M) * y.K;

@@ -600,15 +600,50 @@ constexpr int GBM = 128, GBN = 128, GBK = 16;
 // k rows that one MFMA operand load touches on disjoint bank ranges.
 constexpr int GPAD = 16;
 
-// 16-byte vector of T (4 floats / 2 doubles) and the 2-element pair (re, im).
+// 16-byte vector of T (4 floats / 2 doubles), as written to LDS.
 template <class T>
 struct alignas(16) V16 {
     T v[16 / sizeof(T)];
 };
+
+typedef double v2d __attribute__((ext_vector_type(2)));
+typedef float v2f __attribute__((ext_vector_type(2)));
+// native 16-byte vector of T and native (re, im) pair of T
 template <class T>
-struct alignas(2 * sizeof(T)) V2 {
-    T v[2];
+struct Vec16;
+template <>
+struct Vec16<float> {
+    using type = v4f;
 };
+template <>
+struct Vec16<double> {
+    using type = v2d;
+};
+template <class T>
+struct Vec2;
+template <>
+struct Vec2<float> {
+    using type = v2f;
+};
+template <>
+struct Vec2<double> {
+    using type = v2d;
+};
+
+// Raw buffer descriptors (gfx9 family): word 3 selects 32-bit data with no
+// swizzle, and a byte offset at or past the descriptor's record count reads
+// as zero.  kBufferOOB is past every descriptor the GEMM builds (records stay
+// below 2^31, checked when a problem list is built).
+constexpr int kBufferWord3 = 0x00020000;
+constexpr int kBufferOOB = int(0x80000000u);
+
+// sizeof(V) bytes (4, 8 or 16) at byte offset `off` of the buffer
+template <class V>
+__device__ __forceinline__ V buffer_load(__amdgpu_buffer_rsrc_t r, int off) {
+    if constexpr (sizeof(V) == 16) return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+    else if constexpr (sizeof(V) == 8) return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+    else return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
 
 // C[m][n] = sum_k A[k][m] B[k][n] for a list of problems; one 128 x 128 tile
 // of one problem per workgroup (4 waves of 64 x 64 each), k in steps of 16
@@ -634,9 +669,13 @@ __device__ __forceinline__ void gemm_tile(const GemmProblem<T>& P, int m0, int n
     // q of the thread sits at column 16 VE q + VE (tid % 16), so the 16 lanes
     // of a row write one contiguous 256-byte run per store (every LDS bank
     // once) and read contiguous 256-byte runs from memory.
-    // FP32 loads are unconditional (a row or column outside the problem reads
-    // the problem's first element and is zeroed after the load), so they issue
-    // back to back without branches.
+    // The staging loads are buffer loads: per k step one descriptor for A and
+    // one for B cover the step's rows that lie inside the problem (records =
+    // rows x row bytes), and an element outside the problem's columns gets an
+    // offset past every descriptor.  The hardware returns zero for both, so
+    // no loaded register is touched before the LDS store (B stays in its
+    // storage type until then) and the loads of a step stay in flight behind
+    // the MFMAs of the steps before it.
     constexpr int VE = 16 / sizeof(T);   // elements per 16-byte vector
     const int lr = tid >> 4;             // 0..15
     const int lc = (tid & 15) * VE;      // column of the thread's first element
@@ -644,77 +683,48 @@ __device__ __forceinline__ void gemm_tile(const GemmProblem<T>& P, int m0, int n
     auto ecol = [&](int e) { return lc + (e / VE) * (16 * VE) + (e % VE); };
     // A rows are read as 16-byte vectors when the row stride and base allow it
     const bool avec = (P.lda % VE) == 0 && (reinterpret_cast<uintptr_t>(P.A) % 16) == 0;
-    auto gload = [&](int k0, T (&ra)[8], T (&rb)[8]) {
-        const int k = k0 + lr;
-        const bool krow = k < P.K;
-        if constexpr (sizeof(T) == 4) {
-            // unconditional loads (measured faster for the FP32 tiles)
-            const T* arow = P.A + int64_t(krow ? k : 0) * P.lda;
-            if (avec) {
+    using VT = typename Vec16<T>::type;
+    using PT = typename Vec2<TB>::type;
+    auto gload = [&](int k0, T (&ra)[8], TB (&rb)[8]) {
+        const int rows = min(GBK, P.K - k0);   // k0 < K
+        const __amdgpu_buffer_rsrc_t rA = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<T*>(P.A + int64_t(k0) * P.lda), 0, int(rows * P.lda * int64_t(sizeof(T))), kBufferWord3);
+        const __amdgpu_buffer_rsrc_t rB = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<TB*>(B + int64_t(k0) * P.ldb), 0, int(rows * P.ldb * int64_t(sizeof(TB))), kBufferWord3);
+        const int arow = lr * int(P.lda), brow = lr * int(P.ldb);
+        if (avec) {
 #pragma unroll
-                for (int e = 0; e < 8; e += VE) {
-                    const int mm = m0 + ecol(e);
-                    const bool ok = krow && mm < P.lda;
-                    V16<T> v = *reinterpret_cast<const V16<T>*>(ok ? arow + mm : P.A);
+            for (int e = 0; e < 8; e += VE) {
+                const int mm = m0 + ecol(e);
+                const int off = mm < P.lda ? (arow + mm) * int(sizeof(T)) : kBufferOOB;
+                const VT v = buffer_load<VT>(rA, off);
 #pragma unroll
-                    for (int q = 0; q < VE; ++q) ra[e + q] = ok ? v.v[q] : T(0);
-                }
-            } else {
-#pragma unroll
-                for (int e = 0; e < 8; ++e) {
-                    const int mm = m0 + ecol(e);
-                    const bool ok = krow && mm < P.M;
-                    const T v = *(ok ? arow + mm : P.A);
-                    ra[e] = ok ? v : T(0);
-                }
-            }
-            const TB* brow = B + int64_t(krow ? k : 0) * P.ldb;
-#pragma unroll
-            for (int e = 0; e < 8; e += 2) {
-                const int nn = n0 + ecol(e);
-                const bool ok = krow && nn < P.N;
-                const V2<TB> v = *reinterpret_cast<const V2<TB>*>(ok ? brow + int64_t(nn >> 1) * P.bps : B);
-                rb[e] = ok ? T(v.v[0]) : T(0);
-                rb[e + 1] = ok ? T(v.v[1]) : T(0);
+                for (int q = 0; q < VE; ++q) ra[e + q] = v[q];
             }
         } else {
-            // loads only where the tile overlaps the problem
-            const T* arow = P.A + int64_t(k) * P.lda;
-            if (avec) {
 #pragma unroll
-                for (int e = 0; e < 8; e += VE) {
-                    const int mm = m0 + ecol(e);
-                    V16<T> v{};
-                    if (krow && mm < P.lda) v = *reinterpret_cast<const V16<T>*>(arow + mm);
-#pragma unroll
-                    for (int q = 0; q < VE; ++q) ra[e + q] = v.v[q];
-                }
-            } else {
-#pragma unroll
-                for (int e = 0; e < 8; ++e) {
-                    const int mm = m0 + ecol(e);
-                    ra[e] = (krow && mm < P.M) ? arow[mm] : T(0);
-                }
-            }
-            const TB* brow = B + int64_t(k) * P.ldb;
-#pragma unroll
-            for (int e = 0; e < 8; e += 2) {
-                const int nn = n0 + ecol(e);
-                V2<TB> v{};
-                if (krow && nn < P.N) v = *reinterpret_cast<const V2<TB>*>(brow + int64_t(nn >> 1) * P.bps);
-                rb[e] = T(v.v[0]);
-                rb[e + 1] = T(v.v[1]);
+            for (int e = 0; e < 8; ++e) {
+                const int mm = m0 + ecol(e);
+                ra[e] = buffer_load<T>(rA, mm < P.M ? (arow + mm) * int(sizeof(T)) : kBufferOOB);
             }
         }
+#pragma unroll
+        for (int e = 0; e < 8; e += 2) {
+            const int nn = n0 + ecol(e);
+            const int off = nn < P.N ? (brow + (nn >> 1) * int(P.bps)) * int(sizeof(TB)) : kBufferOOB;
+            const PT v = buffer_load<PT>(rB, off);
+            rb[e] = v[0];
+            rb[e + 1] = v[1];
+        }
     };
-    auto lstore = [&](int buf, const T (&ra)[8], const T (&rb)[8]) {
+    auto lstore = [&](int buf, const T (&ra)[8], const TB (&rb)[8]) {
 #pragma unroll
         for (int e = 0; e < 8; e += VE) {
             V16<T> va, vb;
 #pragma unroll
             for (int q = 0; q < VE; ++q) {
                 va.v[q] = ra[e + q];
-                vb.v[q] = rb[e + q];
+                vb.v[q] = T(rb[e + q]);
             }
             *reinterpret_cast<V16<T>*>(&As[buf][lr][ecol(e)]) = va;
             *reinterpret_cast<V16<T>*>(&Bs[buf][lr][ecol(e)]) = vb;
@@ -740,7 +750,8 @@ __device__ __forceinline__ void gemm_tile(const GemmProblem<T>& P, int m0, int n
     // Step s of 16 k rows lives in LDS buffer s & 1 and is staged through
     // register set s & 1, its global loads issued two steps ahead.
     const int nk = (P.K + GBK - 1) / GBK;
-    T ra0[8], rb0[8], ra1[8], rb1[8];
+    T ra0[8], ra1[8];
+    TB rb0[8], rb1[8];
     gload(0, ra0, rb0);
     lstore(0, ra0, rb0);
     if (nk > 1) gload(GBK, ra1, rb1);
@@ -775,7 +786,7 @@ __device__ __forceinline__ void gemm_tile(const GemmProblem<T>& P, int m0, int n
 
 // TB: storage type of B (FP64 B is rounded to T as it is staged).
 template <class T, class TB>
-__global__ __launch_bounds__(256, sizeof(T) == 8 ? 2 : 3) void k_gemm(const GemmProblem<T>* __restrict__ probs,
+__global__ __launch_bounds__(256, sizeof(T) == 8 || sizeof(TB) == 8 ? 2 : 3) void k_gemm(const GemmProblem<T>* __restrict__ probs,
                                               const int32_t* __restrict__ tmap, const TB* __restrict__ Bbase,
                                               T* __restrict__ Cbase) {
     __shared__ T As[2][GBK][GBM + GPAD];
