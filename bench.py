@@ -368,7 +368,7 @@ def main():
     ap.add_argument("--niter", type=int, default=3, help="Jacobi iterations of the equal_weight workload")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path (maps of a batch "
+        print("bench.py measures one GPU only: the library has no multi-GPU path (maps of a batch "
               "are independent and would be sharded across GPUs with no communication).", file=sys.stderr)
         sys.exit(2)
     if args.workload == "uneven":
