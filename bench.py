@@ -102,12 +102,14 @@ def stage_work(stage, nside, nmaps, tsize, strategy="staged", mode="f64"):
     alm_bytes = n_alm * 16
     if stage == "pack":
         # the refinement packs a0 + correction (two U reads); so does every
-        # Jacobi update of the equal-weight analysis but the first pack
-        n_in = 2 if mode in ("f32_refine", "equal_weight") else 1
+        # Jacobi update of the staged equal-weight analysis but the first pack
+        n_in = 2 if mode == "f32_refine" or (mode == "equal_weight" and strategy != "tables") else 1
         return "byte", n_in * n_alm * 2 * tsize + alm_bytes
     if stage == "unpack":
         if mode == "f32_refine":   # FP32 a0 widened to FP64 (the whole U rectangle is written)
             return "byte", n_alm * 2 * 4 + u_vals * 8
+        if mode == "equal_weight" and strategy == "tables":   # a += A r in the U layout
+            return "byte", 3 * n_alm * 16
         return "byte", alm_bytes + u_vals * 8
     if stage == "cl":
         return "byte", (p + 1) * (p + 2) // 2 * 16 * nmaps

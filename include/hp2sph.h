@@ -210,7 +210,8 @@ const char* hp2sph_last_error(void);
  * number of launches (arrays of length nstages, at most HP2SPH_NSTAGES).
  * Stages: 0 ring transform (S1), 1 pole values (S2), 2 analysis GEMM (S3),
  * 3 analysis Givens sweeps (S4), 4 pack a_lm, 5 unpack a_lm (in the
- * refinement: FP32 a0 widened to FP64 in place of an unpack), 6 synthesis
+ * refinement: FP32 a0 widened to FP64 in place of an unpack; in the Jacobi
+ * iteration on per-order tables: the update a + A r in that layout), 6 synthesis
  * sweeps, 7 synthesis GEMM, 8 inverse ring transform, 9 C_l (S5),
  * 10 residual in ring-Fourier space (the refinement's, and the Jacobi
  * iteration's longitude sums of f - S a), 11 longitude sums of the

@@ -831,6 +831,23 @@ int jacobi_pass(hp2sph_plan_t plan, Group& G, const double* maps, double* alm, i
     Blocks4<double> Gs = blocks_at<double>(ws, G.off_D, G, G.rows_D);
     const double scale = 4.0 * 3.14159265358979323846 / (12.0 * double(G.nside) * double(G.nside));
     STAGE(11, launch_ring_adjoint(maps, G.d_map_off, G.rings, G.t64.fft, Wf, G.dims, scale, s));
+    if (G.tables) {
+        // per-order tables: a stays in the U layout both GEMMs use (truncated
+        // at each map's lmax) and is packed once at the end
+        Blocks4<double> U = blocks_at<double>(ws, G.off_U, G, G.rows_U);
+        Blocks4<double> Ua = blocks_at<double>(ws, plan->off_Ua, G, G.rows_U);
+        STAGE(12, launch_gemm<double>(G.adj64.dev, G.adj64.tmap, G.adj64.slots, Wf.p[0], U.p[0], s));
+        STAGE(5, launch_accumulate(cblocks(U), Ua, G.d_lmax, G.dims, true, s));
+        for (int it = 0; it < niter; ++it) {
+            STAGE(7, launch_gemm<double>(G.syn64.dev, G.syn64.tmap, G.syn64.slots, Ua.p[0], Gs.p[0], s));
+            STAGE(10, launch_adjoint_residual(cblocks(Wf), cblocks(Gs), Wr, G.rings, G.dims, scale, s));
+            STAGE(12, launch_gemm<double>(G.adj64.dev, G.adj64.tmap, G.adj64.slots, Wr.p[0], U.p[0], s));
+            STAGE(5, launch_accumulate(cblocks(U), Ua, G.d_lmax, G.dims, false, s));
+        }
+        STAGE(4, launch_pack<double>(cblocks(Ua), Blocks4<const double>{}, alm, G.d_alm_off, G.d_lmax,
+                                     G.d_pack_tiles, G.n_pack_tiles, G.dims, s));
+        return HP2SPH_OK;
+    }
     if (int e = equal_weight_apply(plan, G, Wf, alm, false, ws, s)) return e;
     for (int it = 0; it < niter; ++it) {
         if (int e = synthesis_coefficients(G, alm, ws, s)) return e;

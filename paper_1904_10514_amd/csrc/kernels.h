@@ -166,6 +166,12 @@ std::vector<int32_t> pack_tiles(int p);
 hipError_t launch_widen(Blocks4<const float> Ua, Blocks4<double> U, const int32_t* lmax, const GroupDims& g,
                         bool live_only, hipStream_t s);
 
+// Jacobi update in the U layout of per-order tables (mode-major only):
+// Uacc = (first ? 0 : Uacc) + U for m <= l <= lmax(map), zero above lmax,
+// rows l < m untouched.
+hipError_t launch_accumulate(Blocks4<const double> U, Blocks4<double> Uacc, const int32_t* lmax, const GroupDims& g,
+                             bool first, hipStream_t s);
+
 // packed complex128 alm -> U (zeros outside 0 <= m <= l <= lmax).
 hipError_t launch_unpack(const double* alm, const int64_t* alm_off, const int32_t* lmax, Blocks4<double> U,
                          const GroupDims& g, hipStream_t s);

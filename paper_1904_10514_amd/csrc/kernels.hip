@@ -1374,6 +1374,44 @@ hipError_t launch_widen(Blocks4<const float> Ua, Blocks4<double> U, const int32_
     return hipGetLastError();
 }
 
+// Jacobi update in the U layout (per-order tables, mode-major):
+// Uacc = (first ? 0 : Uacc) + U for the live entries m <= l <= lmax of each
+// column's map, zero for l > lmax (the synthesis reads a truncated at lmax);
+// rows l < m are never read and stay untouched.
+__global__ void k_accumulate(Blocks4<const double> U, Blocks4<double> Uacc, const int32_t* __restrict__ lmaxv,
+                             GroupDims g, int first) {
+    const int blk = blockIdx.y, kpar = blk >> 1;
+    const int64_t pairs = g.N[kpar] >> 1;
+    const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= int64_t(g.nl[blk]) * pairs) return;
+    const int lp = int(e / pairs);
+    const int64_t q = e % pairs;
+    const int kk = int(q / g.nmaps), map = int(q % g.nmaps);
+    const int l = g.lmin[blk] + 2 * lp, m = 2 * kk + kpar;
+    if (kk >= g.nk[blk] || l < m) return;
+    const int64_t o = int64_t(lp) * g.N[kpar] + 2 * q;
+    D2 v = {0.0, 0.0};
+    if (l <= lmaxv[map]) {
+        const D2 u = *reinterpret_cast<const D2*>(U.p[blk] + o);
+        v = u;
+        if (!first) {
+            const D2 w = *reinterpret_cast<const D2*>(Uacc.p[blk] + o);
+            v = {w.x + u.x, w.y + u.y};
+        }
+    }
+    *reinterpret_cast<D2*>(Uacc.p[blk] + o) = v;
+}
+
+hipError_t launch_accumulate(Blocks4<const double> U, Blocks4<double> Uacc, const int32_t* lmax, const GroupDims& g,
+                             bool first, hipStream_t s) {
+    if (!g.modemajor) return hipErrorInvalidValue;
+    int64_t most = 0;
+    for (int b = 0; b < 4; ++b) most = std::max<int64_t>(most, int64_t(g.nl[b]) * (g.N[b >> 1] >> 1));
+    hipLaunchKernelGGL(k_accumulate, dim3(unsigned((most + 255) / 256), 4), dim3(256), 0, s, U, Uacc, lmax, g,
+                       first ? 1 : 0);
+    return hipGetLastError();
+}
+
 static dim3 pack_grid(const GroupDims& g) {
     int64_t most = 0;
     for (int b = 0; b < 4; ++b) most = std::max<int64_t>(most, int64_t(g.nk[b]) * g.nl[b] * g.nmaps);
