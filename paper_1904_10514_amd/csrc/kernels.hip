@@ -1279,6 +1279,7 @@ __device__ __forceinline__ bool pack_index(const GroupDims& g, int blk, int64_t 
 // layout) and every map's 64 a_l^m are written as one contiguous run of
 // alm.  With Ub given, writes Ua + Ub (the refined a_lm), added in FP64.
 constexpr int kPackL = 64, kPackMaps = 32;
+static_assert(kPackL * kPackMaps % 256 == 0, "a pack tile is a whole number of 256-thread sweeps");
 
 template <class T>
 __global__ __launch_bounds__(256) void k_pack(Blocks4<const T> Ua, Blocks4<const T> Ub, double* __restrict__ alm,
@@ -1289,21 +1290,34 @@ __global__ __launch_bounds__(256) void k_pack(Blocks4<const T> Ua, Blocks4<const
     const int v0 = blockIdx.y * kPackMaps;
     const int kpar = m & 1, kk = m >> 1;
     const bool two = Ub.p[0] != nullptr;
-    for (int i = threadIdx.x; i < kPackL * kPackMaps; i += 256) {
+    // Branch-free, fully unrolled loads: an element outside the tile's maps or
+    // degrees reads the tile's first element (map v0, degree l0, both in range)
+    // and is dropped when the tile is filled, so all of a thread's loads are in
+    // flight before the first of them is used.
+    constexpr int kIt = kPackL * kPackMaps / 256;
+    using P2 = typename Vec2<T>::type;   // one (re, im) pair
+    P2 ra[kIt], rb[kIt];
+#pragma unroll
+    for (int it = 0; it < kIt; ++it) {
+        const int i = threadIdx.x + 256 * it;
         const int vi = i % kPackMaps, li = i / kPackMaps;
-        const int v = v0 + vi, l = l0 + li;
+        const bool ok = v0 + vi < g.nmaps && l0 + li <= g.p;
+        const int v = ok ? v0 + vi : v0, l = ok ? l0 + li : l0;
+        // the block of order parity kpar whose l have the parity of l
+        const int blk = 2 * kpar + ((l & 1) == (g.lmin[2 * kpar] & 1) ? 0 : 1);
+        const int lp = (l - g.lmin[blk]) >> 1;
+        const int64_t o = int64_t(lp) * g.N[kpar] + int64_t(v) * g.cm[kpar] + int64_t(kk) * g.ck[kpar];
+        ra[it] = *reinterpret_cast<const P2*>(Ua.p[blk] + o);
+        if (two) rb[it] = *reinterpret_cast<const P2*>(Ub.p[blk] + o);
+    }
+#pragma unroll
+    for (int it = 0; it < kIt; ++it) {
+        const int i = threadIdx.x + 256 * it;
+        const int vi = i % kPackMaps, li = i / kPackMaps;
         C2<double> z = {0.0, 0.0};
-        if (v < g.nmaps && l <= g.p) {
-            // the block of order parity kpar whose l have the parity of l
-            const int blk = 2 * kpar + ((l & 1) == (g.lmin[2 * kpar] & 1) ? 0 : 1);
-            const int lp = (l - g.lmin[blk]) >> 1;
-            const int64_t o = int64_t(lp) * g.N[kpar] + int64_t(v) * g.cm[kpar] + int64_t(kk) * g.ck[kpar];
-            const T* pa = Ua.p[blk] + o;
-            z = {double(pa[0]), double(pa[1])};
-            if (two) {
-                const T* pb = Ub.p[blk] + o;
-                z = {z.x + double(pb[0]), z.y + double(pb[1])};
-            }
+        if (v0 + vi < g.nmaps && l0 + li <= g.p) {
+            z = {double(ra[it][0]), double(ra[it][1])};
+            if (two) z = {z.x + double(rb[it][0]), z.y + double(rb[it][1])};
         }
         tile[li][vi] = z;
     }
