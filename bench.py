@@ -287,9 +287,35 @@ def uneven_main(args):
             plan.power_spectrum(out, out=cl)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
+        # the same step as one graph launch (the analyze and C_l calls only
+        # enqueue kernels, so they capture into a HIP graph)
+        ref = out.clone()
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            plan.analyze(maps, out=out)
+            plan.power_spectrum(out, out=cl)
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            plan.analyze(maps, out=out)
+            plan.power_spectrum(out, out=cl)
+        graph.replay()
+        torch.cuda.synchronize()
+        if not torch.equal(out, ref):
+            raise RuntimeError("graph replay differs from the eager analysis")
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            graph.replay()
+        torch.cuda.synchronize()
+        dtg = time.perf_counter() - t0
+        del graph
         res[mode] = {"maps_per_s": len(nsides) * args.steps / dt, "ms_per_step": 1e3 * dt / args.steps,
+                     "graph_maps_per_s": len(nsides) * args.steps / dtg, "graph_ms_per_step": 1e3 * dtg / args.steps,
                      "setup_s": setup, "strategy": plan.strategy}
-        print(f"[bench] uneven {mode}: {1e3 * dt / args.steps:.2f} ms/step", file=sys.stderr, flush=True)
+        print(f"[bench] uneven {mode}: {1e3 * dt / args.steps:.2f} ms/step, as one graph launch "
+              f"{1e3 * dtg / args.steps:.2f} ms/step", file=sys.stderr, flush=True)
         plan.close()
         del plan
     counts = {int(n): nsides.count(n) for n in sorted(set(nsides))}
