@@ -50,6 +50,26 @@ def test_error_paths_without_gpu():
     assert lib.hp2sph_synthesize(None, None, None, None, None) == -5
     assert lib.hp2sph_power_spectrum(None, None, None, None) == -5
     assert lib.hp2sph_plan_destroy(None) == -5
+    assert lib.hp2sph_analyze_iterative(None, None, None, 3, None, None) == -5
+    st = ctypes.c_int32()
+    assert lib.hp2sph_plan_strategy(None, ctypes.byref(st)) == -5
+    assert lib.hp2sph_profile(None, 1) == -5
+    ms = (ctypes.c_double * P.NSTAGES)()
+    nl = (ctypes.c_int32 * P.NSTAGES)()
+    assert lib.hp2sph_profile_read(None, ms, nl, P.NSTAGES) == -5
+    assert lib.hp2sph_plan_create_ex(two, lm, 1, 0, 9, ctypes.byref(h)) == -1          # bad strategy
+    assert b"strategy" in lib.hp2sph_last_error()
+    for bad_nside in (1, 2 * P.MAX_NSIDE):
+        ns = (ctypes.c_int32 * 1)(bad_nside)
+        assert lib.hp2sph_plan_create(ns, lm, 1, 0, ctypes.byref(h)) == -1
+    neg = (ctypes.c_int32 * 1)(-1)
+    assert lib.hp2sph_plan_create(two, neg, 1, P.HP2SPH_EQUAL_WEIGHT, ctypes.byref(h)) == -1
+    assert b"lmax" in lib.hp2sph_last_error()
+    # a batch is rejected as a whole if any map is invalid
+    mixed_n = (ctypes.c_int32 * 3)(8, 16, 12)
+    mixed_l = (ctypes.c_int32 * 3)(16, 32, 24)
+    assert lib.hp2sph_plan_create(mixed_n, mixed_l, 3, 0, ctypes.byref(h)) == -1
+    assert not h.value
     cnt = ctypes.c_int64()
     assert lib.hp2sph_host_table(12, 0, 0, None, 0, ctypes.byref(cnt)) == -1
     assert lib.hp2sph_host_table(8, 9, 0, None, 0, ctypes.byref(cnt)) == -1
