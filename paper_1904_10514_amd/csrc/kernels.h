@@ -182,7 +182,7 @@ hipError_t launch_ring_inverse(Blocks4<const double> D, RingTab rt, FftTab<doubl
                                const double* minus_from, const int64_t* map_off, const GroupDims& g,
                                hipStream_t s);
 
-// Raise the dynamic-LDS limit of the ring kernels (up to 128 KB at nside 2048).
+// Raise the dynamic-LDS limit of the ring kernels (up to 139 KB at nside 2048).
 hipError_t configure_kernels();
 
 // C_l per map from packed alm.

@@ -32,7 +32,6 @@ template <class T>
 __device__ __forceinline__ C2<T> ldc(const T* p, int64_t i) { return {p[2 * i], p[2 * i + 1]}; }
 
 __device__ __forceinline__ int ilog2(int v) { return 31 - __clz(v); }
-__device__ __forceinline__ int bitrev(int v, int lg) { return lg == 0 ? 0 : int(__brev(unsigned(v)) >> (32 - lg)); }
 
 struct alignas(16) D2 {
     double x, y;
@@ -1460,14 +1459,6 @@ hipError_t launch_unpack(const double* alm, const int64_t* alm_off, const int32_
 // ---------------------------------------------------------------------------
 // Synthesis: inverse ring transform (+ residual)
 // ---------------------------------------------------------------------------
-
-// e^{+i pi k / n} for any k >= 0 from the table e^{-i pi k'/n}, k' = 0..n
-__device__ __forceinline__ C2<double> eplus(const double* roots, int64_t k, int n) {
-    const int64_t kk = k % (2 * int64_t(n));
-    if (kk <= n) return cconj(ldc(roots, kk));
-    const C2<double> r = ldc(roots, kk - n);
-    return {-r.x, r.y};   // -conj(r)
-}
 
 // Mode sums of one ring from Dsym row h: with D_k = D+_k + sgn D-_k and
 // G_k = D_k e^{i k phi0} (k = 0..p), leaves in buf[lpad(t)], t = 0..n/2,
