@@ -50,6 +50,22 @@ def test_equal_weight_jacobi_vs_oracle(strategy, nside):
 
 
 @pytest.mark.parametrize("strategy", ["staged", "tables"])
+def test_equal_weight_jacobi_vs_oracle_several_tiles(strategy):
+    """nside 128: the tables have 256 ring rows (two 128-row GEMM tiles) and
+    the per-order problems end in ragged k steps; 3 maps (ragged columns)."""
+    nside, batch = 128, 3
+    maps = [white_map(nside, 600 + v) for v in range(batch)]
+    plan = P.Plan(nside, batch=batch, mode="equal_weight", strategy=strategy)
+    a = plan.analyze_iterative(_dev(np.concatenate(maps)), 2)
+    torch.cuda.synchronize()
+    ref = _oracle_batch(maps, [nside] * batch, [2 * nside] * batch, 2)
+    err = rel_err(a.cpu().numpy(), ref)
+    print(f"{strategy} nside 128 niter 2: {err:.3e}")
+    assert err < TOL
+    plan.close()
+
+
+@pytest.mark.parametrize("strategy", ["staged", "tables"])
 def test_equal_weight_truncated_lmax(strategy):
     nside, lmax = 16, 25
     maps = [cmb_map(0, v, nside, lmax)[0] for v in range(2)]

@@ -243,3 +243,24 @@ def test_f32_refine_uneven_batch_vs_refined_oracle():
         print(f"uneven f32+refine nside {n} lmax {L}: vs O_ref {e:.3e}")
         assert e < TOL_REFINE
         off += sz
+
+
+@pytest.mark.parametrize("strategy", ["staged", "tables"])
+@pytest.mark.parametrize("mode", ["f64", "f32_refine"])
+def test_several_tiles_nside128(mode, strategy):
+    """nside 128, 3 maps: the per-order analysis tables have up to 129 rows
+    (a second 128-row tile holding one row), 257 - ceil(m/2) ring rows (ragged
+    k steps) and 6 columns per order; the synthesis tables of the refinement
+    span two full tiles."""
+    nside, batch = 128, 3
+    maps = [white_map(nside, 1300 + v) for v in range(batch)]
+    plan = P.Plan(nside, batch=batch, mode=mode, strategy=strategy)
+    a = plan.analyze(_dev(np.concatenate(maps)))
+    torch.cuda.synchronize()
+    a = a.cpu().numpy()
+    plan.close()
+    route = O.analyze if mode == "f64" else O.analyze_refined
+    ref = np.concatenate([route(f, nside) for f in maps])
+    err = rel_err(a, ref)
+    print(f"{mode} {strategy} nside 128 x 3: {err:.3e}")
+    assert err < (TOL64 if mode == "f64" else TOL_REFINE)
