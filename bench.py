@@ -197,12 +197,23 @@ def make_inputs(torch, P, W, nside, nmaps):
     return maps
 
 
-def time_mode(torch, P, maps, nside, nmaps, mode, steps, warmup, strategy):
+def autotune(plan, maps, out, enabled):
+    """Set-up step outside the timed region: the plan's autotuner picks the
+    GEMM workgroup schedules on these maps."""
+    if not enabled:
+        return {"enabled": False, "schedules": plan.schedules}
+    t0 = time.perf_counter()
+    ms, _ = plan.autotune(maps, reps=3, out=out)
+    return {"enabled": True, "schedules": plan.schedules, "best_ms": ms, "seconds": time.perf_counter() - t0}
+
+
+def time_mode(torch, P, maps, nside, nmaps, mode, steps, warmup, strategy, tune=True):
     t0 = time.perf_counter()
     plan = P.Plan(nside, 2 * nside, batch=nmaps, mode=mode, strategy=strategy)
     setup_s = time.perf_counter() - t0
     alm = torch.empty(plan.alm_total, dtype=torch.complex128, device="cuda")
     cl = torch.empty(plan.cl_total, dtype=torch.float64, device="cuda")
+    tuned = autotune(plan, maps, alm, tune)
     for _ in range(warmup):
         plan.analyze(maps, out=alm)
         plan.power_spectrum(alm, out=cl)
@@ -217,7 +228,7 @@ def time_mode(torch, P, maps, nside, nmaps, mode, steps, warmup, strategy):
     dt = time.perf_counter() - t0
     plan.profile(False)
     prof = plan.profile_read()
-    return plan, alm, cl, dt, setup_s, prof
+    return plan, alm, cl, dt, setup_s, prof, tuned
 
 
 def cpu_baseline(f_host, nside, nsample=48):
@@ -277,6 +288,7 @@ def uneven_main(args):
         setup = time.perf_counter() - t0
         out = torch.empty(plan.alm_total, dtype=torch.complex128, device="cuda")
         cl = torch.empty(plan.cl_total, dtype=torch.float64, device="cuda")
+        tuned = autotune(plan, maps, out, not args.no_autotune)
         for _ in range(args.warmup):
             plan.analyze(maps, out=out)
             plan.power_spectrum(out, out=cl)
@@ -313,7 +325,7 @@ def uneven_main(args):
         del graph
         res[mode] = {"maps_per_s": len(nsides) * args.steps / dt, "ms_per_step": 1e3 * dt / args.steps,
                      "graph_maps_per_s": len(nsides) * args.steps / dtg, "graph_ms_per_step": 1e3 * dtg / args.steps,
-                     "setup_s": setup, "strategy": plan.strategy}
+                     "setup_s": setup, "strategy": plan.strategy, "autotune": tuned}
         print(f"[bench] uneven {mode}: {1e3 * dt / args.steps:.2f} ms/step, as one graph launch "
               f"{1e3 * dtg / args.steps:.2f} ms/step", file=sys.stderr, flush=True)
         plan.close()
@@ -345,6 +357,8 @@ def equal_weight_main(args):
     plan = P.Plan(nside, lmax, batch=nmaps, mode="equal_weight", strategy=args.strategy)
     setup_s = time.perf_counter() - t0
     alm = torch.empty(plan.alm_total, dtype=torch.complex128, device="cuda")
+    # the autotuner times hp2sph_analyze, i.e. 3 Jacobi iterations
+    tuned = autotune(plan, maps, alm, not args.no_autotune and niter == 3)
     for _ in range(args.warmup):
         plan.analyze_iterative(maps, niter, out=alm)
     torch.cuda.synchronize()
@@ -375,7 +389,7 @@ def equal_weight_main(args):
                       "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
                       "config": {"workload": f"equal_weight_nside{nside}_L{lmax}_b{nmaps}", "nside": nside,
                                  "lmax": lmax, "batch": nmaps, "niter": niter, "strategy": plan.strategy},
-                      "setup_s": setup_s, "roofline": rl, "stages": stages}), flush=True)
+                      "setup_s": setup_s, "autotune": tuned, "roofline": rl, "stages": stages}), flush=True)
     plan.close()
 
 
@@ -394,6 +408,8 @@ def main():
                     help="headline: 64 maps of nside 1024; uneven: 256 maps of nside 64..512; equal_weight: "
                          "the equal-weight analysis with Jacobi iterations on the headline inputs (secondary)")
     ap.add_argument("--niter", type=int, default=3, help="Jacobi iterations of the equal_weight workload")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default GEMM schedules instead of running the plan's autotuner at set-up")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path (maps of a batch "
@@ -423,12 +439,12 @@ def main():
     results = {}
     for mode in modes:
         print(f"[bench] timing {mode}", file=sys.stderr, flush=True)
-        plan, alm, cl, dt, setup_s, prof = time_mode(torch, P, maps, nside, nmaps, mode, args.steps, args.warmup,
-                                                     args.strategy)
+        plan, alm, cl, dt, setup_s, prof, tuned = time_mode(torch, P, maps, nside, nmaps, mode, args.steps,
+                                                            args.warmup, args.strategy, not args.no_autotune)
         results[mode] = {"plan": plan, "alm": alm, "cl": cl, "dt": dt, "setup_s": setup_s, "prof": prof,
-                         "strategy": plan.strategy}
-        print(f"[bench] {mode}: {1e3 * dt / args.steps:.2f} ms/step, set-up {setup_s:.1f} s", file=sys.stderr,
-              flush=True)
+                         "strategy": plan.strategy, "autotune": tuned}
+        print(f"[bench] {mode}: {1e3 * dt / args.steps:.2f} ms/step, set-up {setup_s:.1f} s, "
+              f"schedules {tuned['schedules']}", file=sys.stderr, flush=True)
 
     head = results.get("f32_refine") or results[modes[0]]
     head_mode = "f32_refine" if "f32_refine" in results else modes[0]
@@ -487,6 +503,7 @@ def main():
         "f64_ms_per_step": 1e3 * f64["dt"] / args.steps if f64 else None,
         "setup_s": {m: results[m]["setup_s"] for m in results},
         "strategy": {m: results[m]["strategy"] for m in results},
+        "autotune": {m: results[m]["autotune"] for m in results},
         "roofline": roof,
         "stages": stages,
         "f32refine_vs_gpu_f64": {"max_abs_da_over_max_a": rel_a, "max_rel_dcl_l_ge_2": rel_cl},

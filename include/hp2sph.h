@@ -223,6 +223,58 @@ int hp2sph_profile(hp2sph_plan_t plan, int32_t enable);
 int hp2sph_profile_read(hp2sph_plan_t plan, double* ms, int32_t* launches, int32_t nstages);
 
 /*
+ * Workgroup schedules of the grouped GEMMs (the analysis GEMM of S3/S4 with
+ * per-order tables or staged blocks, the synthesis GEMM of the refinement and
+ * of the Jacobi iteration, the transposed-evaluation GEMM of the equal-weight
+ * analysis).  A schedule only decides which workgroup runs which 128 x 128
+ * output tile; every tile sums its k steps in the same order whatever runs
+ * it, so results are bitwise the same under every schedule.  Not part of the
+ * paper's method: a placement choice for MI355X, whose 8 XCDs (each with its
+ * own L2) receive workgroups in turn by workgroup id.
+ *   HP2SPH_SCHED_XCD_ROUND_ROBIN  problems (orders / parity blocks, longest
+ *       first) dealt to the XCDs in turn, all tiles of a problem on one XCD
+ *       (the default of a new plan);
+ *   HP2SPH_SCHED_XCD_BALANCED     each problem, longest first, to the XCD with
+ *       the least work so far (tiles times k extent), tiles kept together;
+ *   HP2SPH_SCHED_LINEAR           workgroup w runs tile w of the problem list
+ *       (no XCD placement).
+ */
+enum {
+    HP2SPH_SCHED_XCD_ROUND_ROBIN = 0,
+    HP2SPH_SCHED_XCD_BALANCED = 1,
+    HP2SPH_SCHED_LINEAR = 2,
+    HP2SPH_NSCHED = 3
+};
+
+/* Use schedule `sched` for every GEMM of the plan (host state only: takes
+ * effect for launches enqueued afterwards; a graph captured before keeps the
+ * schedule it was captured with).  Errors: ESTATE, EINVAL (unknown sched). */
+int hp2sph_set_schedule(hp2sph_plan_t plan, int32_t sched);
+
+/*
+ * Autotuner: for each GEMM that hp2sph_analyze launches (nside groups in plan
+ * order, GEMMs in launch order), times hp2sph_analyze of the caller's maps
+ * under each candidate schedule of that GEMM, the others held at their current
+ * choice, and keeps the fastest; a candidate replaces the current choice only
+ * when it is more than 0.5 % faster (the run-to-run spread of a timed
+ * analysis).  Each timing is the fastest of `reps` analyses (HIP events on
+ * `stream`, after one untimed analysis).  Synchronous: returns after the last
+ * timed run, with alm holding hp2sph_analyze(maps) and *best_ms (if not null)
+ * the time of one analysis under the chosen schedules.  Stage profiling
+ * (hp2sph_profile) is paused meanwhile.  maps, alm, workspace, stream as for
+ * hp2sph_analyze; 1 <= reps <= HP2SPH_MAX_TUNE_REPS.
+ * Errors: as hp2sph_analyze, EINVAL for reps out of range, EDEVICE.
+ */
+#define HP2SPH_MAX_TUNE_REPS 100
+int hp2sph_autotune(hp2sph_plan_t plan, const double* maps, double* alm, void* workspace,
+                    void* stream, int32_t reps, double* best_ms);
+
+/* Schedules in use by the GEMMs hp2sph_analyze launches, in the order the
+ * autotuner visits them: writes min(cap, count) ids to out (may be null when
+ * cap is 0) and the count to *count.  Errors: ESTATE, EINVAL. */
+int hp2sph_schedules(hp2sph_plan_t plan, int32_t* out, int32_t cap, int32_t* count);
+
+/*
  * Host-only inspection of the set-up tables (no GPU needed; used by tests).
  * Writes up to `capacity` doubles of table `table` for `nside` into `out`
  * and the full element count into *count (out may be NULL to query the

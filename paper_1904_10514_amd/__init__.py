@@ -43,9 +43,11 @@ EXPORTED = [
     "hp2sph_plan_create", "hp2sph_workspace_size", "hp2sph_analyze", "hp2sph_synthesize",
     "hp2sph_power_spectrum", "hp2sph_plan_destroy", "hp2sph_last_error", "hp2sph_host_table",
     "hp2sph_profile", "hp2sph_profile_read", "hp2sph_plan_create_ex", "hp2sph_plan_strategy",
-    "hp2sph_analyze_iterative",
+    "hp2sph_analyze_iterative", "hp2sph_set_schedule", "hp2sph_autotune", "hp2sph_schedules",
 ]
 STRATEGIES = {"auto": 0, "staged": 1, "tables": 2}
+SCHEDULES = ["xcd_round_robin", "xcd_balanced", "linear"]
+MAX_TUNE_REPS = 100
 NSTAGES = 13
 STAGES = ["ring_forward", "pole", "gemm_analysis", "sweep_analysis", "pack", "unpack",
           "sweep_synthesis", "gemm_synthesis", "ring_inverse", "cl", "residual_fold",
@@ -66,6 +68,9 @@ _lib.hp2sph_plan_create_ex.argtypes = [ctypes.POINTER(_i32), ctypes.POINTER(_i32
 _lib.hp2sph_plan_strategy.argtypes = [_vp, ctypes.POINTER(_i32)]
 _lib.hp2sph_profile.argtypes = [_vp, _i32]
 _lib.hp2sph_profile_read.argtypes = [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i32), _i32]
+_lib.hp2sph_set_schedule.argtypes = [_vp, _i32]
+_lib.hp2sph_autotune.argtypes = [_vp, _vp, _vp, _vp, _vp, _i32, ctypes.POINTER(ctypes.c_double)]
+_lib.hp2sph_schedules.argtypes = [_vp, ctypes.POINTER(_i32), _i32, ctypes.POINTER(_i32)]
 _lib.hp2sph_host_table.argtypes = [_i32, _i32, _i32, _vp, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
 for _f in EXPORTED:
     if _f not in ("hp2sph_last_error",):
@@ -206,6 +211,36 @@ class Plan:
         _check(_lib.hp2sph_power_spectrum(self._h, alm.data_ptr(), out.data_ptr(), self._stream()),
                "power_spectrum")
         return out
+
+    def set_schedule(self, name):
+        """Workgroup schedule (one of SCHEDULES) for every GEMM of the plan."""
+        if name not in SCHEDULES:
+            raise ValueError(f"schedule must be one of {SCHEDULES}")
+        _check(_lib.hp2sph_set_schedule(self._h, SCHEDULES.index(name)), "set_schedule")
+
+    def autotune(self, maps, reps=3, out=None):
+        """Time the analysis of `maps` under each candidate GEMM schedule and
+        keep the fastest (synchronous).  Returns (ms per analysis, alm)."""
+        torch = _torch()
+        if maps.dtype != torch.float64 or not maps.is_cuda or not maps.is_contiguous():
+            raise ValueError("maps must be a contiguous float64 CUDA tensor")
+        if maps.numel() != self.npix_total:
+            raise ValueError(f"maps has {maps.numel()} values, plan expects {self.npix_total}")
+        if out is None:
+            out = torch.empty(self.alm_total, dtype=torch.complex128, device=maps.device)
+        ms = ctypes.c_double(0.0)
+        _check(_lib.hp2sph_autotune(self._h, maps.data_ptr(), out.data_ptr(), self._ws_ptr, self._stream(),
+                                    int(reps), ctypes.byref(ms)), "autotune")
+        return ms.value, out
+
+    @property
+    def schedules(self):
+        """Schedule names of the GEMMs analyze launches, in launch order."""
+        n = _i32(0)
+        _check(_lib.hp2sph_schedules(self._h, None, 0, ctypes.byref(n)), "schedules")
+        buf = (_i32 * max(n.value, 1))()
+        _check(_lib.hp2sph_schedules(self._h, buf, n.value, ctypes.byref(n)), "schedules")
+        return [SCHEDULES[buf[i]] for i in range(n.value)]
 
     def profile(self, enable):
         """Start (True, clears the accumulators) or stop per-stage event timing."""

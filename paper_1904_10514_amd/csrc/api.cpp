@@ -66,11 +66,25 @@ I* upload_int(std::vector<std::unique_ptr<DevBuf>>& owned, const std::vector<I>&
     return out;
 }
 
+// Workgroup -> (problem, tile) maps of one grouped GEMM, one per candidate
+// schedule (HP2SPH_SCHED_*), and the one the launches use.
+struct GemmSched {
+    int32_t* tmap = nullptr;      // active map
+    int slots = 0;                // its length (workgroups per launch)
+    int sched = HP2SPH_SCHED_XCD_ROUND_ROBIN;
+    int32_t* maps[HP2SPH_NSCHED] = {};
+    int nslots[HP2SPH_NSCHED] = {};
+    void use(int c) {
+        sched = c;
+        tmap = maps[c];
+        slots = nslots[c];
+    }
+};
+
 template <class T>
-struct GemmList {
+struct GemmList : GemmSched {
     GemmProblem<T>* dev = nullptr;
-    int32_t* tmap = nullptr;      // workgroup -> (problem, tile), XCD-aware
-    int n = 0, tiles = 0, slots = 0;
+    int n = 0, tiles = 0;
 };
 
 struct Group {
@@ -352,6 +366,48 @@ Blocks4<const T> cblocks(Blocks4<T> b) {
 // pole row carries m = 0 only).
 int first_row(int m) { return m == 0 ? 0 : (m + 1) / 2; }
 
+// The alternatives to xcd_tile_map (HP2SPH_SCHED_XCD_ROUND_ROBIN) for a
+// finalized problem list in launch order (longest first):
+//   XCD_BALANCED: each problem to the XCD with the least work so far (tiles
+//     times K, longest-processing-time-first), its tiles kept together;
+//     workgroup w runs on XCD w mod 8 (the hardware deals workgroups to the 8
+//     XCDs in turn), entries of -1 pad the XCDs to equal length;
+//   LINEAR: workgroup w runs tile w of the list (no XCD placement).
+template <class T>
+std::vector<int32_t> schedule_map(const std::vector<GemmProblem<T>>& v, int total_tiles, int sched) {
+    constexpr int kXcd = 8;
+    const int n = int(v.size());
+    auto tiles_of = [&](int i) { return (i + 1 < n ? v[i + 1].tile_begin : total_tiles) - v[i].tile_begin; };
+    std::vector<int32_t> out;
+    if (sched == HP2SPH_SCHED_LINEAR) {
+        for (int i = 0; i < n; ++i)
+            for (int t = 0; t < tiles_of(i); ++t) {
+                out.push_back(i);
+                out.push_back(t);
+            }
+        return out;
+    }
+    std::vector<std::vector<int32_t>> per(kXcd);
+    std::vector<int64_t> load(kXcd, 0);
+    for (int i = 0; i < n; ++i) {
+        const int x = int(std::min_element(load.begin(), load.end()) - load.begin());
+        load[x] += int64_t(tiles_of(i)) * v[i].K;
+        for (int t = 0; t < tiles_of(i); ++t) {
+            per[x].push_back(i);
+            per[x].push_back(t);
+        }
+    }
+    size_t len = 0;
+    for (auto& p : per) len = std::max(len, p.size() / 2);
+    out.assign(2 * len * kXcd, -1);
+    for (int x = 0; x < kXcd; ++x)
+        for (size_t j = 0; j < per[x].size() / 2; ++j) {
+            out[2 * (j * kXcd + x)] = per[x][2 * j];
+            out[2 * (j * kXcd + x) + 1] = per[x][2 * j + 1];
+        }
+    return out;
+}
+
 template <class T>
 void upload_list(Group& G, std::vector<GemmProblem<T>>& v, GemmList<T>& out) {
     // the GEMM kernel reads B as aligned (re, im) pairs
@@ -369,9 +425,13 @@ void upload_list(Group& G, std::vector<GemmProblem<T>>& v, GemmList<T>& out) {
     out.tiles = finalize_gemm_problems<T>(v.data(), int(v.size()));
     out.n = int(v.size());
     out.dev = upload_int(G.owned, v);
-    std::vector<int32_t> tm = xcd_tile_map<T>(v.data(), int(v.size()));
-    out.slots = int(tm.size() / 2);
-    out.tmap = upload_int(G.owned, tm);
+    for (int c = 0; c < HP2SPH_NSCHED; ++c) {
+        std::vector<int32_t> tm = c == HP2SPH_SCHED_XCD_ROUND_ROBIN ? xcd_tile_map<T>(v.data(), int(v.size()))
+                                                                   : schedule_map(v, out.tiles, c);
+        out.nslots[c] = int(tm.size() / 2);
+        out.maps[c] = upload_int(G.owned, tm);
+    }
+    out.use(HP2SPH_SCHED_XCD_ROUND_ROBIN);
 }
 
 // TB: storage type of the Dsym rows the GEMM reads (B offsets in TB elements)
@@ -864,6 +924,35 @@ int check_plan(hp2sph_plan_t plan) {
     return HP2SPH_OK;
 }
 
+// The grouped GEMMs hp2sph_analyze launches for one group, in launch order.
+void analysis_lists(const hp2sph_plan_s* plan, Group& G, std::vector<GemmSched*>& out) {
+    auto add = [&](GemmSched& L, int n) {
+        if (n > 0) out.push_back(&L);
+    };
+    GemmList<double>& syn = G.tables ? G.syn64 : G.syn64_staged;
+    switch (plan->mode) {
+        case HP2SPH_F64: add(G.ana64, G.ana64.n); break;
+        case HP2SPH_F32: add(G.ana32, G.ana32.n); break;
+        case HP2SPH_F32_REFINE:
+            add(G.ana32_b64, G.ana32_b64.n);
+            add(syn, syn.n);
+            add(G.ana32, G.ana32.n);
+            break;
+        default:   // equal weight: transposed evaluation, then the synthesis of each iteration
+            add(G.adj64, G.adj64.n);
+            add(syn, syn.n);
+            break;
+    }
+}
+
+// Every GEMM list the plan built (the analyses, synthesis and adjoint).
+void built_lists(Group& G, std::vector<GemmSched*>& out) {
+    for (GemmSched* L : {static_cast<GemmSched*>(&G.ana64), static_cast<GemmSched*>(&G.syn64),
+                         static_cast<GemmSched*>(&G.syn64_staged), static_cast<GemmSched*>(&G.adj64),
+                         static_cast<GemmSched*>(&G.ana32), static_cast<GemmSched*>(&G.ana32_b64)})
+        if (L->maps[0]) out.push_back(L);
+}
+
 }  // namespace
 
 extern "C" {
@@ -1081,6 +1170,90 @@ int hp2sph_profile_read(hp2sph_plan_t plan, double* ms, int32_t* launches, int32
         ms[i] = plan->prof.ms[i];
         launches[i] = plan->prof.launches[i];
     }
+    return HP2SPH_OK;
+}
+
+int hp2sph_set_schedule(hp2sph_plan_t plan, int32_t sched) {
+    if (int e = check_plan(plan)) return e;
+    if (sched < 0 || sched >= HP2SPH_NSCHED) return fail(HP2SPH_EINVAL, "unknown schedule");
+    std::vector<GemmSched*> lists;
+    for (auto& g : plan->groups) built_lists(*g, lists);
+    for (GemmSched* L : lists) L->use(sched);
+    return HP2SPH_OK;
+}
+
+int hp2sph_schedules(hp2sph_plan_t plan, int32_t* out, int32_t cap, int32_t* count) {
+    if (int e = check_plan(plan)) return e;
+    if (!count || cap < 0 || (cap > 0 && !out)) return fail(HP2SPH_EINVAL, "bad arguments");
+    std::vector<GemmSched*> lists;
+    for (auto& g : plan->groups) analysis_lists(plan, *g, lists);
+    for (int i = 0; i < int(lists.size()) && i < cap; ++i) out[i] = lists[i]->sched;
+    *count = int(lists.size());
+    return HP2SPH_OK;
+}
+
+int hp2sph_autotune(hp2sph_plan_t plan, const double* maps, double* alm, void* workspace, void* stream,
+                    int32_t reps, double* best_ms) {
+    if (int e = check_plan(plan)) return e;
+    if (reps < 1 || reps > HP2SPH_MAX_TUNE_REPS) return fail(HP2SPH_EINVAL, "reps out of range");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    const bool prof_on = plan->prof.on;
+    // restores the profiler and frees the events on every exit
+    struct Cleanup {
+        hp2sph_plan_t plan;
+        bool prof_on;
+        hipEvent_t* ev;
+        ~Cleanup() {
+            plan->prof.on = prof_on;
+            for (int i = 0; i < 2; ++i)
+                if (ev[i]) (void)hipEventDestroy(ev[i]);
+        }
+    } cleanup{plan, prof_on, ev};
+    if (int e = hp2sph_profile(plan, 0)) return e;
+    for (int i = 0; i < 2; ++i)
+        if (hipEventCreate(&ev[i]) != hipSuccess) return fail(HP2SPH_EDEVICE, "hipEventCreate failed");
+    // fastest of reps analyses, after an untimed one
+    auto timed = [&](double& ms) -> int {
+        if (int e = hp2sph_analyze(plan, maps, alm, workspace, stream)) return e;
+        ms = 1e300;
+        for (int r = 0; r < reps; ++r) {
+            if (hipEventRecord(ev[0], s) != hipSuccess) return fail(HP2SPH_EDEVICE, "hipEventRecord failed");
+            if (int e = hp2sph_analyze(plan, maps, alm, workspace, stream)) return e;
+            float f = 0.f;
+            if (hipEventRecord(ev[1], s) != hipSuccess || hipEventSynchronize(ev[1]) != hipSuccess ||
+                hipEventElapsedTime(&f, ev[0], ev[1]) != hipSuccess)
+                return fail(HP2SPH_EDEVICE, "timing events failed");
+            ms = std::min(ms, double(f));
+        }
+        return HP2SPH_OK;
+    };
+    std::vector<GemmSched*> lists;
+    for (auto& g : plan->groups) analysis_lists(plan, *g, lists);
+    double best = 0.0;
+    if (int e = timed(best)) return e;
+    for (GemmSched* L : lists) {
+        int keep = L->sched;
+        for (int c = 0; c < HP2SPH_NSCHED; ++c) {
+            if (c == keep) continue;
+            const int prev = L->sched;
+            L->use(c);
+            double t = 0.0;
+            if (int e = timed(t)) {
+                L->use(prev);
+                return e;
+            }
+            if (t < best * (1.0 - 0.005)) {
+                best = t;
+                keep = c;
+            }
+            L->use(keep);
+        }
+    }
+    // leave alm holding the analysis under the chosen schedules
+    if (int e = hp2sph_analyze(plan, maps, alm, workspace, stream)) return e;
+    if (hipStreamSynchronize(s) != hipSuccess) return fail(HP2SPH_EDEVICE, "hipStreamSynchronize failed");
+    if (best_ms) *best_ms = best;
     return HP2SPH_OK;
 }
 
