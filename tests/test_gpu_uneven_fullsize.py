@@ -1,0 +1,89 @@
+"""GPU parity at the batching form's full shape: 256 maps whose nside is drawn
+(seeded) uniformly from {64, 128, 256, 512}, lmax = 2 nside each, one plan over
+the whole batch, with the strategy (`auto`) and the autotuned GEMM schedules
+that bench.py times for this workload.
+
+The oracle cannot analyse the batch's 1.07e9 pixels, so a stratified subset is
+compared map by map:
+* FP32 + refinement against the refined FP64 oracle (one step of eq. uzawa
+  with A the HP2SPH analysis, all FP64) on the first map of the nside 64, 128
+  and 256 classes and on the last map of the nside 64 class;
+* FP64 against the oracle's order-by-order route (the Remark of Sec. 3.2.1)
+  on sampled orders, all l of each, of the first map of every class, nside 512
+  included.
+Inputs are seeded white-noise maps drawn on the host (every scale present):
+the bench's power-law maps come out of the GPU synthesis, and no oracle input
+may come from the GPU path."""
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from gpu_util import rel_err
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+import paper_1904_10514_amd as P   # noqa: E402
+
+# FP32 + refinement vs the refined oracle: the first pass's FP32 error times
+# I - A S (norm up to ~1 on white noise), as in the small-size parity tests.
+TOL_REFINE = 1e-6
+# FP64 at p <= 1024: kappa p eps = 50 * 1024 * 1.1e-16 = 5.6e-12 relative to
+# the largest coefficient on each side (the tolerance of the nside-1024 tests).
+TOL64 = 1.1e-11
+
+
+def _orders(lmax):
+    return sorted({0, 1, 2, 3, lmax // 4, lmax // 2 - 1, lmax // 2, lmax - 1, lmax})
+
+
+@pytest.fixture(scope="module")
+def batch():
+    nsides = [int(v) for v in W.uneven_nsides(256, 3)]
+    lmaxs = [2 * v for v in nsides]
+    maps = [W.random_map(O.npix(ns), W.rng_for(13, i)) for i, ns in enumerate(nsides)]
+    dev = torch.from_numpy(np.concatenate(maps)).cuda()
+    first = {ns: nsides.index(ns) for ns in (64, 128, 256, 512)}
+    last64 = len(nsides) - 1 - nsides[::-1].index(64)
+    return nsides, lmaxs, maps, dev, first, last64
+
+
+def _analyze(batch, mode):
+    nsides, lmaxs, _, dev, _, _ = batch
+    plan = P.Plan(nsides, lmaxs, mode=mode)
+    _, alm = plan.autotune(dev, reps=1)
+    torch.cuda.synchronize()
+    print(f"{mode}: strategy {plan.strategy}, schedules {plan.schedules}")
+    out = alm.cpu().numpy()
+    offs = plan.alm_offsets
+    plan.close()
+    return out, offs
+
+
+def test_uneven_fullsize_refinement_vs_refined_oracle(batch):
+    nsides, lmaxs, maps, _, first, last64 = batch
+    a, offs = _analyze(batch, "f32_refine")
+    for i in (first[64], last64, first[128], first[256]):
+        ref = O.analyze_refined(maps[i], nsides[i])
+        err = rel_err(a[offs[i]:offs[i + 1]], ref)
+        print(f"map {i} (nside {nsides[i]}): FP32 + refinement vs refined oracle {err:.3e}")
+        assert err < TOL_REFINE
+
+
+def test_uneven_fullsize_f64_sampled_orders(batch):
+    nsides, lmaxs, maps, _, first, _ = batch
+    a, offs = _analyze(batch, "f64")
+    for ns, i in sorted(first.items()):
+        lmax = lmaxs[i]
+        orders = _orders(lmax)
+        ref = O.analyze_columns(maps[i], ns, orders, lmax)
+        mine = a[offs[i]:offs[i + 1]]
+        scale = max(np.max(np.abs(ref[m])) for m in orders)
+        worst = 0.0
+        for m in orders:
+            idx = np.array([O.alm_index(l, m, lmax) for l in range(m, lmax + 1)])
+            worst = max(worst, float(np.max(np.abs(mine[idx] - ref[m])) / scale))
+        print(f"map {i} (nside {ns}): FP64 vs oracle on orders {orders}: {worst:.3e}")
+        assert worst < TOL64
