@@ -275,6 +275,19 @@ int hp2sph_autotune(hp2sph_plan_t plan, const double* maps, double* alm, void* w
 int hp2sph_schedules(hp2sph_plan_t plan, int32_t* out, int32_t cap, int32_t* count);
 
 /*
+ * Host-only inspection of a schedule (no GPU needed): the workgroup -> (problem,
+ * tile) map that schedule `sched` gives a list of n GEMM problems of M[i] x N[i]
+ * outputs and extent K[i] in launch order, as the GEMM kernel reads it: entry w
+ * is the pair (problem, tile within the problem) at out[2w], out[2w + 1], or
+ * (-1, -1) for a workgroup that has no tile.  Tiles are 128 x 128 and numbered
+ * row-major within a problem.  Writes min(capacity, 2 * workgroups) entries
+ * and sets *count to 2 * workgroups.  Errors: EINVAL (unknown sched, n < 0,
+ * null arrays, a non-positive size).
+ */
+int hp2sph_schedule_map(int32_t sched, const int32_t* M, const int32_t* N, const int32_t* K, int32_t n,
+                        int32_t* out, int64_t capacity, int64_t* count);
+
+/*
  * Host-only inspection of the set-up tables (no GPU needed; used by tests).
  * Writes up to `capacity` doubles of table `table` for `nside` into `out`
  * and the full element count into *count (out may be NULL to query the

@@ -44,6 +44,7 @@ EXPORTED = [
     "hp2sph_power_spectrum", "hp2sph_plan_destroy", "hp2sph_last_error", "hp2sph_host_table",
     "hp2sph_profile", "hp2sph_profile_read", "hp2sph_plan_create_ex", "hp2sph_plan_strategy",
     "hp2sph_analyze_iterative", "hp2sph_set_schedule", "hp2sph_autotune", "hp2sph_schedules",
+    "hp2sph_schedule_map",
 ]
 STRATEGIES = {"auto": 0, "staged": 1, "tables": 2}
 SCHEDULES = ["xcd_round_robin", "xcd_balanced", "linear"]
@@ -71,6 +72,7 @@ _lib.hp2sph_profile_read.argtypes = [_vp, ctypes.POINTER(ctypes.c_double), ctype
 _lib.hp2sph_set_schedule.argtypes = [_vp, _i32]
 _lib.hp2sph_autotune.argtypes = [_vp, _vp, _vp, _vp, _vp, _i32, ctypes.POINTER(ctypes.c_double)]
 _lib.hp2sph_schedules.argtypes = [_vp, ctypes.POINTER(_i32), _i32, ctypes.POINTER(_i32)]
+_lib.hp2sph_schedule_map.argtypes = [_i32, _vp, _vp, _vp, _i32, _vp, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
 _lib.hp2sph_host_table.argtypes = [_i32, _i32, _i32, _vp, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
 for _f in EXPORTED:
     if _f not in ("hp2sph_last_error",):
@@ -110,6 +112,23 @@ def host_table(nside, table, block=0):
     _check(_lib.hp2sph_host_table(int(nside), int(table), int(block), out.ctypes.data, cnt.value,
                                   ctypes.byref(cnt)), "host_table")
     return out
+
+
+def schedule_map(sched, M, N, K):
+    """Host-only: the workgroup -> (problem, tile) map of schedule `sched` (a
+    name of SCHEDULES) for GEMM problems of sizes M x N, extent K, in launch
+    order, as an (workgroups, 2) int32 array ((-1, -1): no tile)."""
+    M, N, K = (np.ascontiguousarray(x, dtype=np.int32) for x in (M, N, K))
+    if not (len(M) == len(N) == len(K)):
+        raise ValueError("M, N, K must have the same length")
+    cnt = ctypes.c_int64(0)
+    sid = SCHEDULES.index(sched)
+    _check(_lib.hp2sph_schedule_map(sid, M.ctypes.data, N.ctypes.data, K.ctypes.data, len(M), None, 0,
+                                    ctypes.byref(cnt)), "schedule_map")
+    out = np.empty(cnt.value, dtype=np.int32)
+    _check(_lib.hp2sph_schedule_map(sid, M.ctypes.data, N.ctypes.data, K.ctypes.data, len(M), out.ctypes.data,
+                                    cnt.value, ctypes.byref(cnt)), "schedule_map")
+    return out.reshape(-1, 2)
 
 
 def _torch():

@@ -1264,6 +1264,32 @@ int hp2sph_plan_destroy(hp2sph_plan_t plan) {
     return HP2SPH_OK;
 }
 
+int hp2sph_schedule_map(int32_t sched, const int32_t* M, const int32_t* N, const int32_t* K, int32_t n,
+                        int32_t* out, int64_t capacity, int64_t* count) {
+    if (!count) return fail(HP2SPH_EINVAL, "count is null");
+    if (sched < 0 || sched >= HP2SPH_NSCHED) return fail(HP2SPH_EINVAL, "unknown schedule");
+    if (n < 0 || (n > 0 && (!M || !N || !K))) return fail(HP2SPH_EINVAL, "bad problem list");
+    if (capacity < 0 || (capacity > 0 && !out)) return fail(HP2SPH_EINVAL, "bad output buffer");
+    std::vector<int32_t> map;
+    try {
+        std::vector<GemmProblem<double>> v(static_cast<size_t>(n), GemmProblem<double>{});
+        for (int i = 0; i < n; ++i) {
+            if (M[i] <= 0 || N[i] <= 0 || K[i] <= 0) return fail(HP2SPH_EINVAL, "non-positive problem size");
+            v[i].M = M[i];
+            v[i].N = N[i];
+            v[i].K = K[i];
+        }
+        const int tiles = finalize_gemm_problems<double>(v.data(), n);
+        map = sched == HP2SPH_SCHED_XCD_ROUND_ROBIN ? xcd_tile_map<double>(v.data(), n) : schedule_map(v, tiles, sched);
+    } catch (const std::bad_alloc&) {
+        return fail(HP2SPH_ENOMEM, "host allocation failed");
+    }
+    *count = int64_t(map.size());
+    if (capacity > 0)
+        std::memcpy(out, map.data(), sizeof(int32_t) * size_t(std::min<int64_t>(capacity, int64_t(map.size()))));
+    return HP2SPH_OK;
+}
+
 int hp2sph_host_table(int32_t nside, int32_t table, int32_t block, double* out, int64_t capacity, int64_t* count) {
     if (!count) return fail(HP2SPH_EINVAL, "count is null");
     if (nside < 2 || nside > HP2SPH_MAX_NSIDE || !is_pow2(nside)) return fail(HP2SPH_EINVAL, "bad nside");
