@@ -207,6 +207,13 @@ def autotune(plan, maps, out, enabled):
     return {"enabled": True, "schedules": plan.schedules, "best_ms": ms, "seconds": time.perf_counter() - t0}
 
 
+def map0_sha256(maps, npix):
+    """SHA-256 of the first input map (FP64, little-endian bytes), recorded
+    with the bench line so a run's inputs can be compared across runs."""
+    import hashlib
+    return hashlib.sha256(maps[:npix].cpu().numpy().astype("<f8").tobytes()).hexdigest()
+
+
 def time_mode(torch, P, maps, nside, nmaps, mode, steps, warmup, strategy, tune=True):
     t0 = time.perf_counter()
     plan = P.Plan(nside, 2 * nside, batch=nmaps, mode=mode, strategy=strategy)
@@ -337,7 +344,8 @@ def uneven_main(args):
                       "ms_per_step": head["ms_per_step"], "higher_is_better": True, "data": "synthetic",
                       "config": {"workload": "uneven_b256_nside64-512", "batch": len(nsides), "nside_counts": counts,
                                  "lmax": "2 nside",
-                                 "input": "seeded Gaussian a_lm, C_l=l^-2 exp(-l(l+1)s^2), s=0.005, GPU FP64 synthesis"},
+                                 "input": "seeded Gaussian a_lm, C_l=l^-2 exp(-l(l+1)s^2), s=0.005, GPU FP64 synthesis",
+                                 "input_sha256_map0": map0_sha256(maps, 12 * nsides[0] * nsides[0])},
                       "modes": res}), flush=True)
 
 
@@ -388,7 +396,8 @@ def equal_weight_main(args):
                       "warmup": args.warmup, "ms_per_step": 1e3 * dt / args.steps, "higher_is_better": True,
                       "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
                       "config": {"workload": f"equal_weight_nside{nside}_L{lmax}_b{nmaps}", "nside": nside,
-                                 "lmax": lmax, "batch": nmaps, "niter": niter, "strategy": plan.strategy},
+                                 "lmax": lmax, "batch": nmaps, "niter": niter, "strategy": plan.strategy,
+                                 "input_sha256_map0": map0_sha256(maps, 12 * nside * nside)},
                       "setup_s": setup_s, "autotune": tuned, "roofline": rl, "stages": stages}), flush=True)
     plan.close()
 
@@ -496,7 +505,7 @@ def main():
         "dtype": "f32+f64",
         "data": "synthetic",
         "config": {"workload": f"nside{nside}_L{lmax}_b{nmaps}", "nside": nside, "lmax": lmax, "batch": nmaps,
-                   "mode": head_mode, "strategy": head["strategy"],
+                   "mode": head_mode, "strategy": head["strategy"], "input_sha256_map0": map0_sha256(maps, 12 * nside * nside),
                    "input": "seeded Gaussian a_lm, C_l=exp(-l(l+1)s^2)/(l(l+1)), s=0.005, GPU FP64 synthesis, "
                             "+ white noise 1e-3 x map rms"},
         "f64_maps_per_s": f64_value,
