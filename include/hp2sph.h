@@ -233,11 +233,14 @@ int hp2sph_profile_read(hp2sph_plan_t plan, double* ms, int32_t* launches, int32
  * own L2) receive workgroups in turn by workgroup id.
  *   HP2SPH_SCHED_XCD_ROUND_ROBIN  problems (orders / parity blocks, longest
  *       first) dealt to the XCDs in turn, all tiles of a problem on one XCD
- *       (the default of a new plan);
+ *       (the default of a new plan for a GEMM of at least 16 problems, such as
+ *       the per-order GEMMs of the tables strategy);
  *   HP2SPH_SCHED_XCD_BALANCED     each problem, longest first, to the XCD with
  *       the least work so far (tiles times k extent), tiles kept together;
  *   HP2SPH_SCHED_LINEAR           workgroup w runs tile w of the problem list
- *       (no XCD placement).
+ *       (no XCD placement; the default for a GEMM of fewer than 16 problems,
+ *       such as the four parity blocks of the staged strategy, where placing
+ *       whole problems on XCDs would leave XCDs idle).
  */
 enum {
     HP2SPH_SCHED_XCD_ROUND_ROBIN = 0,

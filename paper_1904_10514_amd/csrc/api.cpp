@@ -431,7 +431,10 @@ void upload_list(Group& G, std::vector<GemmProblem<T>>& v, GemmList<T>& out) {
         out.nslots[c] = int(tm.size() / 2);
         out.maps[c] = upload_int(G.owned, tm);
     }
-    out.use(HP2SPH_SCHED_XCD_ROUND_ROBIN);
+    // XCD placement keeps each problem on one XCD, which leaves XCDs idle
+    // when a list has fewer problems than two per XCD (the four parity-block
+    // problems of the staged strategy): those start in list order
+    out.use(v.size() < 2 * 8 ? HP2SPH_SCHED_LINEAR : HP2SPH_SCHED_XCD_ROUND_ROBIN);
 }
 
 // TB: storage type of the Dsym rows the GEMM reads (B offsets in TB elements)
