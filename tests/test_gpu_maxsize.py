@@ -5,7 +5,8 @@ colatitude fit is too slow at this size, so the checks are the exact-recovery
 property on order-1 fields (tests/gpu_util.py), which covers the ring
 transform, pole, fit and packing of every l <= p, the synthesis and the
 refinement; the Givens sweeps of orders >= 2 are covered against the oracle
-at smaller nside and by the staged-vs-tables agreement.
+at smaller nside and by the staged-vs-tables agreement.  The last test runs
+the benchmark's own shape at this nside (16 maps).
 """
 
 import numpy as np
@@ -92,3 +93,24 @@ def test_nside2048_equal_weight_sampled_orders():
     print("residual norms:", norms)
     assert norms[1] <= norms[0] * (1 + 1e-12) and norms[2] <= norms[1] * (1 + 1e-12)
     plan.close()
+
+
+def test_nside2048_batch16_bench_shape():
+    """The nside-2048 benchmark configuration itself: 16 maps, lmax 4096, both
+    modes the bench times, each plan autotuned as the bench does; on order-1
+    fields (recovered exactly for every l <= p) FP64 and FP32 + refinement
+    must return the input coefficients of all 16 maps."""
+    batch = 16
+    maps, expect = order_one_fields(NSIDE, batch, 14)
+    dev = torch.from_numpy(maps.reshape(-1)).cuda()
+    del maps
+    for mode, tol in (("f64", 1e-12), ("f32_refine", 1e-10)):
+        plan = P.Plan(NSIDE, LMAX, batch=batch, mode=mode)
+        assert plan.strategy == "staged"
+        _, a = plan.autotune(dev, reps=1)
+        torch.cuda.synchronize()
+        e = rel_err(a.cpu().numpy().reshape(batch, -1), expect)
+        print(f"order-1 fields, nside 2048 x 16, {mode} (schedules {plan.schedules}): {e:.3e}")
+        plan.close()
+        del a
+        assert e < tol
