@@ -169,8 +169,9 @@ def measured_traffic(stage, dtype, nside, nmaps, strategy):
         if js["workload"] != {"nside": nside, "lmax": 2 * nside, "batch": nmaps, "strategy": strategy}:
             return None
         e = js["stages"].get(f"{stage}/{dtype}")
-        # the counter runs sum a stage's dispatches (two FP32 analysis GEMMs)
-        return None if e is None else (e["read_bytes"] + e["write_bytes"]) / e["dispatches"]
+        # read_bytes / write_bytes are already means over the stage's
+        # dispatches in the counter runs (two for the FP32 analysis GEMMs)
+        return None if e is None else e["read_bytes"] + e["write_bytes"]
     except (OSError, KeyError, ValueError):
         return None
 
