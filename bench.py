@@ -158,7 +158,7 @@ def measured_traffic(stage, dtype, nside, nmaps, strategy):
     by the copy-kernel calibration; None if the kernels changed since then or
     the workload differs."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "hbm_traffic_nside1024_L2048_b64.json")
+    path = os.path.join(ROOT, "profiles", f"hbm_traffic_nside{nside}_L{2 * nside}_b{nmaps}.json")
     try:
         with open(path) as fh:
             js = json.load(fh)
