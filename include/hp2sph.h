@@ -238,15 +238,20 @@ int hp2sph_profile_read(hp2sph_plan_t plan, double* ms, int32_t* launches, int32
  *   HP2SPH_SCHED_XCD_BALANCED     each problem, longest first, to the XCD with
  *       the least work so far (tiles times k extent), tiles kept together;
  *   HP2SPH_SCHED_LINEAR           workgroup w runs tile w of the problem list
- *       (no XCD placement; the default for a GEMM of fewer than 16 problems,
- *       such as the four parity blocks of the staged strategy, where placing
- *       whole problems on XCDs would leave XCDs idle).
+ *       (no XCD placement);
+ *   HP2SPH_SCHED_LINEAR_ROWS      as LINEAR, but within a problem the row tiles
+ *       of one column panel run back to back (row tile fastest), so a column
+ *       panel of B is fetched once while the row tiles that need it are in
+ *       flight, instead of once per row tile (the default for a GEMM of fewer
+ *       than 16 problems, such as the four parity blocks of the staged
+ *       strategy, where placing whole problems on XCDs would leave XCDs idle).
  */
 enum {
     HP2SPH_SCHED_XCD_ROUND_ROBIN = 0,
     HP2SPH_SCHED_XCD_BALANCED = 1,
     HP2SPH_SCHED_LINEAR = 2,
-    HP2SPH_NSCHED = 3
+    HP2SPH_SCHED_LINEAR_ROWS = 3,
+    HP2SPH_NSCHED = 4
 };
 
 /* Use schedule `sched` for every GEMM of the plan (host state only: takes

@@ -47,7 +47,7 @@ EXPORTED = [
     "hp2sph_schedule_map",
 ]
 STRATEGIES = {"auto": 0, "staged": 1, "tables": 2}
-SCHEDULES = ["xcd_round_robin", "xcd_balanced", "linear"]
+SCHEDULES = ["xcd_round_robin", "xcd_balanced", "linear", "linear_rows"]
 MAX_TUNE_REPS = 100
 NSTAGES = 13
 STAGES = ["ring_forward", "pole", "gemm_analysis", "sweep_analysis", "pack", "unpack",

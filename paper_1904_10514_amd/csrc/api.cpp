@@ -372,7 +372,10 @@ int first_row(int m) { return m == 0 ? 0 : (m + 1) / 2; }
 //     times K, longest-processing-time-first), its tiles kept together;
 //     workgroup w runs on XCD w mod 8 (the hardware deals workgroups to the 8
 //     XCDs in turn), entries of -1 pad the XCDs to equal length;
-//   LINEAR: workgroup w runs tile w of the list (no XCD placement).
+//   LINEAR: workgroup w runs tile w of the list (no XCD placement);
+//   LINEAR_ROWS: problems in list order, and within a problem the row tiles
+//     of each column panel consecutively (tile = row * tiles_n + col, row
+//     fastest).
 template <class T>
 std::vector<int32_t> schedule_map(const std::vector<GemmProblem<T>>& v, int total_tiles, int sched) {
     constexpr int kXcd = 8;
@@ -385,6 +388,17 @@ std::vector<int32_t> schedule_map(const std::vector<GemmProblem<T>>& v, int tota
                 out.push_back(i);
                 out.push_back(t);
             }
+        return out;
+    }
+    if (sched == HP2SPH_SCHED_LINEAR_ROWS) {
+        for (int i = 0; i < n; ++i) {
+            const int tn = v[i].tiles_n, tm = tiles_of(i) / tn;
+            for (int c = 0; c < tn; ++c)
+                for (int r = 0; r < tm; ++r) {
+                    out.push_back(i);
+                    out.push_back(r * tn + c);
+                }
+        }
         return out;
     }
     std::vector<std::vector<int32_t>> per(kXcd);
@@ -433,8 +447,9 @@ void upload_list(Group& G, std::vector<GemmProblem<T>>& v, GemmList<T>& out) {
     }
     // XCD placement keeps each problem on one XCD, which leaves XCDs idle
     // when a list has fewer problems than two per XCD (the four parity-block
-    // problems of the staged strategy): those start in list order
-    out.use(v.size() < 2 * 8 ? HP2SPH_SCHED_LINEAR : HP2SPH_SCHED_XCD_ROUND_ROBIN);
+    // problems of the staged strategy): those start in list order, row tiles
+    // of a column panel together
+    out.use(v.size() < 2 * 8 ? HP2SPH_SCHED_LINEAR_ROWS : HP2SPH_SCHED_XCD_ROUND_ROBIN);
 }
 
 // TB: storage type of the Dsym rows the GEMM reads (B offsets in TB elements)

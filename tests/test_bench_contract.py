@@ -51,19 +51,23 @@ def test_per_order_gemm_flops_count_every_coefficient_once():
 
 
 def test_measured_traffic_is_per_launch():
-    """The committed counter summary holds per-dispatch means (FETCH_SIZE and
-    WRITE_SIZE in KiB, averaged over the dispatches it used, then scaled);
-    the bench's roofline traffic is that mean, not divided again."""
+    """The committed counter summaries hold per-dispatch means (FETCH_SIZE and
+    WRITE_SIZE in KiB, averaged over the dispatches used, then scaled); the
+    bench's roofline traffic is that mean, not divided again."""
+    import glob
     import json
-    path = os.path.join(ROOT, "profiles", "hbm_traffic_nside1024_L2048_b64.json")
-    js = json.load(open(path))
-    wl = js["workload"]
-    for key, e in js["stages"].items():
-        stage, dt = key.split("/")
-        got = bench.measured_traffic(stage, dt, wl["nside"], wl["batch"], wl["strategy"])
-        if got is None:   # kernels changed since the counters were taken
-            pytest.skip("counter summary is older than the kernels")
-        assert got == pytest.approx(1024 * (e["fetch_kib"] * js["calibration"]["fetch_scale"] +
-                                            e["write_kib"] * js["calibration"]["write_scale"]), rel=1e-12)
-    # another workload has no measured traffic
-    assert bench.measured_traffic("gemm_synthesis", "f64", 2048, 16, "staged") is None
+    paths = sorted(glob.glob(os.path.join(ROOT, "profiles", "hbm_traffic_*.json")))
+    assert paths
+    for path in paths:
+        js = json.load(open(path))
+        wl = js["workload"]
+        for key, e in js["stages"].items():
+            stage, dt = key.split("/")
+            got = bench.measured_traffic(stage, dt, wl["nside"], wl["batch"], wl["strategy"])
+            if got is None:   # kernels changed since the counters were taken
+                pytest.skip("counter summary is older than the kernels")
+            assert got == pytest.approx(1024 * (e["fetch_kib"] * js["calibration"]["fetch_scale"] +
+                                                e["write_kib"] * js["calibration"]["write_scale"]), rel=1e-12)
+    # a workload without counter runs, or another strategy, has no measured traffic
+    assert bench.measured_traffic("gemm_synthesis", "f64", 512, 3, "tables") is None
+    assert bench.measured_traffic("gemm_synthesis", "f64", 1024, 64, "staged") is None

@@ -50,12 +50,13 @@ def test_every_schedule_gives_the_same_result(mode, strategy, nsides, lmaxs):
     plan = P.Plan(nsides, lmaxs, mode=mode, strategy=strategy)
     iterative = mode == "equal_weight"
     # defaults: XCD placement for the per-order GEMMs (thousands of problems),
-    # list order for the staged ones (four parity-block problems)
+    # list order with row tiles fastest for the staged ones (four
+    # parity-block problems)
     assert plan.schedules
     if strategy == "tables":
         assert all(s == "xcd_round_robin" for s in plan.schedules)
     elif strategy == "staged":
-        assert all(s == "linear" for s in plan.schedules)
+        assert all(s == "linear_rows" for s in plan.schedules)
     results = {}
     for name in P.SCHEDULES:
         plan.set_schedule(name)

@@ -12,7 +12,9 @@ the per-order problems: up to 9 row tiles, 1..3 column tiles, ragged edges):
   round robin puts problem i on XCD i mod 8; balanced keeps the XCD loads
   (tiles x K) within the largest single problem's load of each other, the
   bound of greedy least-loaded placement;
-* linear: workgroup w runs the w-th tile of the list in order, no padding."""
+* linear: workgroup w runs the w-th tile of the list in order, no padding;
+* linear_rows: problems in list order, within each the row tiles of one column
+  panel back to back (tile index = row * column_tiles + column), no padding."""
 
 import ctypes
 
@@ -68,6 +70,17 @@ def test_linear_schedule_is_list_order(case):
     tiles = _tiles(M, N)
     mp = P.schedule_map("linear", M, N, K)
     expect = [(i, t) for i in range(len(M)) for t in range(tiles[i])]
+    assert [tuple(x) for x in mp] == expect
+
+
+@pytest.mark.parametrize("case", range(8))
+def test_linear_rows_schedule_runs_row_tiles_of_a_panel_together(case):
+    M, N, K = _problem_lists()[case]
+    mp = P.schedule_map("linear_rows", M, N, K)
+    expect = []
+    for i in range(len(M)):
+        rows, cols = -(-M[i] // TILE), -(-N[i] // TILE)
+        expect += [(i, r * cols + c) for c in range(cols) for r in range(rows)]
     assert [tuple(x) for x in mp] == expect
 
 
