@@ -96,18 +96,23 @@ def test_nside2048_equal_weight_sampled_orders():
 
 
 def test_nside2048_batch16_bench_shape():
-    """The nside-2048 benchmark configuration itself: 16 maps, lmax 4096, both
-    modes the bench times, each plan autotuned as the bench does; on order-1
-    fields (recovered exactly for every l <= p) FP64 and FP32 + refinement
-    must return the input coefficients of all 16 maps."""
+    """The nside-2048 benchmark configuration itself: 16 maps, lmax 4096, the
+    FP32 + refinement plan (its FP64 ring transform and synthesis included)
+    with the default schedules (`linear_rows` for the staged GEMMs, what the
+    bench's autotuner picks at this shape; the tuner itself is tested in
+    test_gpu_schedule.py); on order-1 fields (recovered exactly for every
+    l <= p) it must return the input coefficients of all 16 maps.  (FP64 at
+    this nside is checked on 2 maps above: each nside-2048 plan takes about a
+    minute to set up.)"""
     batch = 16
     maps, expect = order_one_fields(NSIDE, batch, 14)
     dev = torch.from_numpy(maps.reshape(-1)).cuda()
     del maps
-    for mode, tol in (("f64", 1e-12), ("f32_refine", 1e-10)):
+    for mode, tol in (("f32_refine", 1e-10),):
         plan = P.Plan(NSIDE, LMAX, batch=batch, mode=mode)
         assert plan.strategy == "staged"
-        _, a = plan.autotune(dev, reps=1)
+        assert plan.schedules == ["linear_rows"] * len(plan.schedules)
+        a = plan.analyze(dev)
         torch.cuda.synchronize()
         e = rel_err(a.cpu().numpy().reshape(batch, -1), expect)
         print(f"order-1 fields, nside 2048 x 16, {mode} (schedules {plan.schedules}): {e:.3e}")
