@@ -49,7 +49,10 @@ The steps, with the readings taken where the paper is silent:
 Parity: pinned (see tests/test_oracle_*.py): constant map, real-map
 symmetry, the exact equivariances of the point set, exact recovery of
 Y_l^{+-1} and Y_0^0, Y_1^0, Y_2^0, consistency of the colatitude fit on
-trigonometric polynomials, and agreement of the spatial route (this module's
+trigonometric polynomials, the unweighted normal equations of that fit on
+data it cannot fit exactly (equal weights on all doubled-grid rows), the
+re-expansion of X over k = -p..p onto the fitted columns (the half split of
+the k = +-p columns), and agreement of the spatial route (this module's
 analyze_full) with the Fourier-space route of the Remark in Sec. 3.2.1
 (analyze_columns).
 """

@@ -134,6 +134,72 @@ def test_colatitude_fit_recovers_trig_polynomials(nside):
     assert np.max(np.abs(H._lsq(nside).solve(d) - X)) < 1e-12
 
 
+@pytest.mark.parametrize("nside", [2, 4, 8])
+def test_bivariate_coefficients_reexpand_to_the_fitted_columns(nside):
+    """Sec. 3.3: summed over k = -p..p against e^{i k lambda_t} on the longitude
+    nodes lambda_t = t pi / (2 Nside), the X array gives back the colatitude
+    series fitted to every column of the doubled grid.  On the nodes
+    e^{i p lambda_t} = e^{-i p lambda_t}, so the two k = +-p columns must add up
+    to the single grid Nyquist coefficient C_{-p}: this fixes the half weights
+    of the split (the real-map symmetry, pinned above on all orders, fixes that
+    the two halves are equal)."""
+    p = 2 * nside
+    f = _rand_map(nside, 11)
+    X = H.bivariate_coefficients(f, nside)
+    # the fitted colatitude series of every longitude column, straight from the
+    # least-squares fit of the doubled grid
+    xhat = H._lsq(nside).solve(H.dfs_grid(f, nside).astype(np.complex128))
+    lam = np.arange(4 * nside) * np.pi / (2 * nside)
+    k = np.arange(-p, p + 1)
+    back = X @ np.exp(1j * np.outer(k, lam))
+    assert np.max(np.abs(back - xhat)) < 1e-13 * np.max(np.abs(xhat))
+    # the input has Nyquist content (unshifted belt rings), so the split matters
+    assert np.max(np.abs(X[:, 0])) > 1e-3 * np.max(np.abs(X))
+
+
+def _dfs_colatitudes(nside):
+    """The 8 Nside doubled-grid colatitudes built here from eq. (healpts):
+    north pole, rings 1 .. 4 Nside - 1, south pole, then 2 pi - theta_r."""
+    ns = float(nside)
+    th = []
+    for r in range(1, 4 * nside):
+        j = min(r, 4 * nside - r)
+        if j < nside:
+            z = 1.0 - j * j / (3.0 * ns * ns)
+            t = 2.0 * np.arcsin(j / (np.sqrt(6.0) * ns))    # 1 - cos t = j^2 / (3 Nside^2)
+            th.append(t if r < nside else np.pi - t)
+            assert abs(np.cos(th[-1]) - (z if r < nside else -z)) < 1e-14
+        else:
+            th.append(np.arccos(2.0 * (2 * nside - r) / (3.0 * ns)))
+    th = np.array(th)
+    return np.concatenate([[0.0], th, [np.pi], 2.0 * np.pi - th[::-1]])
+
+
+@pytest.mark.parametrize("nside", [2, 4, 8])
+def test_colatitude_fit_solves_the_unweighted_normal_equations(nside):
+    """Sec. 3.2.2, eqs. normal_eq and equigrid: the fit minimises the plain sum
+    of squares over all 8 Nside doubled-grid rows (pole rows weighted like any
+    other).  On data that no trigonometric polynomial of degree p fits, the
+    residual d - E x must be orthogonal to every column of E_{s,j} =
+    e^{i j theta_s}, j = -p..p, i.e. E^H E x = E^H d.  A weighted fit (say the
+    pole rows counted three times) leaves a residual that is not."""
+    p = 2 * nside
+    theta = _dfs_colatitudes(nside)
+    assert np.allclose(theta, H.dfs_thetas(nside), rtol=0, atol=1e-14)
+    E = np.exp(1j * np.outer(theta, np.arange(-p, p + 1)))
+    rng = np.random.default_rng(12)
+    d = rng.standard_normal(8 * nside) + 1j * rng.standard_normal(8 * nside)
+    x = H._lsq(nside).solve(d)
+    res = d - E @ x
+    assert np.linalg.norm(res) > 0.1 * np.linalg.norm(d)          # not an exact fit
+    assert np.max(np.abs(E.conj().T @ res)) < 1e-12 * np.max(np.abs(E.conj().T @ d))
+    # the normal matrix is the Toeplitz matrix of the sums of e^{i q theta_s}
+    q = np.arange(-2 * p, 2 * p + 1)
+    t = np.exp(1j * np.outer(q, theta)).sum(axis=1)
+    jj = np.arange(-p, p + 1)
+    assert np.max(np.abs(E.conj().T @ E - t[(jj[None, :] - jj[:, None]) + 2 * p])) < 1e-11
+
+
 def test_doubled_grid_gives_sphere_parity():
     """On the doubled grid even-k columns are cosine series and odd-k sine series."""
     nside = 8
