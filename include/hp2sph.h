@@ -88,8 +88,8 @@ enum {
     HP2SPH_EINVAL = -1,      /* bad argument (size, mode, null/misaligned pointer) */
     HP2SPH_ENOMEM = -2,      /* host or device allocation of plan tables failed  */
     HP2SPH_EDEVICE = -3,     /* a HIP call failed; see hp2sph_last_error()       */
-    HP2SPH_EWORKSPACE = -4,  /* workspace pointer null or misaligned             */
-    HP2SPH_ESTATE = -5       /* plan handle is null or already destroyed         */
+    HP2SPH_EWORKSPACE = -4,  /* workspace null, misaligned or too small          */
+    HP2SPH_ESTATE = -5       /* plan handle null, never created or destroyed     */
 };
 
 /* Largest nside a plan accepts (FFT lengths and LDS budgets are sized for it). */
@@ -122,7 +122,8 @@ int hp2sph_plan_create(const int32_t* nside, const int32_t* lmax, int32_t batch,
  *       rings that cannot carry mode m.  Costs O(nside^3) device memory
  *       (~29 GB FP64 at nside 1024).
  *   HP2SPH_STRATEGY_AUTO    tables when the group has >= 8 maps and its tables
- *       fit in a quarter of device memory; staged otherwise.
+ *       take at most a quarter of device memory and fit in the free memory;
+ *       staged otherwise.
  */
 enum {
     HP2SPH_STRATEGY_AUTO = 0,
@@ -133,7 +134,8 @@ enum {
 /* hp2sph_plan_create with an explicit strategy (see above).  Table
  * construction runs on the GPU (Givens sweeps on the set-up matrices) and
  * synchronises the device.  Errors: as hp2sph_plan_create, EINVAL for an
- * unknown strategy, ENOMEM if the tables do not fit. */
+ * unknown strategy, ENOMEM if the tables do not fit in the free device memory
+ * (checked before anything is built or allocated for them). */
 int hp2sph_plan_create_ex(const int32_t* nside, const int32_t* lmax, int32_t batch,
                           int32_t mode, int32_t strategy, hp2sph_plan_t* out);
 
@@ -145,14 +147,15 @@ int hp2sph_workspace_size(hp2sph_plan_t plan, size_t* bytes);
 
 /*
  * Analysis, Algorithm 1: maps (device, FP64, read only) -> alm (device,
- * complex128, written).  workspace: device, >= hp2sph_workspace_size bytes,
- * 256-byte aligned, contents need not be initialised and are clobbered.
+ * complex128, written).  workspace: device, 256-byte aligned, contents need
+ * not be initialised and are clobbered; workspace_bytes: its size, at least
+ * hp2sph_workspace_size (EWORKSPACE otherwise, before anything is launched).
  * For an HP2SPH_EQUAL_WEIGHT plan this is hp2sph_analyze_iterative with
  * niter = 3, the iteration count the paper gives as HEALPix's default.
  * Errors: EINVAL (null/misaligned maps or alm), EWORKSPACE, ESTATE, EDEVICE.
  */
 int hp2sph_analyze(hp2sph_plan_t plan, const double* maps, double* alm,
-                   void* workspace, void* stream);
+                   void* workspace, size_t workspace_bytes, void* stream);
 
 /*
  * Equal-weight analysis with Jacobi iterations (Sec. 2.2, eqs. healsph,
@@ -166,13 +169,15 @@ int hp2sph_analyze(hp2sph_plan_t plan, const double* maps, double* alm,
  * Legendre functions at the ring colatitudes.  The iteration converges to the
  * least-squares a_lm (eq. richardson) at the rate of the spectral radius of
  * I - (4 pi / N) S^* S.  Degrees l <= lmax <= 2 nside (the plan's band).
- * maps, alm, workspace as for hp2sph_analyze; 0 <= niter <= HP2SPH_MAX_JACOBI.
+ * maps, alm, workspace, workspace_bytes as for hp2sph_analyze;
+ * 0 <= niter <= HP2SPH_MAX_JACOBI.
  * Errors: EINVAL (plan of another mode, niter out of range, null/misaligned
  * pointers), EWORKSPACE, ESTATE, EDEVICE.
  */
 #define HP2SPH_MAX_JACOBI 1000
 int hp2sph_analyze_iterative(hp2sph_plan_t plan, const double* maps, double* alm,
-                             int32_t niter, void* workspace, void* stream);
+                             int32_t niter, void* workspace, size_t workspace_bytes,
+                             void* stream);
 
 /*
  * Exact synthesis, eq. (synthesis) (Sec. 2.2): alm (device, complex128,
@@ -184,7 +189,7 @@ int hp2sph_analyze_iterative(hp2sph_plan_t plan, const double* maps, double* alm
  * paper names in Sec. 5.  Errors as for hp2sph_analyze.
  */
 int hp2sph_synthesize(hp2sph_plan_t plan, const double* alm, double* maps,
-                      void* workspace, void* stream);
+                      void* workspace, size_t workspace_bytes, void* stream);
 
 /*
  * Angular power spectrum, eq. (APS): C_l = (|a_l^0|^2 + 2 sum_{m=1}^{l}
@@ -195,7 +200,11 @@ int hp2sph_synthesize(hp2sph_plan_t plan, const double* alm, double* maps,
 int hp2sph_power_spectrum(hp2sph_plan_t plan, const double* alm, double* cl,
                           void* stream);
 
-/* Free the plan's device tables and host state.  ESTATE for a null plan. */
+/* Free the plan's device tables and host state.  ESTATE for a null handle or
+ * one that is not a live plan (never created, or destroyed already): handles
+ * are looked up among the live plans, never dereferenced, so a second destroy
+ * is reported, not undefined.  Destroying a plan while a call on it runs on
+ * another thread is the caller's error. */
 int hp2sph_plan_destroy(hp2sph_plan_t plan);
 
 /* Thread-local text of the last error on the calling thread ("" if none). */
@@ -269,13 +278,14 @@ int hp2sph_set_schedule(hp2sph_plan_t plan, int32_t sched);
  * `stream`, after one untimed analysis).  Synchronous: returns after the last
  * timed run, with alm holding hp2sph_analyze(maps) and *best_ms (if not null)
  * the time of one analysis under the chosen schedules.  Stage profiling
- * (hp2sph_profile) is paused meanwhile.  maps, alm, workspace, stream as for
- * hp2sph_analyze; 1 <= reps <= HP2SPH_MAX_TUNE_REPS.
+ * (hp2sph_profile) is paused meanwhile.  maps, alm, workspace,
+ * workspace_bytes, stream as for hp2sph_analyze; 1 <= reps <=
+ * HP2SPH_MAX_TUNE_REPS.
  * Errors: as hp2sph_analyze, EINVAL for reps out of range, EDEVICE.
  */
 #define HP2SPH_MAX_TUNE_REPS 100
 int hp2sph_autotune(hp2sph_plan_t plan, const double* maps, double* alm, void* workspace,
-                    void* stream, int32_t reps, double* best_ms);
+                    size_t workspace_bytes, void* stream, int32_t reps, double* best_ms);
 
 /* Schedules in use by the GEMMs hp2sph_analyze launches, in the order the
  * autotuner visits them: writes min(cap, count) ids to out (may be null when

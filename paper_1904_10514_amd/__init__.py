@@ -58,9 +58,10 @@ _vp = ctypes.c_void_p
 _i32 = ctypes.c_int32
 _lib.hp2sph_plan_create.argtypes = [ctypes.POINTER(_i32), ctypes.POINTER(_i32), _i32, _i32, ctypes.POINTER(_vp)]
 _lib.hp2sph_workspace_size.argtypes = [_vp, ctypes.POINTER(ctypes.c_size_t)]
-_lib.hp2sph_analyze.argtypes = [_vp, _vp, _vp, _vp, _vp]
-_lib.hp2sph_synthesize.argtypes = [_vp, _vp, _vp, _vp, _vp]
-_lib.hp2sph_analyze_iterative.argtypes = [_vp, _vp, _vp, _i32, _vp, _vp]
+_sz = ctypes.c_size_t
+_lib.hp2sph_analyze.argtypes = [_vp, _vp, _vp, _vp, _sz, _vp]
+_lib.hp2sph_synthesize.argtypes = [_vp, _vp, _vp, _vp, _sz, _vp]
+_lib.hp2sph_analyze_iterative.argtypes = [_vp, _vp, _vp, _i32, _vp, _sz, _vp]
 _lib.hp2sph_power_spectrum.argtypes = [_vp, _vp, _vp, _vp]
 _lib.hp2sph_plan_destroy.argtypes = [_vp]
 _lib.hp2sph_last_error.restype = ctypes.c_char_p
@@ -70,7 +71,7 @@ _lib.hp2sph_plan_strategy.argtypes = [_vp, ctypes.POINTER(_i32)]
 _lib.hp2sph_profile.argtypes = [_vp, _i32]
 _lib.hp2sph_profile_read.argtypes = [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i32), _i32]
 _lib.hp2sph_set_schedule.argtypes = [_vp, _i32]
-_lib.hp2sph_autotune.argtypes = [_vp, _vp, _vp, _vp, _vp, _i32, ctypes.POINTER(ctypes.c_double)]
+_lib.hp2sph_autotune.argtypes = [_vp, _vp, _vp, _vp, _sz, _vp, _i32, ctypes.POINTER(ctypes.c_double)]
 _lib.hp2sph_schedules.argtypes = [_vp, ctypes.POINTER(_i32), _i32, ctypes.POINTER(_i32)]
 _lib.hp2sph_schedule_map.argtypes = [_i32, _vp, _vp, _vp, _i32, _vp, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
 _lib.hp2sph_host_table.argtypes = [_i32, _i32, _i32, _vp, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
@@ -138,6 +139,22 @@ def _torch():
     return torch
 
 
+def _check_tensor(t, name, dtype, numel, device):
+    """The C ABI takes raw pointers, so every buffer is checked here before a
+    call: its dtype, element count, contiguity and device (the plan's)."""
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{name} must be a torch tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_cuda or t.device != device:
+        raise ValueError(f"{name} must live on {device}, got {t.device}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.numel() != numel:
+        raise ValueError(f"{name} has {t.numel()} elements, the plan expects {numel}")
+
+
 class Plan:
     """A plan for a batch of maps (uniform or uneven nside)."""
 
@@ -170,7 +187,8 @@ class Plan:
         ws = ctypes.c_size_t(0)
         _check(_lib.hp2sph_workspace_size(self._h, ctypes.byref(ws)), "workspace_size")
         self.workspace_bytes = ws.value
-        self._ws = torch.empty(max(ws.value, 1) + 256, dtype=torch.uint8, device="cuda")
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        self._ws = torch.empty(max(ws.value, 1) + 256, dtype=torch.uint8, device=self.device)
         base = self._ws.data_ptr()
         self._ws_ptr = (base + 255) // 256 * 256
         self.npix_total = sum(npix(v) for v in nside)
@@ -184,49 +202,56 @@ class Plan:
         import torch
         return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
-    def analyze(self, maps, out=None):
-        torch = _torch()
-        if maps.dtype != torch.float64 or not maps.is_cuda or not maps.is_contiguous():
-            raise ValueError("maps must be a contiguous float64 CUDA tensor")
-        if maps.numel() != self.npix_total:
-            raise ValueError(f"maps has {maps.numel()} values, plan expects {self.npix_total}")
+    def _maps(self, maps):
+        import torch
+        _check_tensor(maps, "maps", torch.float64, self.npix_total, self.device)
+
+    def _alm(self, alm, name="alm"):
+        import torch
+        _check_tensor(alm, name, torch.complex128, self.alm_total, self.device)
+
+    def _alm_out(self, out):
+        import torch
         if out is None:
-            out = torch.empty(self.alm_total, dtype=torch.complex128, device=maps.device)
-        _check(_lib.hp2sph_analyze(self._h, maps.data_ptr(), out.data_ptr(), self._ws_ptr, self._stream()),
-               "analyze")
+            return torch.empty(self.alm_total, dtype=torch.complex128, device=self.device)
+        self._alm(out, "out")
+        return out
+
+    def analyze(self, maps, out=None):
+        _torch()
+        self._maps(maps)
+        out = self._alm_out(out)
+        _check(_lib.hp2sph_analyze(self._h, maps.data_ptr(), out.data_ptr(), self._ws_ptr, self.workspace_bytes,
+                                   self._stream()), "analyze")
         return out
 
     def analyze_iterative(self, maps, niter, out=None):
         """Equal-weight analysis with `niter` Jacobi iterations (mode="equal_weight")."""
-        torch = _torch()
-        if maps.dtype != torch.float64 or not maps.is_cuda or not maps.is_contiguous():
-            raise ValueError("maps must be a contiguous float64 CUDA tensor")
-        if maps.numel() != self.npix_total:
-            raise ValueError(f"maps has {maps.numel()} values, plan expects {self.npix_total}")
-        if out is None:
-            out = torch.empty(self.alm_total, dtype=torch.complex128, device=maps.device)
+        _torch()
+        self._maps(maps)
+        out = self._alm_out(out)
         _check(_lib.hp2sph_analyze_iterative(self._h, maps.data_ptr(), out.data_ptr(), int(niter), self._ws_ptr,
-                                             self._stream()), "analyze_iterative")
+                                             self.workspace_bytes, self._stream()), "analyze_iterative")
         return out
 
     def synthesize(self, alm, out=None):
         torch = _torch()
-        if alm.dtype != torch.complex128 or not alm.is_cuda or not alm.is_contiguous():
-            raise ValueError("alm must be a contiguous complex128 CUDA tensor")
-        if alm.numel() != self.alm_total:
-            raise ValueError("alm has the wrong size for this plan")
+        self._alm(alm)
         if out is None:
-            out = torch.empty(self.npix_total, dtype=torch.float64, device=alm.device)
-        _check(_lib.hp2sph_synthesize(self._h, alm.data_ptr(), out.data_ptr(), self._ws_ptr, self._stream()),
-               "synthesize")
+            out = torch.empty(self.npix_total, dtype=torch.float64, device=self.device)
+        else:
+            _check_tensor(out, "out", torch.float64, self.npix_total, self.device)
+        _check(_lib.hp2sph_synthesize(self._h, alm.data_ptr(), out.data_ptr(), self._ws_ptr, self.workspace_bytes,
+                                      self._stream()), "synthesize")
         return out
 
     def power_spectrum(self, alm, out=None):
         torch = _torch()
-        if alm.dtype != torch.complex128 or not alm.is_cuda or not alm.is_contiguous():
-            raise ValueError("alm must be a contiguous complex128 CUDA tensor")
+        self._alm(alm)
         if out is None:
-            out = torch.empty(self.cl_total, dtype=torch.float64, device=alm.device)
+            out = torch.empty(self.cl_total, dtype=torch.float64, device=self.device)
+        else:
+            _check_tensor(out, "out", torch.float64, self.cl_total, self.device)
         _check(_lib.hp2sph_power_spectrum(self._h, alm.data_ptr(), out.data_ptr(), self._stream()),
                "power_spectrum")
         return out
@@ -240,16 +265,12 @@ class Plan:
     def autotune(self, maps, reps=3, out=None):
         """Time the analysis of `maps` under each candidate GEMM schedule and
         keep the fastest (synchronous).  Returns (ms per analysis, alm)."""
-        torch = _torch()
-        if maps.dtype != torch.float64 or not maps.is_cuda or not maps.is_contiguous():
-            raise ValueError("maps must be a contiguous float64 CUDA tensor")
-        if maps.numel() != self.npix_total:
-            raise ValueError(f"maps has {maps.numel()} values, plan expects {self.npix_total}")
-        if out is None:
-            out = torch.empty(self.alm_total, dtype=torch.complex128, device=maps.device)
+        _torch()
+        self._maps(maps)
+        out = self._alm_out(out)
         ms = ctypes.c_double(0.0)
-        _check(_lib.hp2sph_autotune(self._h, maps.data_ptr(), out.data_ptr(), self._ws_ptr, self._stream(),
-                                    int(reps), ctypes.byref(ms)), "autotune")
+        _check(_lib.hp2sph_autotune(self._h, maps.data_ptr(), out.data_ptr(), self._ws_ptr, self.workspace_bytes,
+                                    self._stream(), int(reps), ctypes.byref(ms)), "autotune")
         return ms.value, out
 
     @property

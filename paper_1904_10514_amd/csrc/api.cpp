@@ -6,9 +6,11 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <stdexcept>
 #include <string>
+#include <unordered_set>
 #include <vector>
 
 #include "../../include/hp2sph.h"
@@ -193,7 +195,6 @@ struct hp2sph_plan_s {
     size_t off_Ua = 0;                // refinement: FP32 a0 in the U layout; equal weight: FP64 a in the U layout
     size_t off_Wf = 0, off_Wr = 0;   // equal weight: longitude sums of the maps and of the residual
     int strategy = 0;                 // requested HP2SPH_STRATEGY_*
-    uint32_t magic = 0x48503253u;
 };
 
 using namespace hp2sph;
@@ -240,13 +241,11 @@ void set_layout(GroupDims& d, bool modemajor) {
     }
 }
 
-void build_group(hp2sph_plan_t plan, Group& G) {
-    HostTables h;
-    build_tables(G.nside, h, true);
-    const int p = h.p;
+// Shapes of a group's blocks and workspace rows (host arithmetic only).
+void init_dims(Group& G) {
     GroupDims& d = G.dims;
     d.nside = G.nside;
-    d.p = p;
+    d.p = 2 * G.nside;
     d.nmaps = int(G.members.size());
     for (int b = 0; b < 4; ++b) {
         BlockShape bs = block_shape(G.nside, b);
@@ -261,6 +260,14 @@ void build_group(hp2sph_plan_t plan, Group& G) {
     d.N[0] = int64_t(d.nmaps) * d.Npm[0];
     d.N[1] = int64_t(d.nmaps) * d.Npm[1];
     set_layout(d, false);
+}
+
+void build_group(hp2sph_plan_t plan, Group& G) {
+    HostTables h;
+    build_tables(G.nside, h, true);
+    const int p = h.p;
+    GroupDims& d = G.dims;
+    init_dims(G);
     for (int i = 0; i < 3; ++i) G.pole_w[i] = h.pole_w[i];
 
     // rings
@@ -937,8 +944,27 @@ int jacobi_pass(hp2sph_plan_t plan, Group& G, const double* maps, double* alm, i
 
 bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
 
+// Handles of the plans that are alive (created and not yet destroyed).  A
+// handle is checked against this set before anything reads through it, so a
+// destroyed or never-created handle gives ESTATE without touching its memory.
+std::mutex g_plans_mu;
+std::unordered_set<const hp2sph_plan_s*>& live_plans() {
+    static std::unordered_set<const hp2sph_plan_s*> s;
+    return s;
+}
+
 int check_plan(hp2sph_plan_t plan) {
-    if (!plan || plan->magic != 0x48503253u) return fail(HP2SPH_ESTATE, "invalid plan handle");
+    if (!plan) return fail(HP2SPH_ESTATE, "plan handle is null");
+    std::lock_guard<std::mutex> lk(g_plans_mu);
+    if (!live_plans().count(plan)) return fail(HP2SPH_ESTATE, "not a live plan handle (never created, or destroyed)");
+    return HP2SPH_OK;
+}
+
+int check_workspace(hp2sph_plan_t plan, const void* workspace, size_t bytes) {
+    if (!workspace || !aligned(workspace, kAlign)) return fail(HP2SPH_EWORKSPACE, "workspace null or not 256-byte aligned");
+    if (bytes < plan->ws_bytes)
+        return fail(HP2SPH_EWORKSPACE, "workspace of " + std::to_string(bytes) + " bytes is smaller than the " +
+                                           std::to_string(plan->ws_bytes) + " bytes the plan needs");
     return HP2SPH_OK;
 }
 
@@ -1026,18 +1052,27 @@ int hp2sph_plan_create_ex(const int32_t* nside, const int32_t* lmax, int32_t bat
             auto G = std::make_unique<Group>();
             G->nside = it->first;
             G->members = it->second;
+            init_dims(*G);
+            // strategy: per-order tables when asked, or (auto) when the batch is
+            // large enough to fill MFMA tiles and the tables take at most a
+            // quarter of the device memory (and fit in what is free); staged
+            // sweeps otherwise
+            bool tables = (strategy == HP2SPH_STRATEGY_TABLES);
+            size_t fre = 0, tot = 0;
+            if (hipMemGetInfo(&fre, &tot) != hipSuccess) return fail(HP2SPH_EDEVICE, "hipMemGetInfo failed");
+            if (strategy == HP2SPH_STRATEGY_AUTO) {
+                const size_t need = order_table_bytes(*G, mode);
+                tables = G->dims.nmaps >= 8 && need <= tot / 4 && need <= fre;
+            }
+            // tables that cannot fit are refused before anything is built or
+            // allocated for them
+            if (tables && order_table_bytes(*G, mode) > fre)
+                return fail(HP2SPH_ENOMEM, "per-order tables of nside " + std::to_string(G->nside) + " need " +
+                                               std::to_string(order_table_bytes(*G, mode) >> 20) + " MiB, " +
+                                               std::to_string(fre >> 20) + " MiB of device memory are free");
             build_group(plan.get(), *G);
             G->off_D = 0;
             G->off_U = align_up(G->bytes_D);
-            // strategy: per-order tables when asked, or (auto) when the batch is
-            // large enough to fill MFMA tiles and the tables take at most a
-            // quarter of the device memory; staged sweeps otherwise
-            bool tables = (strategy == HP2SPH_STRATEGY_TABLES);
-            if (strategy == HP2SPH_STRATEGY_AUTO) {
-                size_t fre = 0, tot = 0;
-                if (hipMemGetInfo(&fre, &tot) != hipSuccess) tot = 0;
-                tables = G->dims.nmaps >= 8 && order_table_bytes(*G, mode) <= tot / 4;
-            }
             G->tables = tables;
             set_layout(G->dims, tables);
             staged_synthesis_list(*G, G->syn64_staged);
@@ -1084,6 +1119,10 @@ int hp2sph_plan_create_ex(const int32_t* nside, const int32_t* lmax, int32_t bat
     } catch (const std::exception& e) {
         return fail(HP2SPH_EDEVICE, e.what());
     }
+    {
+        std::lock_guard<std::mutex> lk(g_plans_mu);
+        live_plans().insert(plan.get());
+    }
     *out = plan.release();
     return HP2SPH_OK;
 }
@@ -1105,12 +1144,13 @@ int hp2sph_workspace_size(hp2sph_plan_t plan, size_t* bytes) {
     return HP2SPH_OK;
 }
 
-int hp2sph_analyze(hp2sph_plan_t plan, const double* maps, double* alm, void* workspace, void* stream) {
+int hp2sph_analyze(hp2sph_plan_t plan, const double* maps, double* alm, void* workspace, size_t workspace_bytes,
+                   void* stream) {
     if (int e = check_plan(plan)) return e;
     g_prof = &plan->prof;
     if (!maps || !alm) return fail(HP2SPH_EINVAL, "maps/alm is null");
     if (!aligned(maps, 16) || !aligned(alm, 16)) return fail(HP2SPH_EINVAL, "maps/alm not 16-byte aligned");
-    if (!workspace || !aligned(workspace, kAlign)) return fail(HP2SPH_EWORKSPACE, "workspace null or not 256-byte aligned");
+    if (int e = check_workspace(plan, workspace, workspace_bytes)) return e;
     hipStream_t s = static_cast<hipStream_t>(stream);
     for (auto& gp : plan->groups) {
         Group& G = *gp;
@@ -1128,26 +1168,27 @@ int hp2sph_analyze(hp2sph_plan_t plan, const double* maps, double* alm, void* wo
 }
 
 int hp2sph_analyze_iterative(hp2sph_plan_t plan, const double* maps, double* alm, int32_t niter, void* workspace,
-                             void* stream) {
+                             size_t workspace_bytes, void* stream) {
     if (int e = check_plan(plan)) return e;
     g_prof = &plan->prof;
     if (plan->mode != HP2SPH_EQUAL_WEIGHT) return fail(HP2SPH_EINVAL, "plan was not created with HP2SPH_EQUAL_WEIGHT");
     if (niter < 0 || niter > HP2SPH_MAX_JACOBI) return fail(HP2SPH_EINVAL, "niter out of range");
     if (!maps || !alm) return fail(HP2SPH_EINVAL, "maps/alm is null");
     if (!aligned(maps, 16) || !aligned(alm, 16)) return fail(HP2SPH_EINVAL, "maps/alm not 16-byte aligned");
-    if (!workspace || !aligned(workspace, kAlign)) return fail(HP2SPH_EWORKSPACE, "workspace null or not 256-byte aligned");
+    if (int e = check_workspace(plan, workspace, workspace_bytes)) return e;
     hipStream_t s = static_cast<hipStream_t>(stream);
     for (auto& gp : plan->groups)
         if (int e = jacobi_pass(plan, *gp, maps, alm, niter, workspace, s)) return e;
     return HP2SPH_OK;
 }
 
-int hp2sph_synthesize(hp2sph_plan_t plan, const double* alm, double* maps, void* workspace, void* stream) {
+int hp2sph_synthesize(hp2sph_plan_t plan, const double* alm, double* maps, void* workspace, size_t workspace_bytes,
+                      void* stream) {
     if (int e = check_plan(plan)) return e;
     g_prof = &plan->prof;
     if (!maps || !alm) return fail(HP2SPH_EINVAL, "maps/alm is null");
     if (!aligned(maps, 16) || !aligned(alm, 16)) return fail(HP2SPH_EINVAL, "maps/alm not 16-byte aligned");
-    if (!workspace || !aligned(workspace, kAlign)) return fail(HP2SPH_EWORKSPACE, "workspace null or not 256-byte aligned");
+    if (int e = check_workspace(plan, workspace, workspace_bytes)) return e;
     hipStream_t s = static_cast<hipStream_t>(stream);
     for (auto& gp : plan->groups)
         if (int e = synthesis_pass(*gp, alm, maps, nullptr, workspace, s)) return e;
@@ -1210,8 +1251,8 @@ int hp2sph_schedules(hp2sph_plan_t plan, int32_t* out, int32_t cap, int32_t* cou
     return HP2SPH_OK;
 }
 
-int hp2sph_autotune(hp2sph_plan_t plan, const double* maps, double* alm, void* workspace, void* stream,
-                    int32_t reps, double* best_ms) {
+int hp2sph_autotune(hp2sph_plan_t plan, const double* maps, double* alm, void* workspace, size_t workspace_bytes,
+                    void* stream, int32_t reps, double* best_ms) {
     if (int e = check_plan(plan)) return e;
     if (reps < 1 || reps > HP2SPH_MAX_TUNE_REPS) return fail(HP2SPH_EINVAL, "reps out of range");
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -1233,11 +1274,11 @@ int hp2sph_autotune(hp2sph_plan_t plan, const double* maps, double* alm, void* w
         if (hipEventCreate(&ev[i]) != hipSuccess) return fail(HP2SPH_EDEVICE, "hipEventCreate failed");
     // fastest of reps analyses, after an untimed one
     auto timed = [&](double& ms) -> int {
-        if (int e = hp2sph_analyze(plan, maps, alm, workspace, stream)) return e;
+        if (int e = hp2sph_analyze(plan, maps, alm, workspace, workspace_bytes, stream)) return e;
         ms = 1e300;
         for (int r = 0; r < reps; ++r) {
             if (hipEventRecord(ev[0], s) != hipSuccess) return fail(HP2SPH_EDEVICE, "hipEventRecord failed");
-            if (int e = hp2sph_analyze(plan, maps, alm, workspace, stream)) return e;
+            if (int e = hp2sph_analyze(plan, maps, alm, workspace, workspace_bytes, stream)) return e;
             float f = 0.f;
             if (hipEventRecord(ev[1], s) != hipSuccess || hipEventSynchronize(ev[1]) != hipSuccess ||
                 hipEventElapsedTime(&f, ev[0], ev[1]) != hipSuccess)
@@ -1269,15 +1310,19 @@ int hp2sph_autotune(hp2sph_plan_t plan, const double* maps, double* alm, void* w
         }
     }
     // leave alm holding the analysis under the chosen schedules
-    if (int e = hp2sph_analyze(plan, maps, alm, workspace, stream)) return e;
+    if (int e = hp2sph_analyze(plan, maps, alm, workspace, workspace_bytes, stream)) return e;
     if (hipStreamSynchronize(s) != hipSuccess) return fail(HP2SPH_EDEVICE, "hipStreamSynchronize failed");
     if (best_ms) *best_ms = best;
     return HP2SPH_OK;
 }
 
 int hp2sph_plan_destroy(hp2sph_plan_t plan) {
-    if (int e = check_plan(plan)) return e;
-    plan->magic = 0;
+    if (!plan) return fail(HP2SPH_ESTATE, "plan handle is null");
+    {
+        std::lock_guard<std::mutex> lk(g_plans_mu);
+        if (live_plans().erase(plan) == 0)
+            return fail(HP2SPH_ESTATE, "not a live plan handle (never created, or destroyed)");
+    }
     delete plan;
     return HP2SPH_OK;
 }

@@ -46,11 +46,20 @@ def test_error_paths_without_gpu():
     assert lib.hp2sph_plan_create(two, lm, 1, 0, None) == -1
     ws = ctypes.c_size_t()
     assert lib.hp2sph_workspace_size(None, ctypes.byref(ws)) == -5
-    assert lib.hp2sph_analyze(None, None, None, None, None) == -5
-    assert lib.hp2sph_synthesize(None, None, None, None, None) == -5
+    assert lib.hp2sph_analyze(None, None, None, None, 0, None) == -5
+    assert lib.hp2sph_synthesize(None, None, None, None, 0, None) == -5
     assert lib.hp2sph_power_spectrum(None, None, None, None) == -5
     assert lib.hp2sph_plan_destroy(None) == -5
-    assert lib.hp2sph_analyze_iterative(None, None, None, 3, None, None) == -5
+    assert lib.hp2sph_analyze_iterative(None, None, None, 3, None, 0, None) == -5
+    # a handle that was never created is looked up among the live plans and
+    # refused without being read through (here: the address of a host buffer)
+    fake = ctypes.create_string_buffer(4096)
+    fh = ctypes.cast(fake, ctypes.c_void_p)
+    assert lib.hp2sph_plan_destroy(fh) == -5
+    assert b"live plan" in lib.hp2sph_last_error()
+    assert lib.hp2sph_workspace_size(fh, ctypes.byref(ws)) == -5
+    assert lib.hp2sph_analyze(fh, None, None, None, 0, None) == -5
+    assert fake.raw == bytes(4096)
     st = ctypes.c_int32()
     assert lib.hp2sph_plan_strategy(None, ctypes.byref(st)) == -5
     assert lib.hp2sph_profile(None, 1) == -5
