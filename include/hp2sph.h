@@ -306,6 +306,24 @@ int hp2sph_schedule_map(int32_t sched, const int32_t* M, const int32_t* N, const
                         int32_t* out, int64_t capacity, int64_t* count);
 
 /*
+ * Host-only check of the grouped GEMMs' memory accesses (no GPU needed; used
+ * by tests).  Builds the GEMM problem lists a plan of `nmaps` maps of one
+ * `nside` with `mode` and `strategy` (STAGED or TABLES) would launch, over
+ * stand-in table addresses of the sizes the plan allocates, and checks them:
+ * every problem's A rows inside its table, B and C inside their workspace
+ * regions, and a replay of the kernel's staging addresses (the same offset
+ * functions the kernel runs) for every tile of every problem -- each element
+ * inside the problem must be read through an offset below its k step's
+ * descriptor size and inside the allocation, each element outside it must get
+ * an offset the descriptor range check turns into zero.  Writes the number
+ * of checks to *checked, of failures to *violations (the first one described
+ * in hp2sph_last_error()) and of vector reads of the zero row padding of the
+ * per-order tables to *padding.  Errors: EINVAL, ENOMEM.
+ */
+int hp2sph_gemm_check(int32_t nside, int32_t nmaps, int32_t mode, int32_t strategy,
+                      int64_t* checked, int64_t* violations, int64_t* padding);
+
+/*
  * Host-only inspection of the set-up tables (no GPU needed; used by tests).
  * Writes up to `capacity` doubles of table `table` for `nside` into `out`
  * and the full element count into *count (out may be NULL to query the

@@ -29,6 +29,16 @@ if not os.path.exists(LIB_PATH):
         "libhp2sph.so is not built; run `python paper_1904_10514_amd/build.py` "
         "(hipcc, gfx950) before importing paper_1904_10514_amd")
 
+# PyTorch ships its own HIP runtime (libamdhip64.so.7, the soname of the
+# system one the library links against).  Whichever is loaded first serves the
+# whole process, and the library must share the runtime instance that owns the
+# tensors and streams it is given: so torch, and with it its runtime, is
+# loaded before the library.
+try:
+    import torch as _torch_rt   # noqa: F401
+except ImportError:
+    pass
+
 _lib = ctypes.CDLL(LIB_PATH)
 
 HP2SPH_F64, HP2SPH_F32_REFINE, HP2SPH_F32, HP2SPH_EQUAL_WEIGHT = 0, 1, 2, 3
@@ -44,7 +54,7 @@ EXPORTED = [
     "hp2sph_power_spectrum", "hp2sph_plan_destroy", "hp2sph_last_error", "hp2sph_host_table",
     "hp2sph_profile", "hp2sph_profile_read", "hp2sph_plan_create_ex", "hp2sph_plan_strategy",
     "hp2sph_analyze_iterative", "hp2sph_set_schedule", "hp2sph_autotune", "hp2sph_schedules",
-    "hp2sph_schedule_map",
+    "hp2sph_schedule_map", "hp2sph_gemm_check",
 ]
 STRATEGIES = {"auto": 0, "staged": 1, "tables": 2}
 SCHEDULES = ["xcd_round_robin", "xcd_balanced", "linear", "linear_rows"]
@@ -75,6 +85,7 @@ _lib.hp2sph_autotune.argtypes = [_vp, _vp, _vp, _vp, _sz, _vp, _i32, ctypes.POIN
 _lib.hp2sph_schedules.argtypes = [_vp, ctypes.POINTER(_i32), _i32, ctypes.POINTER(_i32)]
 _lib.hp2sph_schedule_map.argtypes = [_i32, _vp, _vp, _vp, _i32, _vp, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
 _lib.hp2sph_host_table.argtypes = [_i32, _i32, _i32, _vp, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
+_lib.hp2sph_gemm_check.argtypes = [_i32, _i32, _i32, _i32] + [ctypes.POINTER(ctypes.c_int64)] * 3
 for _f in EXPORTED:
     if _f not in ("hp2sph_last_error",):
         getattr(_lib, _f).restype = ctypes.c_int

@@ -10,6 +10,7 @@
 #include <new>
 #include <stdexcept>
 #include <string>
+#include <type_traits>
 #include <unordered_set>
 #include <vector>
 
@@ -116,8 +117,8 @@ struct Group {
     bool tables = false;
     // device GEMM problem lists
     GemmList<double> ana64, syn64, syn64_staged;
-    GemmList<float> ana32;
-    GemmList<float> ana32_b64;   // FP32 analysis reading FP64 Dsym (first pass of the refinement)
+    GemmList<float> ana32;       // FP32 analysis of FP32 Dsym (second pass of the refinement)
+    GemmList<float> ana32_b64;   // FP32 analysis reading FP64 Dsym (single FP32 pass, first pass of the refinement)
     GemmList<double> adj64;      // equal-weight analysis: transposed evaluation (adjoint of the synthesis GEMM)
 };
 
@@ -126,7 +127,7 @@ const GemmList<T>& gemm_list(const Group& G);
 template <>
 const GemmList<double>& gemm_list<double>(const Group& G) { return G.ana64; }
 template <>
-const GemmList<float>& gemm_list<float>(const Group& G) { return G.ana32; }
+const GemmList<float>& gemm_list<float>(const Group& G) { return G.ana32_b64; }
 
 }  // namespace
 }  // namespace hp2sph
@@ -260,6 +261,19 @@ void init_dims(Group& G) {
     d.N[0] = int64_t(d.nmaps) * d.Npm[0];
     d.N[1] = int64_t(d.nmaps) * d.Npm[1];
     set_layout(d, false);
+    // workspace sizes (FP64 elements; FP32 stages alias the same bytes)
+    const int K = 2 * G.nside + 1;
+    G.bytes_D = 0;
+    G.bytes_U = 0;
+    for (int b = 0; b < 4; ++b) {
+        const int kpar = b >> 1;
+        G.rows_D[b] = K;
+        G.rows_U[b] = d.nl[b];
+        G.blk_off_D[b] = G.bytes_D;
+        G.blk_off_U[b] = G.bytes_U;
+        G.bytes_D += align_up(size_t(K) * d.N[kpar] * sizeof(double));
+        G.bytes_U += align_up(size_t(d.nl[b]) * d.N[kpar] * sizeof(double));
+    }
 }
 
 void build_group(hp2sph_plan_t plan, Group& G) {
@@ -307,7 +321,6 @@ void build_group(hp2sph_plan_t plan, Group& G) {
         }
     }
     fill_fft(G.t64, h, G.owned);
-    if (need32) fill_fft(G.t32, h, G.owned);
 
     // per-member offsets
     std::vector<int64_t> mo, ao, co;
@@ -330,19 +343,6 @@ void build_group(hp2sph_plan_t plan, Group& G) {
         G.d_pack_tiles = upload_int(G.owned, pt);
     }
 
-    // workspace sizes (FP64 elements; FP32 stages alias the same bytes)
-    const int K = 2 * G.nside + 1;
-    G.bytes_D = 0;
-    G.bytes_U = 0;
-    for (int b = 0; b < 4; ++b) {
-        const int kpar = b >> 1;
-        G.rows_D[b] = K;
-        G.rows_U[b] = d.nl[b];
-        G.blk_off_D[b] = G.bytes_D;
-        G.blk_off_U[b] = G.bytes_U;
-        G.bytes_D += align_up(size_t(K) * d.N[kpar] * sizeof(double));
-        G.bytes_U += align_up(size_t(d.nl[b]) * d.N[kpar] * sizeof(double));
-    }
 }
 
 template <class T>
@@ -429,8 +429,26 @@ std::vector<int32_t> schedule_map(const std::vector<GemmProblem<T>>& v, int tota
     return out;
 }
 
+// A device allocation [lo, hi) that GEMM operands must stay inside.
+struct Extent {
+    uintptr_t lo = 0, hi = 0;
+};
+
+// Result of checking a problem list against the allocations its launches use.
+struct ListCheck {
+    int64_t checked = 0;      // addresses and offsets checked
+    int64_t violations = 0;   // of which out of their allocation or descriptor
+    int64_t padding = 0;      // in-range A reads of the zero row padding (vector loads past M)
+    std::string first;        // the first violation, described
+    void bad(const std::string& what) {
+        if (violations++ == 0) first = what;
+    }
+};
+
+// Validation, longest-first order and tile ranges of a problem list (the
+// order the launches and the schedule maps use).
 template <class T>
-void upload_list(Group& G, std::vector<GemmProblem<T>>& v, GemmList<T>& out) {
+int prepare_list(std::vector<GemmProblem<T>>& v) {
     // the GEMM kernel reads B as aligned (re, im) pairs
     for (const auto& P : v)
         if ((P.boff | P.ldb | P.bps | P.N) & 1) throw std::runtime_error("GEMM problem with unpaired B columns");
@@ -439,11 +457,146 @@ void upload_list(Group& G, std::vector<GemmProblem<T>>& v, GemmList<T>& out) {
     for (const auto& P : v)
         if (P.lda >= (int64_t(1) << 24) || P.ldb >= (int64_t(1) << 24))
             throw std::runtime_error("GEMM row stride too large for the 32-bit offsets of the staging loads");
-    // longest problems first, then tile ranges in that order
     std::stable_sort(v.begin(), v.end(), [](const GemmProblem<T>& x, const GemmProblem<T>& y) {
         return int64_t(x.M) * x.K > int64_t(y.M) * y.K;
     });
-    out.tiles = finalize_gemm_problems<T>(v.data(), int(v.size()));
+    return finalize_gemm_problems<T>(v.data(), int(v.size()));
+}
+
+// Extents of every problem of a finalized list against its allocations:
+// A (absolute, a set-up table) must lie in one of `tables`; B and C are
+// offsets from the launch's base pointers into workspace regions of
+// b_bytes / c_bytes.  Cheap (per problem), run on every list a plan builds.
+template <class T, class TB>
+void check_extents(const std::vector<GemmProblem<T>>& v, const std::vector<Extent>& tables, size_t b_bytes,
+                   size_t c_bytes, ListCheck& out) {
+    for (size_t i = 0; i < v.size(); ++i) {
+        const GemmProblem<T>& P = v[i];
+        const std::string id = "problem " + std::to_string(i) + " (M " + std::to_string(P.M) + ", N " +
+                               std::to_string(P.N) + ", K " + std::to_string(P.K) + ")";
+        // A: rows 0 .. K-1 of lda elements, the last one read up to lda (vector
+        // loads) or M; every k step's descriptor ends at A + (k0 + rows) lda
+        const uintptr_t a0 = reinterpret_cast<uintptr_t>(P.A);
+        const uintptr_t a1 = a0 + uintptr_t(P.K) * uintptr_t(P.lda) * sizeof(T);
+        bool inside = false;
+        for (const Extent& e : tables) inside = inside || (a0 >= e.lo && a1 <= e.hi);
+        out.checked += 1;
+        if (!inside) out.bad(id + ": A rows outside every table allocation");
+        // B: element (k, n) at boff + k ldb + (n >> 1) bps + (n & 1) (none when K = 0)
+        const int64_t bmax = P.boff + int64_t(P.K - 1) * P.ldb + int64_t((P.N - 1) >> 1) * P.bps + 1;
+        out.checked += 1;
+        if (P.K > 0 && (P.boff < 0 || uint64_t(bmax + 1) * sizeof(TB) > b_bytes))
+            out.bad(id + ": B outside its workspace region");
+        // C: element (m, n) at coff + m ldc + (n >> 1) cps + (n & 1)
+        const int64_t cmax = P.coff + int64_t(P.M - 1) * P.ldc + int64_t((P.N - 1) >> 1) * P.cps + 1;
+        out.checked += 1;
+        if (P.coff < 0 || uint64_t(cmax + 1) * sizeof(T) > c_bytes) out.bad(id + ": C outside its workspace region");
+        // descriptor sizes stay below 2^31 (the out-of-range offset is 2^31)
+        out.checked += 1;
+        if (int64_t(kGemmBK) * P.lda * int64_t(sizeof(T)) >= (int64_t(1) << 31) ||
+            int64_t(kGemmBK) * P.ldb * int64_t(sizeof(TB)) >= (int64_t(1) << 31))
+            out.bad(id + ": descriptor records reach 2^31");
+    }
+}
+
+// Replay of the GEMM kernel's staging addresses (gemm_a_offset /
+// gemm_b_offset, the functions the kernel calls) for every tile of every
+// problem: each element inside the problem must get an offset below its k
+// step's descriptor records whose address lies in the operand's allocation,
+// and each element outside (columns past M or N, rows past K) an offset at or
+// past the records, so that the hardware returns zero without reading memory.
+// Offsets do not depend on the k step except through its row count, so each
+// tile is replayed for a full step (16 rows) and for the last step; every
+// step's descriptor range is checked against the allocation.
+template <class T, class TB>
+void replay_list(const std::vector<GemmProblem<T>>& v, const std::vector<Extent>& tables, size_t b_bytes,
+                 ListCheck& out) {
+    constexpr int VE = GemmStage<T>::VE;
+    for (size_t i = 0; i < v.size(); ++i) {
+        const GemmProblem<T>& P = v[i];
+        const std::string id = "problem " + std::to_string(i);
+        const uintptr_t a0 = reinterpret_cast<uintptr_t>(P.A);
+        Extent ta{};
+        for (const Extent& e : tables)
+            if (a0 >= e.lo && a0 < e.hi) ta = e;
+        const bool avec = gemm_a_vector(P);
+        const int nk = (P.K + kGemmBK - 1) / kGemmBK;
+        // every k step's descriptors inside the allocations
+        for (int s = 0; s < nk; ++s) {
+            const int k0 = s * kGemmBK;
+            const uintptr_t abase = a0 + uintptr_t(k0) * uintptr_t(P.lda) * sizeof(T);
+            const uint64_t bbase = (uint64_t(P.boff) + uint64_t(k0) * uint64_t(P.ldb)) * sizeof(TB);
+            out.checked += 2;
+            if (abase < ta.lo || abase + gemm_a_records(P, k0) > ta.hi)
+                out.bad(id + " (M " + std::to_string(P.M) + ", K " + std::to_string(P.K) + ", lda " +
+                        std::to_string(P.lda) + ", k0 " + std::to_string(k0) + "): A descriptor [" +
+                        std::to_string(abase - ta.lo) + ", +" + std::to_string(gemm_a_records(P, k0)) +
+                        ") outside the table of " + std::to_string(ta.hi - ta.lo) + " bytes");
+            if (bbase + gemm_b_records<T, TB>(P, k0) > b_bytes)
+                out.bad(id + ": B descriptor outside the workspace region");
+        }
+        const int tiles_m = (P.M + kGemmBM - 1) / kGemmBM;
+        // a full step (if any) and the last; the kernel stages step 0 even
+        // when K = 0 (no rows: every element must fall outside)
+        int steps[2] = {0, nk > 0 ? (nk - 1) * kGemmBK : 0};
+        const int nsteps = nk > 1 ? 2 : 1;
+        for (int tm = 0; tm < tiles_m; ++tm)
+            for (int tn = 0; tn < P.tiles_n; ++tn)
+                for (int si = 0; si < nsteps; ++si) {
+                    const int k0 = nsteps == 2 ? steps[si] : 0;
+                    const int rows = gemm_step_rows(P, k0);
+                    const uint32_t ra = gemm_a_records(P, k0), rb = gemm_b_records<T, TB>(P, k0);
+                    const uintptr_t abase = a0 + uintptr_t(k0) * uintptr_t(P.lda) * sizeof(T);
+                    const uint64_t bbase = (uint64_t(P.boff) + uint64_t(k0) * uint64_t(P.ldb)) * sizeof(TB);
+                    const int m0 = tm * kGemmBM, n0 = tn * kGemmBN;
+                    for (int tid = 0; tid < kGemmThreads; ++tid) {
+                        const int lr = GemmStage<T>::row(tid);
+                        for (int e = 0; e < 8; e += (avec ? VE : 1)) {
+                            const int mm = m0 + GemmStage<T>::col(tid, e);
+                            const int width = avec ? VE : 1;
+                            const bool live = lr < rows && mm < P.M;   // some element of the load is in the problem
+                            const uint32_t off = gemm_a_offset(P, avec, m0, tid, e);
+                            out.checked += 1;
+                            if (live) {
+                                if (off == kGemmOOB || uint64_t(off) + width * sizeof(T) > ra ||
+                                    abase + off + width * sizeof(T) > ta.hi)
+                                    out.bad(id + ": A element inside the problem not read");
+                                else if (mm + width > P.M)
+                                    out.padding += 1;
+                            } else if (off < ra && lr >= rows) {
+                                out.bad(id + ": A row past K inside the descriptor");
+                            } else if (off < ra) {
+                                // columns past M inside the descriptor: only the
+                                // zero padding of a vector-read row (mm < lda)
+                                if (!(avec && mm < P.lda)) out.bad(id + ": A column past M read from memory");
+                                else out.padding += 1;
+                            }
+                        }
+                        for (int e = 0; e < 8; e += 2) {
+                            const int nn = n0 + GemmStage<T>::col(tid, e);
+                            const bool live = lr < rows && nn < P.N;
+                            const uint32_t off = gemm_b_offset<T, TB>(P, n0, tid, e);
+                            out.checked += 1;
+                            if (live) {
+                                if (off == kGemmOOB || uint64_t(off) + 2 * sizeof(TB) > rb ||
+                                    bbase + off + 2 * sizeof(TB) > b_bytes)
+                                    out.bad(id + ": B pair inside the problem not read");
+                            } else if (off < rb) {
+                                out.bad(id + " (N " + std::to_string(P.N) + ", K " + std::to_string(P.K) + ", ldb " +
+                                        std::to_string(P.ldb) + ", bps " + std::to_string(P.bps) + ", tile n0 " +
+                                        std::to_string(n0) + ", k0 " + std::to_string(k0) + ", tid " +
+                                        std::to_string(tid) + ", e " + std::to_string(e) +
+                                        "): B element outside the problem inside the descriptor");
+                            }
+                        }
+                    }
+                }
+    }
+}
+
+template <class T>
+void upload_list(Group& G, std::vector<GemmProblem<T>>& v, GemmList<T>& out) {
+    out.tiles = prepare_list(v);
     out.n = int(v.size());
     out.dev = upload_int(G.owned, v);
     for (int c = 0; c < HP2SPH_NSCHED; ++c) {
@@ -459,15 +612,39 @@ void upload_list(Group& G, std::vector<GemmProblem<T>>& v, GemmList<T>& out) {
     out.use(v.size() < 2 * 8 ? HP2SPH_SCHED_LINEAR_ROWS : HP2SPH_SCHED_XCD_ROUND_ROBIN);
 }
 
+// Extents of a list that is about to be uploaded (throws on a violation).
+template <class T, class TB = T>
+void require_extents(const std::vector<GemmProblem<T>>& v, const std::vector<Extent>& tables, size_t b_bytes,
+                     size_t c_bytes) {
+    ListCheck c;
+    check_extents<T, TB>(v, tables, b_bytes, c_bytes, c);
+    if (c.violations) throw std::runtime_error("GEMM problem list out of bounds: " + c.first);
+}
+
+// Extent of a device buffer
+Extent extent_of(const void* p, size_t bytes) {
+    Extent e;
+    e.lo = reinterpret_cast<uintptr_t>(p);
+    e.hi = e.lo + bytes;
+    return e;
+}
+
+// The set-up tables a staged group's GEMMs read, per block.
+struct StagedBases {
+    const void* ana[4] = {};        // analysis matrices [h][l'] (T)
+    const double* syn[4] = {};      // synthesis matrices [l'][h]
+    const double* synT[4] = {};     // their transposes [h][l'] (equal weight)
+};
+
 // TB: storage type of the Dsym rows the GEMM reads (B offsets in TB elements)
 template <class T, class TB = T>
-void staged_analysis_list(Group& G, const DevTables<T>& t, GemmList<T>& out) {
+std::vector<GemmProblem<T>> staged_analysis_problems(const Group& G, const StagedBases& t) {
     const GroupDims& d = G.dims;
     std::vector<GemmProblem<T>> v;
     for (int b = 0; b < 4; ++b) {
         const int kpar = b >> 1;
         GemmProblem<T> P{};
-        P.A = t.ana[b];
+        P.A = static_cast<const T*>(t.ana[b]);
         P.M = d.nl[b];
         P.N = int(d.N[kpar]);
         P.K = 2 * G.nside + 1;
@@ -480,16 +657,16 @@ void staged_analysis_list(Group& G, const DevTables<T>& t, GemmList<T>& out) {
         P.cps = 2;
         v.push_back(P);
     }
-    upload_list(G, v, out);
+    return v;
 }
 
-void staged_synthesis_list(Group& G, GemmList<double>& out) {
+std::vector<GemmProblem<double>> staged_synthesis_problems(const Group& G, const StagedBases& t) {
     const GroupDims& d = G.dims;
     std::vector<GemmProblem<double>> v;
     for (int b = 0; b < 4; ++b) {
         const int kpar = b >> 1;
         GemmProblem<double> P{};
-        P.A = G.syn[b];
+        P.A = t.syn[b];
         P.M = 2 * G.nside + 1;
         P.N = int(d.N[kpar]);
         P.K = d.nl[b];
@@ -502,20 +679,20 @@ void staged_synthesis_list(Group& G, GemmList<double>& out) {
         P.cps = 2;
         v.push_back(P);
     }
-    upload_list(G, v, out);
+    return v;
 }
 
 // Equal-weight analysis, staged: per block, the transposed evaluation matrix
 // (rows h = 1 .. 2 nside, the rings; the pole row carries no pixel) applied to
 // the weighted longitude sums, then the analysis sweeps (the transpose of the
 // synthesis sweeps: the rotations are orthogonal).
-void staged_adjoint_list(Group& G, GemmList<double>& out) {
+std::vector<GemmProblem<double>> staged_adjoint_problems(const Group& G, const StagedBases& t) {
     const GroupDims& d = G.dims;
     std::vector<GemmProblem<double>> v;
     for (int b = 0; b < 4; ++b) {
         const int kpar = b >> 1;
         GemmProblem<double> P{};
-        P.A = G.synT[b] + d.nl[b];   // row h = 1
+        P.A = t.synT[b] + d.nl[b];   // row h = 1
         P.M = d.nl[b];
         P.N = int(d.N[kpar]);
         P.K = 2 * G.nside;
@@ -528,7 +705,7 @@ void staged_adjoint_list(Group& G, GemmList<double>& out) {
         P.cps = 2;
         v.push_back(P);
     }
-    upload_list(G, v, out);
+    return v;
 }
 
 // Element offsets and sizes of the per-order tables of one block.
@@ -569,6 +746,107 @@ size_t order_table_bytes(const Group& G, int mode) {
     return ana * 4 + syn * 8;
 }
 
+// Per-order tables of one group, per block (null where the mode has none).
+struct OrderBases {
+    const double* ana64[4] = {};
+    const float* ana32[4] = {};
+    const double* syn64[4] = {};
+    const double* adj64[4] = {};
+};
+
+// The grouped GEMM problems of the per-order tables: one per (block, order).
+struct OrderLists {
+    std::vector<GemmProblem<double>> ana64, syn64, adj64;
+    std::vector<GemmProblem<float>> ana32, ana32_b64;   // FP32 analysis of FP32 / FP64 ring coefficients
+};
+
+OrderLists order_problems(const Group& G, int mode, const OrderBases& t) {
+    const GroupDims& d = G.dims;
+    const int K = 2 * G.nside + 1;
+    OrderLists out;
+    for (int b = 0; b < 4; ++b) {
+        const int kpar = b >> 1;
+        OrderLayout L = order_layout(G, b);
+        for (int kk = 0; kk < d.nk[b]; ++kk) {
+            // order m = p in the block whose degrees have the other parity has
+            // no l: no analysis or adjoint output (no problem), while its
+            // synthesis problem (K = 0) writes the zeros the ring rows need
+            const bool live = d.nl[b] - kk > 0;
+            const int h0 = L.h0[kk];
+            // mode-major layout: mode k' of every map is one contiguous run of 2 nmaps
+            const int64_t kcol = int64_t(kk) * 2 * d.nmaps;
+            if (live && (t.ana64[b] || t.ana32[b])) {
+                GemmProblem<double> P{};
+                P.M = d.nl[b] - kk;
+                P.K = K - h0;
+                P.N = 2 * d.nmaps;
+                P.lda = order_table_lda(P.M);
+                P.ldb = d.N[kpar];
+                P.bps = 2;
+                P.ldc = d.N[kpar];
+                P.cps = 2;
+                if (mode == HP2SPH_F64) {
+                    P.A = t.ana64[b] + L.ana_off[kk];
+                    P.boff = int64_t(G.blk_off_D[b] / 8) + int64_t(h0) * d.N[kpar] + kcol;
+                    P.coff = int64_t(G.blk_off_U[b] / 8) + int64_t(kk) * d.N[kpar] + kcol;
+                    out.ana64.push_back(P);
+                } else {
+                    GemmProblem<float> Q{};
+                    Q.A = t.ana32[b] + L.ana_off[kk];
+                    Q.M = P.M;
+                    Q.K = P.K;
+                    Q.N = P.N;
+                    Q.lda = P.lda;
+                    Q.ldb = P.ldb;
+                    Q.bps = P.bps;
+                    Q.ldc = P.ldc;
+                    Q.cps = P.cps;
+                    Q.coff = int64_t(G.blk_off_U[b] / 4) + int64_t(kk) * d.N[kpar] + kcol;
+                    if (mode == HP2SPH_F32_REFINE) {
+                        Q.boff = int64_t(G.blk_off_D[b] / 4) + int64_t(h0) * d.N[kpar] + kcol;
+                        out.ana32.push_back(Q);
+                    }
+                    Q.boff = int64_t(G.blk_off_D[b] / 8) + int64_t(h0) * d.N[kpar] + kcol;
+                    out.ana32_b64.push_back(Q);
+                }
+            }
+            if (t.syn64[b]) {
+                GemmProblem<double> S{};
+                S.A = t.syn64[b] + L.syn_off[kk];
+                S.M = 2 * G.nside;
+                S.K = d.nl[b] - kk;
+                S.N = 2 * d.nmaps;
+                S.lda = 2 * G.nside;
+                S.boff = int64_t(G.blk_off_U[b] / 8) + int64_t(kk) * d.N[kpar] + kcol;
+                S.ldb = d.N[kpar];
+                S.bps = 2;
+                S.coff = int64_t(G.blk_off_D[b] / 8) + int64_t(1) * d.N[kpar] + kcol;
+                S.ldc = d.N[kpar];
+                S.cps = 2;
+                out.syn64.push_back(S);
+            }
+            if (live && t.adj64[b]) {
+                // a_l^m = sum_h Tsyn[l][h] W[h]: the transposed synthesis table
+                // over the ring rows h = 1 .. 2 nside
+                GemmProblem<double> Q{};
+                Q.A = t.adj64[b] + L.adj_off[kk];
+                Q.M = d.nl[b] - kk;
+                Q.K = 2 * G.nside;
+                Q.N = 2 * d.nmaps;
+                Q.lda = order_table_lda(Q.M);
+                Q.boff = int64_t(G.blk_off_D[b] / 8) + int64_t(1) * d.N[kpar] + kcol;
+                Q.ldb = d.N[kpar];
+                Q.bps = 2;
+                Q.coff = int64_t(G.blk_off_U[b] / 8) + int64_t(kk) * d.N[kpar] + kcol;
+                Q.ldc = d.N[kpar];
+                Q.cps = 2;
+                out.adj64.push_back(Q);
+            }
+        }
+    }
+    return out;
+}
+
 #define HIPTHROW(expr)                                                                        \
     do {                                                                                      \
         hipError_t e_ = (expr);                                                               \
@@ -588,8 +866,8 @@ void build_order_tables(hp2sph_plan_t plan, Group& G) {
     const bool want_ana = (plan->mode != HP2SPH_EQUAL_WEIGHT);
     const bool want_syn = (plan->mode == HP2SPH_F32_REFINE || plan->mode == HP2SPH_EQUAL_WEIGHT);
     const bool want_adj = (plan->mode == HP2SPH_EQUAL_WEIGHT);
-    std::vector<GemmProblem<double>> la64, ls64, lj64;
-    std::vector<GemmProblem<float>> la32, la32b;
+    OrderBases bases;
+    std::vector<Extent> extents;
     // temporary buffer for the virtual batch (chains replicated over k')
     size_t per_v = 0;
     for (int b = 0; b < 4; ++b) per_v = std::max(per_v, size_t(d.nl[b]) * 2 * d.nk[b] * sizeof(double));
@@ -660,99 +938,88 @@ void build_order_tables(hp2sph_plan_t plan, Group& G) {
                                              2 * G.nside, nullptr));
             HIPTHROW(hipDeviceSynchronize());
         }
-        // problem lists of this block
-        const double* tana64 = want_ana ? static_cast<const double*>(ana64->p) : nullptr;
-        float* tana32 = nullptr;
         if (want_ana && plan->mode != HP2SPH_F64) {
+            // FP32 copy of the analysis tables (zero padding included)
             auto a32 = std::make_unique<DevBuf>();
             a32->bytes = size_t(L.ana_size) * 4;
             HIPTHROW(hipMalloc(&a32->p, a32->bytes));
-            HIPTHROW(launch_convert(tana64, static_cast<float*>(a32->p), L.ana_size, nullptr));
+            HIPTHROW(launch_convert(static_cast<const double*>(ana64->p), static_cast<float*>(a32->p), L.ana_size,
+                                    nullptr));
             HIPTHROW(hipDeviceSynchronize());
-            tana32 = static_cast<float*>(a32->p);
+            bases.ana32[b] = static_cast<const float*>(a32->p);
+            extents.push_back(extent_of(a32->p, a32->bytes));
             G.owned.push_back(std::move(a32));
+        } else if (want_ana) {
+            bases.ana64[b] = static_cast<const double*>(ana64->p);
+            extents.push_back(extent_of(ana64->p, ana64->bytes));
+            G.owned.push_back(std::move(ana64));
         }
-        for (int kk = 0; kk < d.nk[b]; ++kk) {
-            const int h0 = L.h0[kk];
-            GemmProblem<double> P{};
-            P.M = d.nl[b] - kk;
-            P.K = K - h0;
-            P.N = 2 * d.nmaps;
-            // mode-major layout: mode k' of every map is one contiguous run of 2 nmaps
-            const int64_t kcol = int64_t(kk) * 2 * d.nmaps;
-            P.lda = order_table_lda(P.M);
-            P.ldb = d.N[kpar];
-            P.bps = 2;
-            P.ldc = d.N[kpar];
-            P.cps = 2;
-            if (!want_ana) {
-                // no HP2SPH analysis tables in an equal-weight plan
-            } else if (plan->mode == HP2SPH_F64) {
-                P.A = tana64 + L.ana_off[kk];
-                P.boff = int64_t(G.blk_off_D[b] / 8) + int64_t(h0) * d.N[kpar] + kcol;
-                P.coff = int64_t(G.blk_off_U[b] / 8) + int64_t(kk) * d.N[kpar] + kcol;
-                la64.push_back(P);
-            } else {
-                GemmProblem<float> Q{};
-                Q.A = tana32 + L.ana_off[kk];
-                Q.M = P.M;
-                Q.K = P.K;
-                Q.N = P.N;
-                Q.lda = P.lda;
-                Q.ldb = P.ldb;
-                Q.bps = P.bps;
-                Q.ldc = P.ldc;
-                Q.cps = P.cps;
-                Q.boff = int64_t(G.blk_off_D[b] / 4) + int64_t(h0) * d.N[kpar] + kcol;
-                Q.coff = int64_t(G.blk_off_U[b] / 4) + int64_t(kk) * d.N[kpar] + kcol;
-                la32.push_back(Q);
-                Q.boff = int64_t(G.blk_off_D[b] / 8) + int64_t(h0) * d.N[kpar] + kcol;
-                la32b.push_back(Q);
-            }
-            if (want_syn) {
-                GemmProblem<double> S{};
-                S.A = static_cast<const double*>(syn64->p) + L.syn_off[kk];
-                S.M = 2 * G.nside;
-                S.K = d.nl[b] - kk;
-                S.N = 2 * d.nmaps;
-                S.lda = 2 * G.nside;
-                S.boff = int64_t(G.blk_off_U[b] / 8) + int64_t(kk) * d.N[kpar] + kcol;
-                S.ldb = d.N[kpar];
-                S.bps = 2;
-                S.coff = int64_t(G.blk_off_D[b] / 8) + int64_t(1) * d.N[kpar] + kcol;
-                S.ldc = d.N[kpar];
-                S.cps = 2;
-                ls64.push_back(S);
-            }
-            if (want_adj) {
-                // a_l^m = sum_h Tsyn[l][h] W[h]: the transposed synthesis table
-                // over the ring rows h = 1 .. 2 nside
-                GemmProblem<double> Q{};
-                Q.A = static_cast<const double*>(adj64->p) + L.adj_off[kk];
-                Q.M = d.nl[b] - kk;
-                Q.K = 2 * G.nside;
-                Q.N = 2 * d.nmaps;
-                Q.lda = order_table_lda(Q.M);
-                Q.boff = int64_t(G.blk_off_D[b] / 8) + int64_t(1) * d.N[kpar] + kcol;
-                Q.ldb = d.N[kpar];
-                Q.bps = 2;
-                Q.coff = int64_t(G.blk_off_U[b] / 8) + int64_t(kk) * d.N[kpar] + kcol;
-                Q.ldc = d.N[kpar];
-                Q.cps = 2;
-                lj64.push_back(Q);
-            }
+        if (want_syn) {
+            bases.syn64[b] = static_cast<const double*>(syn64->p);
+            extents.push_back(extent_of(syn64->p, syn64->bytes));
+            G.owned.push_back(std::move(syn64));
         }
-        if (want_ana && plan->mode == HP2SPH_F64) G.owned.push_back(std::move(ana64));
-        if (want_syn) G.owned.push_back(std::move(syn64));
-        if (want_adj) G.owned.push_back(std::move(adj64));
+        if (want_adj) {
+            bases.adj64[b] = static_cast<const double*>(adj64->p);
+            extents.push_back(extent_of(adj64->p, adj64->bytes));
+            G.owned.push_back(std::move(adj64));
+        }
     }
-    if (want_ana) {
-        if (plan->mode == HP2SPH_F64) upload_list(G, la64, G.ana64);
-        else upload_list(G, la32, G.ana32);
+    OrderLists ol = order_problems(G, plan->mode, bases);
+    // every problem inside its table and its workspace regions (see the
+    // launches: analysis D -> U, synthesis U -> D, adjoint D -> U)
+    require_extents<double>(ol.ana64, extents, G.bytes_D, G.bytes_U);
+    require_extents<float>(ol.ana32, extents, G.bytes_D, G.bytes_U);
+    require_extents<float, double>(ol.ana32_b64, extents, G.bytes_D, G.bytes_U);
+    require_extents<double>(ol.syn64, extents, G.bytes_U, G.bytes_D);
+    require_extents<double>(ol.adj64, extents, G.bytes_D, G.bytes_U);
+    if (!ol.ana64.empty()) upload_list(G, ol.ana64, G.ana64);
+    if (!ol.ana32.empty()) upload_list(G, ol.ana32, G.ana32);
+    if (!ol.ana32_b64.empty()) upload_list(G, ol.ana32_b64, G.ana32_b64);
+    if (!ol.syn64.empty()) upload_list(G, ol.syn64, G.syn64);
+    if (!ol.adj64.empty()) upload_list(G, ol.adj64, G.adj64);
+}
+
+// Staged lists of one group from its device tables (extents checked, then
+// uploaded).
+void build_staged_lists(hp2sph_plan_t plan, Group& G) {
+    const GroupDims& d = G.dims;
+    const int K = 2 * G.nside + 1;
+    StagedBases t64, t32;
+    std::vector<Extent> ext;
+    for (int b = 0; b < 4; ++b) {
+        t64.ana[b] = G.t64.ana[b];
+        t32.ana[b] = G.t32.ana[b];
+        t64.syn[b] = G.syn[b];
+        t64.synT[b] = G.synT[b];
+        const size_t n = size_t(K) * d.nl[b];
+        if (G.t64.ana[b]) ext.push_back(extent_of(G.t64.ana[b], n * 8));
+        if (G.t32.ana[b]) ext.push_back(extent_of(G.t32.ana[b], n * 4));
+        if (G.syn[b]) ext.push_back(extent_of(G.syn[b], n * 8));
+        if (G.synT[b]) ext.push_back(extent_of(G.synT[b], n * 8));
     }
-    if (plan->mode == HP2SPH_F32_REFINE) upload_list(G, la32b, G.ana32_b64);
-    if (want_syn) upload_list(G, ls64, G.syn64);
-    if (want_adj) upload_list(G, lj64, G.adj64);
+    auto syn = staged_synthesis_problems(G, t64);
+    require_extents<double>(syn, ext, G.bytes_U, G.bytes_D);
+    upload_list(G, syn, G.syn64_staged);
+    if (G.tables) return;
+    if (plan->mode == HP2SPH_EQUAL_WEIGHT) {
+        auto v = staged_adjoint_problems(G, t64);
+        require_extents<double>(v, ext, G.bytes_D, G.bytes_U);
+        upload_list(G, v, G.adj64);
+    } else if (plan->mode == HP2SPH_F64) {
+        auto v = staged_analysis_problems<double>(G, t64);
+        require_extents<double>(v, ext, G.bytes_D, G.bytes_U);
+        upload_list(G, v, G.ana64);
+    } else {
+        if (plan->mode == HP2SPH_F32_REFINE) {
+            auto v = staged_analysis_problems<float>(G, t32);
+            require_extents<float>(v, ext, G.bytes_D, G.bytes_U);
+            upload_list(G, v, G.ana32);
+        }
+        auto w = staged_analysis_problems<float, double>(G, t32);
+        require_extents<float, double>(w, ext, G.bytes_D, G.bytes_U);
+        upload_list(G, w, G.ana32_b64);
+    }
 }
 
 // Launch `expr` as stage `st`, bracketed by events when profiling is on.
@@ -785,16 +1052,19 @@ DevTables<double>& tabs<double>(Group& G) { return G.t64; }
 template <>
 DevTables<float>& tabs<float>(Group& G) { return G.t32; }
 
-// One analysis pass of one group in precision T: maps_in -> alm (write or add).
+// One analysis pass of one group, colatitude fit and conversion in precision
+// T: maps_in -> alm.  The ring transform and pole values are FP64 in both
+// precisions (for T = float this is the first pass of the refinement: the
+// GEMM rounds the FP64 ring coefficients to FP32 as it stages them).
 template <class T>
 int analysis_pass(Group& G, const double* maps_in, double* alm, void* ws, hipStream_t s) {
     DevTables<T>& t = tabs<T>(G);
-    Blocks4<T> D = blocks_at<T>(ws, G.off_D, G, G.rows_D);
+    Blocks4<double> D = blocks_at<double>(ws, G.off_D, G, G.rows_D);
     Blocks4<T> U = blocks_at<T>(ws, G.off_U, G, G.rows_U);
-    STAGE(0, launch_ring_forward<T>(maps_in, G.d_map_off, G.rings, t.fft, D, G.dims, s));
-    STAGE(1, launch_pole<T>(D, G.dims, G.pole_w[0], G.pole_w[1], G.pole_w[2], s));
+    STAGE(0, launch_ring_forward<double>(maps_in, G.d_map_off, G.rings, G.t64.fft, D, G.dims, s));
+    STAGE(1, launch_pole<double>(D, G.dims, G.pole_w[0], G.pole_w[1], G.pole_w[2], s));
     const GemmList<T>& gl = gemm_list<T>(G);
-    STAGE(2, launch_gemm<T>(gl.dev, gl.tmap, gl.slots, D.p[0], U.p[0], s));
+    STAGE(2, (launch_gemm<T, double>(gl.dev, gl.tmap, gl.slots, D.p[0], U.p[0], s)));
     Blocks4<const T> Gv;
     for (int b = 0; b < 4; ++b) Gv.p[b] = t.givens[b];
     if (!G.tables) STAGE(3, launch_sweep_fwd<T>(U, Gv, G.dims, s));
@@ -976,7 +1246,7 @@ void analysis_lists(const hp2sph_plan_s* plan, Group& G, std::vector<GemmSched*>
     GemmList<double>& syn = G.tables ? G.syn64 : G.syn64_staged;
     switch (plan->mode) {
         case HP2SPH_F64: add(G.ana64, G.ana64.n); break;
-        case HP2SPH_F32: add(G.ana32, G.ana32.n); break;
+        case HP2SPH_F32: add(G.ana32_b64, G.ana32_b64.n); break;
         case HP2SPH_F32_REFINE:
             add(G.ana32_b64, G.ana32_b64.n);
             add(syn, syn.n);
@@ -1075,17 +1345,8 @@ int hp2sph_plan_create_ex(const int32_t* nside, const int32_t* lmax, int32_t bat
             G->off_U = align_up(G->bytes_D);
             G->tables = tables;
             set_layout(G->dims, tables);
-            staged_synthesis_list(*G, G->syn64_staged);
-            if (tables) {
-                build_order_tables(plan.get(), *G);
-            } else if (mode == HP2SPH_EQUAL_WEIGHT) {
-                staged_adjoint_list(*G, G->adj64);
-            } else if (mode == HP2SPH_F64) {
-                staged_analysis_list<double>(*G, G->t64, G->ana64);
-            } else {
-                staged_analysis_list<float>(*G, G->t32, G->ana32);
-                if (mode == HP2SPH_F32_REFINE) staged_analysis_list<float, double>(*G, G->t32, G->ana32_b64);
-            }
+            build_staged_lists(plan.get(), *G);
+            if (tables) build_order_tables(plan.get(), *G);
             max_group = std::max(max_group, G->off_U + align_up(G->bytes_U));
             plan->groups.push_back(std::move(G));
         }
@@ -1350,6 +1611,86 @@ int hp2sph_schedule_map(int32_t sched, const int32_t* M, const int32_t* N, const
     *count = int64_t(map.size());
     if (capacity > 0)
         std::memcpy(out, map.data(), sizeof(int32_t) * size_t(std::min<int64_t>(capacity, int64_t(map.size()))));
+    return HP2SPH_OK;
+}
+
+int hp2sph_gemm_check(int32_t nside, int32_t nmaps, int32_t mode, int32_t strategy, int64_t* checked,
+                      int64_t* violations, int64_t* padding) {
+    if (!checked || !violations || !padding) return fail(HP2SPH_EINVAL, "null output");
+    if (nside < 2 || nside > HP2SPH_MAX_NSIDE || !is_pow2(nside)) return fail(HP2SPH_EINVAL, "bad nside");
+    if (nmaps < 1) return fail(HP2SPH_EINVAL, "nmaps must be positive");
+    if (mode < HP2SPH_F64 || mode > HP2SPH_EQUAL_WEIGHT) return fail(HP2SPH_EINVAL, "unknown precision mode");
+    if (strategy != HP2SPH_STRATEGY_STAGED && strategy != HP2SPH_STRATEGY_TABLES)
+        return fail(HP2SPH_EINVAL, "strategy must be staged or tables");
+    ListCheck c;
+    try {
+        Group G;
+        G.nside = nside;
+        for (int i = 0; i < nmaps; ++i) G.members.push_back(i);
+        init_dims(G);
+        const bool tables = strategy == HP2SPH_STRATEGY_TABLES;
+        G.tables = tables;
+        set_layout(G.dims, tables);
+        // stand-in addresses for the device tables: disjoint 256-byte aligned
+        // ranges of the sizes the plan allocates (nothing is dereferenced)
+        uintptr_t next = uintptr_t(1) << 40;
+        std::vector<Extent> ext;
+        auto place = [&](size_t bytes) {
+            Extent e = extent_of(reinterpret_cast<const void*>(next), bytes);
+            ext.push_back(e);
+            next += (bytes + 4095) / 4096 * 4096 + 4096;
+            return reinterpret_cast<const void*>(e.lo);
+        };
+        const int K = 2 * nside + 1;
+        auto run = [&](auto v, auto tb_tag, size_t b_bytes, size_t c_bytes) {
+            using T = std::remove_cv_t<std::remove_pointer_t<decltype(v[0].A)>>;
+            using TB = decltype(tb_tag);
+            prepare_list(v);
+            check_extents<T, TB>(v, ext, b_bytes, c_bytes, c);
+            replay_list<T, TB>(v, ext, b_bytes, c);
+        };
+        if (!tables) {
+            StagedBases t;
+            for (int b = 0; b < 4; ++b) {
+                const size_t n = size_t(K) * G.dims.nl[b];
+                t.ana[b] = place(n * (mode == HP2SPH_F64 ? 8 : 4));
+                t.syn[b] = static_cast<const double*>(place(n * 8));
+                t.synT[b] = static_cast<const double*>(place(n * 8));
+            }
+            run(staged_synthesis_problems(G, t), double{}, G.bytes_U, G.bytes_D);
+            if (mode == HP2SPH_EQUAL_WEIGHT) run(staged_adjoint_problems(G, t), double{}, G.bytes_D, G.bytes_U);
+            else if (mode == HP2SPH_F64) run(staged_analysis_problems<double>(G, t), double{}, G.bytes_D, G.bytes_U);
+            else {
+                if (mode == HP2SPH_F32_REFINE) run(staged_analysis_problems<float>(G, t), float{}, G.bytes_D, G.bytes_U);
+                run(staged_analysis_problems<float, double>(G, t), double{}, G.bytes_D, G.bytes_U);
+            }
+        } else {
+            OrderBases t;
+            for (int b = 0; b < 4; ++b) {
+                OrderLayout L = order_layout(G, b);
+                if (mode == HP2SPH_F64) t.ana64[b] = static_cast<const double*>(place(size_t(L.ana_size) * 8));
+                if (mode == HP2SPH_F32 || mode == HP2SPH_F32_REFINE)
+                    t.ana32[b] = static_cast<const float*>(place(size_t(L.ana_size) * 4));
+                if (mode == HP2SPH_F32_REFINE || mode == HP2SPH_EQUAL_WEIGHT)
+                    t.syn64[b] = static_cast<const double*>(place(size_t(L.syn_size) * 8));
+                if (mode == HP2SPH_EQUAL_WEIGHT) t.adj64[b] = static_cast<const double*>(place(size_t(L.adj_size) * 8));
+            }
+            OrderLists ol = order_problems(G, mode, t);
+            if (!ol.ana64.empty()) run(ol.ana64, double{}, G.bytes_D, G.bytes_U);
+            if (!ol.ana32.empty()) run(ol.ana32, float{}, G.bytes_D, G.bytes_U);
+            if (!ol.ana32_b64.empty()) run(ol.ana32_b64, double{}, G.bytes_D, G.bytes_U);
+            if (!ol.syn64.empty()) run(ol.syn64, double{}, G.bytes_U, G.bytes_D);
+            if (!ol.adj64.empty()) run(ol.adj64, double{}, G.bytes_D, G.bytes_U);
+        }
+    } catch (const std::bad_alloc&) {
+        return fail(HP2SPH_ENOMEM, "host allocation failed");
+    } catch (const std::exception& e) {
+        return fail(HP2SPH_EINVAL, e.what());
+    }
+    *checked = c.checked;
+    *violations = c.violations;
+    *padding = c.padding;
+    g_last_error = c.violations ? c.first : std::string();
     return HP2SPH_OK;
 }
 

@@ -77,6 +77,72 @@ struct GemmProblem {
 // multiple of 4 elements so that its rows can be read as 16-byte vectors.
 __host__ __device__ inline int order_table_lda(int M) { return (M + 3) & ~3; }
 
+// Staging geometry of the grouped GEMM (128 x 128 output tiles, k steps of 16
+// rows, 256 threads), shared by the kernel and the host-side replay of its
+// addresses.  Thread tid stages 8 elements of k row tid / 16 of each operand
+// tile: its 16-byte vector q sits at column 16 VE q + VE (tid % 16), VE the
+// elements per 16 bytes, so the 16 lanes of a row cover one contiguous run.
+// The staging loads are raw buffer loads: per k step one descriptor for A
+// and one for B span the step's rows that lie in the problem, and an element
+// outside the problem's columns gets the offset kGemmOOB, past every
+// descriptor, so the hardware returns zero for it.
+constexpr int kGemmBM = 128, kGemmBN = 128, kGemmBK = 16, kGemmThreads = 256;
+constexpr uint32_t kGemmOOB = 0x80000000u;
+template <class T>
+struct GemmStage {
+    static constexpr int VE = 16 / int(sizeof(T));   // elements per 16-byte vector
+    // k row (within the step) and column (within the tile) of element e of thread tid
+    __host__ __device__ static int row(int tid) { return tid >> 4; }
+    __host__ __device__ static int col(int tid, int e) { return (tid & 15) * VE + (e / VE) * (16 * VE) + (e % VE); }
+};
+// Rows of the k step that starts at k0 (k0 < K).
+template <class T>
+__host__ __device__ inline int gemm_step_rows(const GemmProblem<T>& P, int k0) {
+    return P.K - k0 < kGemmBK ? P.K - k0 : kGemmBK;
+}
+// A is read as 16-byte vectors when its row stride and base allow it; the
+// vector at column mm then covers mm .. mm + VE - 1 < lda (the row padding).
+template <class T>
+__host__ __device__ inline bool gemm_a_vector(const GemmProblem<T>& P) {
+    return (P.lda % GemmStage<T>::VE) == 0 && (reinterpret_cast<uintptr_t>(P.A) % 16) == 0;
+}
+// Bytes covered by the A / B descriptors of the k step at k0 (their bases are
+// A + k0 lda and B + k0 ldb): every row of the step up to the end of the
+// problem's elements in its last row, so that a descriptor never reaches past
+// the operand (a problem's columns may start inside a row of a wider array).
+// The vector loads of A read up to the row padding (column lda).
+// A problem with K = 0 (a synthesis order with no degree: its output is zero)
+// still stages one step, of no rows: its descriptors are empty.
+template <class T>
+__host__ __device__ inline uint32_t gemm_a_records(const GemmProblem<T>& P, int k0) {
+    const int rows = gemm_step_rows(P, k0);
+    if (rows <= 0) return 0;
+    const int64_t last = gemm_a_vector(P) ? P.lda : P.M;
+    return uint32_t((int64_t(rows - 1) * P.lda + last) * int64_t(sizeof(T)));
+}
+template <class T, class TB>
+__host__ __device__ inline uint32_t gemm_b_records(const GemmProblem<T>& P, int k0) {
+    const int rows = gemm_step_rows(P, k0);
+    if (rows <= 0) return 0;
+    return uint32_t((int64_t(rows - 1) * P.ldb + int64_t((P.N - 1) >> 1) * P.bps + 2) * int64_t(sizeof(TB)));
+}
+// Byte offset of the A load of element e (a 16-byte vector at e % VE == 0 when
+// gemm_a_vector, else one element) of thread tid in the tile at row m0.
+template <class T>
+__host__ __device__ inline uint32_t gemm_a_offset(const GemmProblem<T>& P, bool avec, int m0, int tid, int e) {
+    const int mm = m0 + GemmStage<T>::col(tid, e);
+    const bool in = avec ? mm < P.lda : mm < P.M;
+    return in ? uint32_t((GemmStage<T>::row(tid) * int(P.lda) + mm) * int(sizeof(T))) : kGemmOOB;
+}
+// Byte offset of the (re, im) pair load of elements e, e + 1 (e even) of B in
+// the tile at column n0.
+template <class T, class TB>
+__host__ __device__ inline uint32_t gemm_b_offset(const GemmProblem<T>& P, int n0, int tid, int e) {
+    const int nn = n0 + GemmStage<T>::col(tid, e);
+    return nn < P.N ? uint32_t((GemmStage<T>::row(tid) * int(P.ldb) + (nn >> 1) * int(P.bps)) * int(sizeof(TB)))
+                    : kGemmOOB;
+}
+
 // Assign tile ranges (in list order) and return the number of tiles.
 template <class T>
 int finalize_gemm_problems(GemmProblem<T>* p, int n);

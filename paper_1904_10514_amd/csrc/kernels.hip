@@ -594,7 +594,7 @@ struct MfmaAcc<float> {
     static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
 };
 
-constexpr int GBM = 128, GBN = 128, GBK = 16;
+constexpr int GBM = kGemmBM, GBN = kGemmBN, GBK = kGemmBK;
 // Row pad of the LDS tiles: a row stride of GBM + 16 elements puts the four
 // k rows that one MFMA operand load touches on disjoint bank ranges.
 constexpr int GPAD = 16;
@@ -631,10 +631,9 @@ struct Vec2<double> {
 
 // Raw buffer descriptors (gfx9 family): word 3 selects 32-bit data with no
 // swizzle, and a byte offset at or past the descriptor's record count reads
-// as zero.  kBufferOOB is past every descriptor the GEMM builds (records stay
+// as zero.  kGemmOOB is past every descriptor the GEMM builds (records stay
 // below 2^31, checked when a problem list is built).
 constexpr int kBufferWord3 = 0x00020000;
-constexpr int kBufferOOB = int(0x80000000u);
 
 // sizeof(V) bytes (4, 8 or 16) at byte offset `off` of the buffer
 template <class V>
@@ -675,43 +674,33 @@ __device__ __forceinline__ void gemm_tile(const GemmProblem<T>& P, int m0, int n
     // no loaded register is touched before the LDS store (B stays in its
     // storage type until then) and the loads of a step stay in flight behind
     // the MFMAs of the steps before it.
-    constexpr int VE = 16 / sizeof(T);   // elements per 16-byte vector
-    const int lr = tid >> 4;             // 0..15
-    const int lc = (tid & 15) * VE;      // column of the thread's first element
-    // column of the thread's staged element e (0..7)
-    auto ecol = [&](int e) { return lc + (e / VE) * (16 * VE) + (e % VE); };
-    // A rows are read as 16-byte vectors when the row stride and base allow it
-    const bool avec = (P.lda % VE) == 0 && (reinterpret_cast<uintptr_t>(P.A) % 16) == 0;
+    // The offsets and descriptor sizes come from GemmStage / gemm_*_offset
+    // (kernels.h), which the host-side replay of the problem lists also runs.
+    constexpr int VE = GemmStage<T>::VE;
+    const int lr = GemmStage<T>::row(tid);   // 0..15
+    auto ecol = [&](int e) { return GemmStage<T>::col(tid, e); };
+    const bool avec = gemm_a_vector(P);
     using VT = typename Vec16<T>::type;
     using PT = typename Vec2<TB>::type;
     auto gload = [&](int k0, T (&ra)[8], TB (&rb)[8]) {
-        const int rows = min(GBK, P.K - k0);   // k0 < K
         const __amdgpu_buffer_rsrc_t rA = __builtin_amdgcn_make_buffer_rsrc(
-            const_cast<T*>(P.A + int64_t(k0) * P.lda), 0, int(rows * P.lda * int64_t(sizeof(T))), kBufferWord3);
+            const_cast<T*>(P.A + int64_t(k0) * P.lda), 0, int(gemm_a_records(P, k0)), kBufferWord3);
         const __amdgpu_buffer_rsrc_t rB = __builtin_amdgcn_make_buffer_rsrc(
-            const_cast<TB*>(B + int64_t(k0) * P.ldb), 0, int(rows * P.ldb * int64_t(sizeof(TB))), kBufferWord3);
-        const int arow = lr * int(P.lda), brow = lr * int(P.ldb);
+            const_cast<TB*>(B + int64_t(k0) * P.ldb), 0, int(gemm_b_records<T, TB>(P, k0)), kBufferWord3);
         if (avec) {
 #pragma unroll
             for (int e = 0; e < 8; e += VE) {
-                const int mm = m0 + ecol(e);
-                const int off = mm < P.lda ? (arow + mm) * int(sizeof(T)) : kBufferOOB;
-                const VT v = buffer_load<VT>(rA, off);
+                const VT v = buffer_load<VT>(rA, int(gemm_a_offset(P, true, m0, tid, e)));
 #pragma unroll
                 for (int q = 0; q < VE; ++q) ra[e + q] = v[q];
             }
         } else {
 #pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const int mm = m0 + ecol(e);
-                ra[e] = buffer_load<T>(rA, mm < P.M ? (arow + mm) * int(sizeof(T)) : kBufferOOB);
-            }
+            for (int e = 0; e < 8; ++e) ra[e] = buffer_load<T>(rA, int(gemm_a_offset(P, false, m0, tid, e)));
         }
 #pragma unroll
         for (int e = 0; e < 8; e += 2) {
-            const int nn = n0 + ecol(e);
-            const int off = nn < P.N ? (brow + (nn >> 1) * int(P.bps)) * int(sizeof(TB)) : kBufferOOB;
-            const PT v = buffer_load<PT>(rB, off);
+            const PT v = buffer_load<PT>(rB, int(gemm_b_offset<T, TB>(P, n0, tid, e)));
             rb[e] = v[0];
             rb[e + 1] = v[1];
         }
@@ -1931,8 +1920,6 @@ hipError_t configure_kernels() {
     const void* fns[] = {
         reinterpret_cast<const void*>(&k_ring_forward<double, 256>),
         reinterpret_cast<const void*>(&k_ring_forward<double, 512>),
-        reinterpret_cast<const void*>(&k_ring_forward<float, 256>),
-        reinterpret_cast<const void*>(&k_ring_forward<float, 512>),
         reinterpret_cast<const void*>(&k_ring_inverse<256>),
         reinterpret_cast<const void*>(&k_ring_inverse<512>),
         reinterpret_cast<const void*>(&k_ring_adjoint<256>),
@@ -1949,8 +1936,6 @@ hipError_t configure_kernels() {
 // explicit instantiations
 template hipError_t launch_ring_forward<double>(const double*, const int64_t*, RingTab, FftTab<double>,
                                                 Blocks4<double>, const GroupDims&, hipStream_t);
-template hipError_t launch_ring_forward<float>(const double*, const int64_t*, RingTab, FftTab<float>,
-                                               Blocks4<float>, const GroupDims&, hipStream_t);
 template hipError_t launch_pole<double>(Blocks4<double>, const GroupDims&, double, double, double, hipStream_t);
 template hipError_t launch_pole<float>(Blocks4<float>, const GroupDims&, double, double, double, hipStream_t);
 template hipError_t launch_gemm<double, double>(const GemmProblem<double>*, const int32_t*, int, const double*,

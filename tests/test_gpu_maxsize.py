@@ -1,13 +1,19 @@
 """GPU checks at the largest supported nside (2048, lmax 4096): the ring
 transforms run 512-thread workgroups with 8192-point FFTs and the plan takes
-the staged strategy (per-order tables would not fit).  The oracle's dense
-colatitude fit is too slow at this size, so the checks are the exact-recovery
-property on order-1 fields (tests/gpu_util.py), which covers the ring
-transform, pole, fit and packing of every l <= p, the synthesis and the
-refinement; the Givens sweeps of orders >= 2 are covered against the oracle
-at smaller nside and by the staged-vs-tables agreement.  The last test runs
-the benchmark's own shape at this nside (16 maps).
+the staged strategy (per-order tables would not fit).  The checks are the
+exact-recovery property on order-1 fields (tests/gpu_util.py), which covers
+the ring transform, pole, fit and packing of every l <= p, the synthesis and
+the refinement; FP64 on a white-noise map against the oracle's values on
+sampled orders up to m = 4096 (tests/golden/oplain_nside2048.txt, computed
+offline: the oracle's dense colatitude fit takes minutes at this size),
+which puts the Givens sweeps of every depth through a check; and, in
+tests/test_gpu_equivariance.py, the exact equivariances at this size for
+every order in both precision modes.  The last test runs the benchmark's own
+shape at this nside (16 maps).
 """
+
+import hashlib
+import os
 
 import numpy as np
 import pytest
@@ -28,16 +34,46 @@ def fields():
     return torch.from_numpy(maps.reshape(-1)).cuda(), expect
 
 
-def test_nside2048_f64_recovers_order_one_fields(fields):
+def _golden2048():
+    out = {"alm": {}}
+    for line in open(os.path.join(os.path.dirname(__file__), "golden", "oplain_nside2048.txt")):
+        w = line.split()
+        if not w or w[0].startswith("#"):
+            continue
+        if w[0] == "sha256":
+            out["sha256"] = w[1]
+        elif w[0] == "alm":
+            out["alm"][(int(w[1]), int(w[2]))] = complex(float(w[3]), float(w[4]))
+    return out
+
+
+def test_nside2048_f64_recovers_order_one_fields_and_matches_oracle(fields):
+    """FP64, staged, on the two order-1 fields and on the white-noise map of
+    tests/golden/oplain_nside2048.txt (the oracle's order-by-order route,
+    written by make_oplain_nside2048.py), whose sampled orders m = 0 .. 4096
+    (sweeps up to 2048 deep) must match to kappa p eps = 50 * 4096 * 1.1e-16."""
     dev, expect = fields
-    plan = P.Plan(NSIDE, LMAX, batch=BATCH, mode="f64")
+    import oracle as O
+    import workloads as W
+    g = _golden2048()
+    white = W.random_map(O.npix(NSIDE), W.rng_for(14, 0))
+    assert hashlib.sha256(np.ascontiguousarray(white).astype("<f8").tobytes()).hexdigest() == g["sha256"]
+    batch = torch.cat([dev, torch.from_numpy(white).cuda()])
+    del white
+    plan = P.Plan(NSIDE, LMAX, batch=BATCH + 1, mode="f64")
     assert plan.strategy == "staged"
-    a = plan.analyze(dev)
+    a = plan.analyze(batch)
     torch.cuda.synchronize()
-    e = rel_err(a.cpu().numpy().reshape(BATCH, -1), expect)
+    a = a.cpu().numpy().reshape(BATCH + 1, -1)
     plan.close()
-    print(f"order-1 fields, nside 2048 x 2: FP64 {e:.3e}")
+    e = rel_err(a[:BATCH], expect)
+    keys = sorted(g["alm"])
+    ref = np.array([g["alm"][k] for k in keys])
+    got = np.array([a[BATCH][O.alm_index(l, m, LMAX)] for m, l in keys])
+    eo = float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
+    print(f"nside 2048, FP64: order-1 fields {e:.3e}; white noise vs oracle on sampled orders {eo:.3e}")
     assert e < 1e-12
+    assert eo < 50 * 4096 * 1.1e-16
 
 
 def test_nside2048_refinement_recovers_order_one_fields(fields):

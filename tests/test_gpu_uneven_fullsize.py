@@ -7,13 +7,19 @@ The oracle cannot analyse the batch's 1.07e9 pixels, so a stratified subset is
 compared map by map:
 * FP32 + refinement against the refined FP64 oracle (one step of eq. uzawa
   with A the HP2SPH analysis, all FP64) on the first map of the nside 64, 128
-  and 256 classes and on the last map of the nside 64 class;
+  and 256 classes and on the last map of the nside 64 class, computed here,
+  and on the first map of the nside 512 class against the oracle's values
+  stored in tests/golden/oref_uneven_nside512.txt (written by
+  make_oref_uneven512.py: C_l for every l and a_l^m on sampled orders);
 * FP64 against the oracle's order-by-order route (the Remark of Sec. 3.2.1)
   on sampled orders, all l of each, of the first map of every class, nside 512
   included.
 Inputs are seeded white-noise maps drawn on the host (every scale present):
 the bench's power-law maps come out of the GPU synthesis, and no oracle input
 may come from the GPU path."""
+
+import hashlib
+import os
 
 import numpy as np
 import pytest
@@ -28,8 +34,10 @@ torch = pytest.importorskip("torch")
 import paper_1904_10514_amd as P   # noqa: E402
 
 # FP32 + refinement vs the refined oracle: the first pass's FP32 error times
-# I - A S (norm up to ~1 on white noise), as in the small-size parity tests.
+# I - A S (norm up to ~1 on white noise), as in the small-size parity tests,
+# and the relative C_l bound of tests/test_gpu_headline_accuracy.py.
 TOL_REFINE = 1e-6
+TOL_REFINE_CL = 1e-6
 # FP64 at p <= 1024: kappa p eps = 50 * 1024 * 1.1e-16 = 5.6e-12 relative to
 # the largest coefficient on each side (the tolerance of the nside-1024 tests).
 TOL64 = 1.1e-11
@@ -62,6 +70,23 @@ def _analyze(batch, mode):
     return out, offs
 
 
+def _golden512():
+    out = {"cl": {}, "alm": {}}
+    for line in open(os.path.join(os.path.dirname(__file__), "golden", "oref_uneven_nside512.txt")):
+        w = line.split()
+        if not w or w[0].startswith("#"):
+            continue
+        if w[0] == "index":
+            out["index"] = int(w[1])
+        elif w[0] == "sha256":
+            out["sha256"] = w[1]
+        elif w[0] == "cl":
+            out["cl"][int(w[1])] = float(w[2])
+        elif w[0] == "alm":
+            out["alm"][(int(w[1]), int(w[2]))] = complex(float(w[3]), float(w[4]))
+    return out
+
+
 def test_uneven_fullsize_refinement_vs_refined_oracle(batch):
     nsides, lmaxs, maps, _, first, last64 = batch
     a, offs = _analyze(batch, "f32_refine")
@@ -70,6 +95,22 @@ def test_uneven_fullsize_refinement_vs_refined_oracle(batch):
         err = rel_err(a[offs[i]:offs[i + 1]], ref)
         print(f"map {i} (nside {nsides[i]}): FP32 + refinement vs refined oracle {err:.3e}")
         assert err < TOL_REFINE
+    # the nside 512 class against the stored oracle values
+    g = _golden512()
+    i = first[512]
+    assert g["index"] == i
+    assert hashlib.sha256(np.ascontiguousarray(maps[i]).astype("<f8").tobytes()).hexdigest() == g["sha256"]
+    mine = a[offs[i]:offs[i + 1]]
+    keys = sorted(g["alm"])
+    ref_a = np.array([g["alm"][k] for k in keys])
+    got = np.array([mine[O.alm_index(l, m, 1024)] for m, l in keys])
+    err = float(np.max(np.abs(got - ref_a)) / np.max(np.abs(ref_a)))
+    cl = O.power_spectrum(mine, 1024)
+    ref_cl = np.array([g["cl"][l] for l in range(1025)])
+    ecl = float(np.max(np.abs(cl[2:] - ref_cl[2:]) / ref_cl[2:]))
+    print(f"map {i} (nside 512): FP32 + refinement vs refined oracle, sampled orders {err:.3e}, rel C_l {ecl:.3e}")
+    assert err < TOL_REFINE
+    assert ecl < TOL_REFINE_CL
 
 
 def test_uneven_fullsize_f64_sampled_orders(batch):
