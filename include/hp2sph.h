@@ -158,6 +158,25 @@ int hp2sph_analyze(hp2sph_plan_t plan, const double* maps, double* alm,
                    void* workspace, size_t workspace_bytes, void* stream);
 
 /*
+ * hp2sph_analyze with no workspace argument, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc): the workspace is a static device array of
+ * HP2SPH_NOALLOC_WORKSPACE bytes inside the library, one per device, held
+ * until the process ends (its device address is looked up when the first
+ * plan is created on that device).  The call allocates nothing and records
+ * no profiling events; it computes exactly what hp2sph_analyze computes.
+ * Every call on a device shares that device's array and leaves its contents
+ * behind: calls that overlap in time on one device (two streams, two
+ * threads) race on it and must be serialised by the caller.  maps, alm,
+ * stream as for hp2sph_analyze.
+ * Errors: EINVAL (the plan needs more than HP2SPH_NOALLOC_WORKSPACE bytes of
+ * workspace -- see hp2sph_workspace_size -- or null/misaligned maps or alm),
+ * ESTATE, EDEVICE.
+ */
+#define HP2SPH_NOALLOC_WORKSPACE (256u << 20)
+int hp2sph_analyze_noalloc(hp2sph_plan_t plan, const double* maps, double* alm, void* stream);
+
+/*
  * Equal-weight analysis with Jacobi iterations (Sec. 2.2, eqs. healsph,
  * uzawa, richardson), for plans created with HP2SPH_EQUAL_WEIGHT:
  *   a(0) = A f,  a(k+1) = a(k) + A (f - S a(k)),  k < niter,

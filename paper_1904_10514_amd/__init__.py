@@ -54,7 +54,7 @@ EXPORTED = [
     "hp2sph_power_spectrum", "hp2sph_plan_destroy", "hp2sph_last_error", "hp2sph_host_table",
     "hp2sph_profile", "hp2sph_profile_read", "hp2sph_plan_create_ex", "hp2sph_plan_strategy",
     "hp2sph_analyze_iterative", "hp2sph_set_schedule", "hp2sph_autotune", "hp2sph_schedules",
-    "hp2sph_schedule_map", "hp2sph_gemm_check",
+    "hp2sph_schedule_map", "hp2sph_gemm_check", "hp2sph_analyze_noalloc",
 ]
 STRATEGIES = {"auto": 0, "staged": 1, "tables": 2}
 SCHEDULES = ["xcd_round_robin", "xcd_balanced", "linear", "linear_rows"]
@@ -86,6 +86,8 @@ _lib.hp2sph_schedules.argtypes = [_vp, ctypes.POINTER(_i32), _i32, ctypes.POINTE
 _lib.hp2sph_schedule_map.argtypes = [_i32, _vp, _vp, _vp, _i32, _vp, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
 _lib.hp2sph_host_table.argtypes = [_i32, _i32, _i32, _vp, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
 _lib.hp2sph_gemm_check.argtypes = [_i32, _i32, _i32, _i32] + [ctypes.POINTER(ctypes.c_int64)] * 3
+_lib.hp2sph_analyze_noalloc.argtypes = [_vp, _vp, _vp, _vp]
+NOALLOC_WORKSPACE = 256 << 20
 for _f in EXPORTED:
     if _f not in ("hp2sph_last_error",):
         getattr(_lib, _f).restype = ctypes.c_int
@@ -234,6 +236,17 @@ class Plan:
         out = self._alm_out(out)
         _check(_lib.hp2sph_analyze(self._h, maps.data_ptr(), out.data_ptr(), self._ws_ptr, self.workspace_bytes,
                                    self._stream()), "analyze")
+        return out
+
+    def analyze_noalloc(self, maps, out):
+        """hp2sph_analyze_noalloc: the analysis with the library's static device
+        workspace (no workspace argument, nothing allocated); `out` must be
+        given.  Calls that overlap in time on one device race on that workspace."""
+        _torch()
+        self._maps(maps)
+        self._alm(out, "out")
+        _check(_lib.hp2sph_analyze_noalloc(self._h, maps.data_ptr(), out.data_ptr(), self._stream()),
+               "analyze_noalloc")
         return out
 
     def analyze_iterative(self, maps, niter, out=None):

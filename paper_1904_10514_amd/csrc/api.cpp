@@ -1375,6 +1375,11 @@ int hp2sph_plan_create_ex(const int32_t* nside, const int32_t* lmax, int32_t bat
         plan->ws_bytes = ws;
         // kernels with more than 64 KB of dynamic LDS
         if (configure_kernels() != hipSuccess) return fail(HP2SPH_EDEVICE, "hipFuncSetAttribute failed");
+        // device address of this device's static workspace (for
+        // hp2sph_analyze_noalloc), looked up once per device at set-up
+        if (hipError_t e = scratch_init(); e != hipSuccess)
+            return fail(HP2SPH_EDEVICE, std::string("hipGetSymbolAddress of the static workspace: ") +
+                                            hipGetErrorString(e));
     } catch (const std::bad_alloc&) {
         return fail(HP2SPH_ENOMEM, "allocation of plan tables failed");
     } catch (const std::exception& e) {
@@ -1426,6 +1431,25 @@ int hp2sph_analyze(hp2sph_plan_t plan, const double* maps, double* alm, void* wo
         }
     }
     return HP2SPH_OK;
+}
+
+static_assert(kScratchBytes == HP2SPH_NOALLOC_WORKSPACE, "static workspace size of the C ABI");
+
+int hp2sph_analyze_noalloc(hp2sph_plan_t plan, const double* maps, double* alm, void* stream) {
+    if (int e = check_plan(plan)) return e;
+    if (plan->ws_bytes > kScratchBytes)
+        return fail(HP2SPH_EINVAL, "the plan needs " + std::to_string(plan->ws_bytes) + " bytes of workspace, more than "
+                                   "the " + std::to_string(kScratchBytes) + " bytes of the static workspace");
+    void* ws = scratch_ptr(plan->device);
+    if (!ws) return fail(HP2SPH_ESTATE, "no static workspace on the plan's device");
+    // no profiling events here: they come from a pool that may need creating
+    Profiler* const saved = g_prof;
+    const bool was_on = plan->prof.on;
+    plan->prof.on = false;
+    const int e = hp2sph_analyze(plan, maps, alm, ws, kScratchBytes, stream);
+    plan->prof.on = was_on;
+    g_prof = saved;
+    return e;
 }
 
 int hp2sph_analyze_iterative(hp2sph_plan_t plan, const double* maps, double* alm, int32_t niter, void* workspace,

@@ -251,6 +251,15 @@ hipError_t launch_ring_inverse(Blocks4<const double> D, RingTab rt, FftTab<doubl
 // Raise the dynamic-LDS limit of the ring kernels (up to 139 KB at nside 2048).
 hipError_t configure_kernels();
 
+// Size of the static device workspace of the allocation-free analysis
+// (HP2SPH_NOALLOC_WORKSPACE of the C ABI).
+constexpr size_t kScratchBytes = size_t(256) << 20;
+// Looks up (once per device, with that device current) the device address of
+// the static workspace; scratch_ptr(device) returns it afterwards (null if
+// scratch_init never ran on that device).
+hipError_t scratch_init();
+void* scratch_ptr(int device);
+
 // C_l per map from packed alm.
 hipError_t launch_cl(const double* alm, const int64_t* alm_off, const int32_t* lmax, double* cl,
                      const int64_t* cl_off, int nmaps, int lmax_max, hipStream_t s);

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 
 namespace hp2sph {
 
@@ -1913,6 +1914,42 @@ hipError_t launch_cl(const double* alm, const int64_t* alm_off, const int32_t* l
     dim3 grid(unsigned((lmax_max + kClL) / kClL), nmaps);
     hipLaunchKernelGGL(k_cl, grid, dim3(kClL * kClParts), 0, s, alm, alm_off, lmax, cl, cl_off);
     return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Static workspace of the allocation-free analysis (hp2sph_analyze_noalloc)
+// ---------------------------------------------------------------------------
+
+// A file-scope device array: every device the library runs on holds its own
+// copy until the process ends.  In host code `scratch` names a host-side
+// stand-in, not device memory: its device address is looked up per device
+// with hipGetSymbolAddress (scratch_init) and only that address is used.
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxScratchDevices] = {};
+}  // namespace
+
+hipError_t scratch_init() {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxScratchDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[dev]) return hipSuccess;
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = ptr;
+    return hipSuccess;
+}
+
+void* scratch_ptr(int device) {
+    if (device < 0 || device >= kMaxScratchDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return g_scratch_ptr[device];
 }
 
 hipError_t configure_kernels() {
