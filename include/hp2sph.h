@@ -102,6 +102,12 @@ enum {
  * (geometry, the colatitude least-squares solve fused with the Legendre
  * connection, Givens angles, FFT twiddles) is built here on the host in FP64
  * and copied to the device once; nothing of it is rebuilt per call.
+ * If the environment variable HP2SPH_TABLE_CACHE names a directory, the host
+ * tables of each nside are read from a file there when one written by the
+ * same build of the library exists, and written there otherwise (one file
+ * per nside, written under a temporary name and renamed; about 200 MB at
+ * nside 1024, 1 GB at 2048).  A missing, unreadable or foreign file only
+ * costs the rebuild; an unwritable directory is not an error.
  * On success *out receives the plan (owned by the caller; free it with
  * hp2sph_plan_destroy).  Errors: EINVAL, ENOMEM, EDEVICE.
  */

@@ -2,10 +2,16 @@
 // here runs per call.
 #include "tables.h"
 
+#include <unistd.h>
+
 #include <algorithm>
 #include <cmath>
 #include <complex>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
 #include <stdexcept>
+#include <string>
 #include <thread>
 
 namespace hp2sph {
@@ -221,8 +227,9 @@ void givens_cs(int l, int mp, double* c, double* s) {
     *c = std::sqrt(double(num_c) / double(d));
 }
 
-void build_tables(int nside, HostTables& t, bool with_fft) {
-    if (nside < 2 || !is_pow2(nside)) throw std::invalid_argument("nside must be a power of two >= 2");
+namespace {
+
+void build_uncached(int nside, HostTables& t, bool with_fft) {
     t.nside = nside;
     const int p = 2 * nside;
     t.p = p;
@@ -409,6 +416,112 @@ void build_tables(int nside, HostTables& t, bool with_fft) {
             F[2 * k + 1] = bc[k].imag();
         }
     });
+}
+
+// ---------------------------------------------------------------------------
+// On-disk cache of the tables (HP2SPH_TABLE_CACHE names a directory)
+// ---------------------------------------------------------------------------
+//
+// One file per nside: a header (magic, the build stamp of this file, nside,
+// whether the FFT tables are present) and then every table as (count, raw
+// bytes).  The build stamp ties a file to the code that wrote it: a rebuilt
+// library ignores (and rewrites) files of an earlier build.  Files are
+// written to a temporary name and renamed, so a reader never sees a partial
+// file; a file that does not parse is rebuilt.
+
+constexpr char kCacheMagic[8] = {'H', 'P', '2', 'S', 'T', 'A', 'B', '1'};
+const char* const kBuildStamp = __DATE__ " " __TIME__;
+
+struct CacheFile {
+    FILE* f = nullptr;
+    ~CacheFile() {
+        if (f) std::fclose(f);
+    }
+};
+
+template <class V>
+bool put_vec(FILE* f, const std::vector<V>& v) {
+    const uint64_t n = v.size();
+    return std::fwrite(&n, sizeof n, 1, f) == 1 && (n == 0 || std::fwrite(v.data(), sizeof(V), n, f) == n);
+}
+
+template <class V>
+bool get_vec(FILE* f, std::vector<V>& v) {
+    uint64_t n = 0;
+    if (std::fread(&n, sizeof n, 1, f) != 1 || n > (uint64_t(1) << 36) / sizeof(V)) return false;
+    v.resize(n);
+    return n == 0 || std::fread(v.data(), sizeof(V), n, f) == n;
+}
+
+struct CacheHeader {
+    char magic[8];
+    char stamp[32];
+    int32_t nside, with_fft, fft_max, pad;
+    double pole_w[3];
+};
+
+bool io_tables(FILE* f, HostTables& t, bool write) {
+    auto vec = [&](auto& v) { return write ? put_vec(f, v) : get_vec(f, v); };
+    bool ok = vec(t.rings);
+    for (int b = 0; b < 4 && ok; ++b) ok = vec(t.ana[b]) && vec(t.syn[b]) && vec(t.givens[b]);
+    ok = ok && vec(t.twiddle) && vec(t.rootoff) && vec(t.roots) && vec(t.chirpoff) && vec(t.chirp) &&
+         vec(t.chirpfftoff) && vec(t.chirpm) && vec(t.chirpfft);
+    return ok;
+}
+
+std::string cache_path(const char* dir, int nside) {
+    return std::string(dir) + "/hp2sph_tables_nside" + std::to_string(nside) + ".bin";
+}
+
+bool cache_load(const char* dir, int nside, bool with_fft, HostTables& t) {
+    CacheFile cf;
+    cf.f = std::fopen(cache_path(dir, nside).c_str(), "rb");
+    if (!cf.f) return false;
+    CacheHeader hd{};
+    if (std::fread(&hd, sizeof hd, 1, cf.f) != 1) return false;
+    if (std::memcmp(hd.magic, kCacheMagic, 8) != 0 || std::strncmp(hd.stamp, kBuildStamp, sizeof hd.stamp) != 0 ||
+        hd.nside != nside || (with_fft && !hd.with_fft))
+        return false;
+    HostTables r;
+    if (!io_tables(cf.f, r, false)) return false;
+    r.nside = nside;
+    r.p = 2 * nside;
+    r.fft_max = hd.fft_max;
+    for (int i = 0; i < 3; ++i) r.pole_w[i] = hd.pole_w[i];
+    if (r.rings.size() != size_t(4 * nside - 1)) return false;
+    t = std::move(r);
+    return true;
+}
+
+void cache_store(const char* dir, int nside, bool with_fft, HostTables& t) {
+    const std::string path = cache_path(dir, nside);
+    const std::string tmp = path + ".tmp" + std::to_string(long(getpid()));
+    bool ok = false;
+    {
+        CacheFile cf;
+        cf.f = std::fopen(tmp.c_str(), "wb");
+        if (!cf.f) return;   // an unwritable cache directory only costs the rebuild
+        CacheHeader hd{};
+        std::memcpy(hd.magic, kCacheMagic, 8);
+        std::strncpy(hd.stamp, kBuildStamp, sizeof hd.stamp - 1);
+        hd.nside = nside;
+        hd.with_fft = with_fft ? 1 : 0;
+        hd.fft_max = t.fft_max;
+        for (int i = 0; i < 3; ++i) hd.pole_w[i] = t.pole_w[i];
+        ok = std::fwrite(&hd, sizeof hd, 1, cf.f) == 1 && io_tables(cf.f, t, true);
+        ok = (std::fflush(cf.f) == 0) && ok;
+    }
+    if (!ok || std::rename(tmp.c_str(), path.c_str()) != 0) std::remove(tmp.c_str());
+}
+
+}  // namespace
+
+void build_tables(int nside, HostTables& t, bool with_fft) {
+    if (nside < 2 || !is_pow2(nside)) throw std::invalid_argument("nside must be a power of two >= 2");
+    const char* dir = std::getenv("HP2SPH_TABLE_CACHE");
+    if (dir && *dir && cache_load(dir, nside, with_fft, t)) return;
+    build_uncached(nside, t, with_fft);
+    if (dir && *dir) cache_store(dir, nside, with_fft, t);
 }
 
 }  // namespace hp2sph

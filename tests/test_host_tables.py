@@ -250,3 +250,45 @@ def test_synthesis_tables_reproduce_oracle_synthesis(nside):
         out[rt["start"][r]:rt["start"][r] + n] = (np.fft.ifft(H) * n).real
     ref = O.synthesize(a, nside, p)
     assert np.max(np.abs(out - ref)) < 1e-12 * max(1.0, np.max(np.abs(ref)))
+
+
+def test_table_cache_round_trip_and_rejects_foreign_files(tmp_path, monkeypatch):
+    """HP2SPH_TABLE_CACHE: the first build writes one file per nside, later
+    builds read it back bit for bit; a truncated file or one with another
+    build stamp is ignored (rebuilt and rewritten), never half-read."""
+    monkeypatch.delenv("HP2SPH_TABLE_CACHE", raising=False)
+    nside = 8
+    fresh = {(t, b): P.host_table(nside, t, b) for t in (2, 3, 4) for b in range(4)}
+    fresh[(1, 0)] = P.host_table(nside, 1, 0)
+    monkeypatch.setenv("HP2SPH_TABLE_CACHE", str(tmp_path))
+    path = tmp_path / f"hp2sph_tables_nside{nside}.bin"
+
+    def all_equal():
+        return all(np.array_equal(P.host_table(nside, t, b), v) for (t, b), v in fresh.items())
+
+    assert all_equal()                      # builds and writes
+    assert path.exists()
+    size = path.stat().st_size
+    assert all_equal()                      # reads
+    # a truncated file: ignored, rebuilt, rewritten whole
+    data = path.read_bytes()
+    path.write_bytes(data[: size // 2])
+    assert all_equal()
+    assert path.stat().st_size == size
+    # another build's stamp: ignored
+    bad = bytearray(path.read_bytes())
+    bad[8:40] = b"Jan  1 1970 00:00:00".ljust(32, b"\0")
+    path.write_bytes(bytes(bad))
+    assert all_equal()
+    assert path.read_bytes() == data
+    # the read path is what serves a cached nside: a value changed in the
+    # file (the first entry of the block-0 analysis matrix, after the
+    # 80-byte header and the ring table of 4 nside - 1 records of 40 bytes)
+    # comes back as changed
+    off = 80 + 8 + (4 * nside - 1) * 40 + 8
+    assert data[off:off + 8] == fresh[(2, 0)][:1].tobytes()
+    poisoned = bytearray(data)
+    poisoned[off:off + 8] = np.float64(12345.0).tobytes()
+    path.write_bytes(bytes(poisoned))
+    got = P.host_table(nside, 2, 0)
+    assert got[0] == 12345.0 and np.array_equal(got[1:], fresh[(2, 0)][1:])
