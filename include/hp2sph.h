@@ -98,7 +98,11 @@ enum {
 /*
  * Create a plan for `batch` maps.  nside[b] is a power of two in
  * [2, HP2SPH_MAX_NSIDE]; 0 <= lmax[b] <= 2 nside[b].  Maps with equal nside
- * form one group that every stage processes in one launch.  The set-up
+ * form one group; each stage of an analysis is one launch over a work list
+ * that holds every group (the ring transforms of nside 2048 in a launch of
+ * their own, with twice the threads per workgroup), except the Givens sweeps
+ * of staged groups and the equal-weight analysis, which run per group.  The
+ * workspace holds every group's buffers side by side.  The set-up
  * (geometry, the colatitude least-squares solve fused with the Legendre
  * connection, Givens angles, FFT twiddles) is built here on the host in FP64
  * and copied to the device once; nothing of it is rebuilt per call.
@@ -294,17 +298,24 @@ enum {
 int hp2sph_set_schedule(hp2sph_plan_t plan, int32_t sched);
 
 /*
- * Autotuner: for each GEMM that hp2sph_analyze launches (nside groups in plan
- * order, GEMMs in launch order), times hp2sph_analyze of the caller's maps
- * under each candidate schedule of that GEMM, the others held at their current
- * choice, and keeps the fastest; a candidate replaces the current choice only
+ * Autotuner: for each GEMM that hp2sph_analyze launches (GEMMs in launch
+ * order; the analysis modes merge every nside group into one GEMM per role),
+ * times hp2sph_analyze of the caller's maps under each candidate schedule of
+ * that GEMM, the others held at their current choice, and keeps the fastest;
+ * then the same for the work grid of the refinement's fold
+ * (hp2sph_set_fold_grid).  A candidate replaces the current choice only
  * when it is more than 0.5 % faster (the run-to-run spread of a timed
  * analysis).  Each timing is the fastest of `reps` analyses (HIP events on
  * `stream`, after one untimed analysis).  Synchronous: returns after the last
  * timed run, with alm holding hp2sph_analyze(maps) and *best_ms (if not null)
  * the time of one analysis under the chosen schedules.  Stage profiling
- * (hp2sph_profile) is paused meanwhile.  maps, alm, workspace,
- * workspace_bytes, stream as for hp2sph_analyze; 1 <= reps <=
+ * (hp2sph_profile) is paused meanwhile.  The choices are remembered for the
+ * plan's shape (device, mode, and each group's nside, map count and
+ * strategy): a plan of that shape created later in the process starts with
+ * them, and so does one in a later process when the environment variable
+ * HP2SPH_TUNE_CACHE names a file (read at the first plan creation, appended
+ * to by each autotune; an unreadable file is ignored).  maps, alm,
+ * workspace, workspace_bytes, stream as for hp2sph_analyze; 1 <= reps <=
  * HP2SPH_MAX_TUNE_REPS.
  * Errors: as hp2sph_analyze, EINVAL for reps out of range, EDEVICE.
  */
@@ -316,6 +327,22 @@ int hp2sph_autotune(hp2sph_plan_t plan, const double* maps, double* alm, void* w
  * autotuner visits them: writes min(cap, count) ids to out (may be null when
  * cap is 0) and the count to *count.  Errors: ESTATE, EINVAL. */
 int hp2sph_schedules(hp2sph_plan_t plan, int32_t* out, int32_t cap, int32_t* count);
+
+/*
+ * Work grid of the refinement's residual fold.  The stages of an analysis
+ * run as one launch over a work list that holds every nside group of the
+ * plan (items grouped by nside, largest first; a fold item is one ring pair
+ * of 16 maps).  Grid 0: one workgroup per item (the default).  Grid g >= 8:
+ * a persistent launch of g workgroups (rounded down to a multiple of 8, so
+ * that each item keeps its XCD) that walk the list.  Results are bitwise the
+ * same under every grid.  hp2sph_autotune chooses it after the GEMM
+ * schedules (candidates 0, 2 and 4 workgroups per compute unit) and
+ * remembers its choice per plan shape.  Host state only, like
+ * hp2sph_set_schedule.  Errors: ESTATE, EINVAL (a grid below 0 or between 1
+ * and 7), null output.
+ */
+int hp2sph_set_fold_grid(hp2sph_plan_t plan, int32_t grid);
+int hp2sph_fold_grid(hp2sph_plan_t plan, int32_t* grid);
 
 /*
  * Host-only inspection of a schedule (no GPU needed): the workgroup -> (problem,

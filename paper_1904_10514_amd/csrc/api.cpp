@@ -3,6 +3,7 @@
 
 #include <algorithm>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -88,10 +89,12 @@ template <class T>
 struct GemmList : GemmSched {
     GemmProblem<T>* dev = nullptr;
     int n = 0, tiles = 0;
+    std::vector<GemmProblem<T>> host;   // the uploaded list (launch order)
 };
 
 struct Group {
     int nside = 0;
+    int index = 0;                    // position in the plan's group list
     std::vector<int> members;         // batch indices
     GroupDims dims{};
     double pole_w[3] = {0, 0, 0};
@@ -108,8 +111,13 @@ struct Group {
     int32_t* d_pack_tiles = nullptr;   // (m, l0) of the pack tiles
     int n_pack_tiles = 0;
     int lmax_max = 0;
-    // workspace offsets (bytes, relative to the plan's workspace)
+    // workspace regions (byte offsets from the plan's workspace; each group
+    // has its own, so that one launch can serve every group): D, U and, by
+    // mode, the refinement's Df (FP64 ring coefficients), Dr (FP32 residual
+    // coefficients), Ua (FP32 a0) or the equal-weight analysis' Ua (FP64 a),
+    // Wf and Wr (longitude sums of the maps and of the residual)
     size_t off_D = 0, off_U = 0;
+    size_t off_Df = 0, off_Dr = 0, off_Ua = 0, off_Wf = 0, off_Wr = 0;
     size_t bytes_D = 0, bytes_U = 0;
     int64_t rows_D[4] = {}, rows_U[4] = {};
     size_t blk_off_D[4] = {}, blk_off_U[4] = {};   // byte offset of each block in its region
@@ -190,12 +198,27 @@ struct hp2sph_plan_s {
     std::vector<int32_t> nside, lmax;
     std::vector<int64_t> map_off, alm_off, cl_off;
     int64_t total_pix = 0, total_alm = 0, total_cl = 0;
-    std::vector<std::unique_ptr<hp2sph::Group>> groups;
+    std::vector<std::unique_ptr<hp2sph::Group>> groups;   // descending nside
     size_t ws_bytes = 0;
-    size_t off_Df = 0, off_Dr = 0;    // refinement: FP64 ring coefficients, FP32 residual coefficients
-    size_t off_Ua = 0;                // refinement: FP32 a0 in the U layout; equal weight: FP64 a in the U layout
-    size_t off_Wf = 0, off_Wr = 0;   // equal weight: longitude sums of the maps and of the residual
     int strategy = 0;                 // requested HP2SPH_STRATEGY_*
+    // work-list launches: one descriptor per group (device and host copies),
+    // the spans of groups that share the ring kernels' thread count, and the
+    // persistent grid of the fold (0: one workgroup per item)
+    std::vector<std::unique_ptr<hp2sph::DevBuf>> owned;
+    std::vector<hp2sph::GroupDesc> gdesc;
+    hp2sph::GroupDesc* d_gdesc = nullptr;
+    std::vector<std::pair<int, int>> ring_spans;
+    int fold_grid = 0;
+    // per-map offsets of the whole batch (C_l in one launch)
+    int64_t* d_alm_off = nullptr;
+    int64_t* d_cl_off = nullptr;
+    int32_t* d_lmax = nullptr;
+    int lmax_max = 0;
+    // the analysis GEMMs of every group merged into one list per role (B and
+    // C offsets from the workspace base): FP64 analysis; FP32 analysis of
+    // FP64 ring coefficients; FP64 synthesis; FP32 analysis of FP32 ones
+    hp2sph::GemmList<double> m_ana64, m_syn64;
+    hp2sph::GemmList<float> m_ana32_b64, m_ana32;
 };
 
 using namespace hp2sph;
@@ -595,15 +618,16 @@ void replay_list(const std::vector<GemmProblem<T>>& v, const std::vector<Extent>
 }
 
 template <class T>
-void upload_list(Group& G, std::vector<GemmProblem<T>>& v, GemmList<T>& out) {
+void upload_list(std::vector<std::unique_ptr<DevBuf>>& owned, std::vector<GemmProblem<T>>& v, GemmList<T>& out) {
     out.tiles = prepare_list(v);
     out.n = int(v.size());
-    out.dev = upload_int(G.owned, v);
+    out.dev = upload_int(owned, v);
+    out.host = v;
     for (int c = 0; c < HP2SPH_NSCHED; ++c) {
         std::vector<int32_t> tm = c == HP2SPH_SCHED_XCD_ROUND_ROBIN ? xcd_tile_map<T>(v.data(), int(v.size()))
                                                                    : schedule_map(v, out.tiles, c);
         out.nslots[c] = int(tm.size() / 2);
-        out.maps[c] = upload_int(G.owned, tm);
+        out.maps[c] = upload_int(owned, tm);
     }
     // XCD placement keeps each problem on one XCD, which leaves XCDs idle
     // when a list has fewer problems than two per XCD (the four parity-block
@@ -973,11 +997,11 @@ void build_order_tables(hp2sph_plan_t plan, Group& G) {
     require_extents<float, double>(ol.ana32_b64, extents, G.bytes_D, G.bytes_U);
     require_extents<double>(ol.syn64, extents, G.bytes_U, G.bytes_D);
     require_extents<double>(ol.adj64, extents, G.bytes_D, G.bytes_U);
-    if (!ol.ana64.empty()) upload_list(G, ol.ana64, G.ana64);
-    if (!ol.ana32.empty()) upload_list(G, ol.ana32, G.ana32);
-    if (!ol.ana32_b64.empty()) upload_list(G, ol.ana32_b64, G.ana32_b64);
-    if (!ol.syn64.empty()) upload_list(G, ol.syn64, G.syn64);
-    if (!ol.adj64.empty()) upload_list(G, ol.adj64, G.adj64);
+    if (!ol.ana64.empty()) upload_list(G.owned, ol.ana64, G.ana64);
+    if (!ol.ana32.empty()) upload_list(G.owned, ol.ana32, G.ana32);
+    if (!ol.ana32_b64.empty()) upload_list(G.owned, ol.ana32_b64, G.ana32_b64);
+    if (!ol.syn64.empty()) upload_list(G.owned, ol.syn64, G.syn64);
+    if (!ol.adj64.empty()) upload_list(G.owned, ol.adj64, G.adj64);
 }
 
 // Staged lists of one group from its device tables (extents checked, then
@@ -1000,25 +1024,25 @@ void build_staged_lists(hp2sph_plan_t plan, Group& G) {
     }
     auto syn = staged_synthesis_problems(G, t64);
     require_extents<double>(syn, ext, G.bytes_U, G.bytes_D);
-    upload_list(G, syn, G.syn64_staged);
+    upload_list(G.owned, syn, G.syn64_staged);
     if (G.tables) return;
     if (plan->mode == HP2SPH_EQUAL_WEIGHT) {
         auto v = staged_adjoint_problems(G, t64);
         require_extents<double>(v, ext, G.bytes_D, G.bytes_U);
-        upload_list(G, v, G.adj64);
+        upload_list(G.owned, v, G.adj64);
     } else if (plan->mode == HP2SPH_F64) {
         auto v = staged_analysis_problems<double>(G, t64);
         require_extents<double>(v, ext, G.bytes_D, G.bytes_U);
-        upload_list(G, v, G.ana64);
+        upload_list(G.owned, v, G.ana64);
     } else {
         if (plan->mode == HP2SPH_F32_REFINE) {
             auto v = staged_analysis_problems<float>(G, t32);
             require_extents<float>(v, ext, G.bytes_D, G.bytes_U);
-            upload_list(G, v, G.ana32);
+            upload_list(G.owned, v, G.ana32);
         }
         auto w = staged_analysis_problems<float, double>(G, t32);
         require_extents<float, double>(w, ext, G.bytes_D, G.bytes_U);
-        upload_list(G, w, G.ana32_b64);
+        upload_list(G.owned, w, G.ana32_b64);
     }
 }
 
@@ -1052,24 +1076,51 @@ DevTables<double>& tabs<double>(Group& G) { return G.t64; }
 template <>
 DevTables<float>& tabs<float>(Group& G) { return G.t32; }
 
-// One analysis pass of one group, colatitude fit and conversion in precision
-// T: maps_in -> alm.  The ring transform and pole values are FP64 in both
-// precisions (for T = float this is the first pass of the refinement: the
-// GEMM rounds the FP64 ring coefficients to FP32 as it stages them).
+// Work-list launch over groups [first, first + n) of the plan.
+GroupLaunch span_launch(hp2sph_plan_t plan, int first, int n, void* ws, int grid_cap = 0) {
+    return GroupLaunch{plan->d_gdesc, plan->gdesc.data(), first, n, static_cast<char*>(ws), grid_cap};
+}
+GroupLaunch all_groups(hp2sph_plan_t plan, void* ws, int grid_cap = 0) {
+    return span_launch(plan, 0, int(plan->groups.size()), ws, grid_cap);
+}
+
+// S1 of every group into region `reg`: one launch per span of groups that
+// share the ring kernels' thread count.
+int ring_forward_all(hp2sph_plan_t plan, const double* maps, int reg, void* ws, hipStream_t s) {
+    for (const auto& sp : plan->ring_spans)
+        STAGE(0, launch_ring_forward(maps, span_launch(plan, sp.first, sp.second, ws), reg, s));
+    return HP2SPH_OK;
+}
+
 template <class T>
-int analysis_pass(Group& G, const double* maps_in, double* alm, void* ws, hipStream_t s) {
-    DevTables<T>& t = tabs<T>(G);
-    Blocks4<double> D = blocks_at<double>(ws, G.off_D, G, G.rows_D);
-    Blocks4<T> U = blocks_at<T>(ws, G.off_U, G, G.rows_U);
-    STAGE(0, launch_ring_forward<double>(maps_in, G.d_map_off, G.rings, G.t64.fft, D, G.dims, s));
-    STAGE(1, launch_pole<double>(D, G.dims, G.pole_w[0], G.pole_w[1], G.pole_w[2], s));
-    const GemmList<T>& gl = gemm_list<T>(G);
-    STAGE(2, (launch_gemm<T, double>(gl.dev, gl.tmap, gl.slots, D.p[0], U.p[0], s)));
-    Blocks4<const T> Gv;
-    for (int b = 0; b < 4; ++b) Gv.p[b] = t.givens[b];
-    if (!G.tables) STAGE(3, launch_sweep_fwd<T>(U, Gv, G.dims, s));
-    STAGE(4, launch_pack<T>(cblocks(U), Blocks4<const T>{}, alm, G.d_alm_off, G.d_lmax, G.d_pack_tiles,
-                            G.n_pack_tiles, G.dims, s));
+const GemmList<T>& merged_analysis(const hp2sph_plan_s* plan);
+template <>
+const GemmList<double>& merged_analysis<double>(const hp2sph_plan_s* plan) { return plan->m_ana64; }
+template <>
+const GemmList<float>& merged_analysis<float>(const hp2sph_plan_s* plan) { return plan->m_ana32_b64; }
+
+// One analysis of every group, colatitude fit and conversion in precision T:
+// maps -> alm.  Each stage is one work-list launch over all groups (the
+// GEMM one launch over the merged problem list); the Givens sweeps of groups
+// on the staged strategy run per group.  The ring transform and pole values
+// are FP64 in both precisions (for T = float this is the first pass of the
+// refinement: the GEMM rounds the FP64 ring coefficients to FP32 as it
+// stages them).
+template <class T>
+int analysis_all(hp2sph_plan_t plan, const double* maps, double* alm, void* ws, hipStream_t s) {
+    if (int e = ring_forward_all(plan, maps, kRegD, ws, s)) return e;
+    STAGE(1, launch_pole<double>(all_groups(plan, ws), kRegD, s));
+    const GemmList<T>& gl = merged_analysis<T>(plan);
+    STAGE(2, (launch_gemm<T, double>(gl.dev, gl.tmap, gl.slots, static_cast<const double*>(ws), static_cast<T*>(ws),
+                                     s)));
+    for (auto& gp : plan->groups) {
+        Group& G = *gp;
+        if (G.tables) continue;
+        Blocks4<const T> Gv;
+        for (int b = 0; b < 4; ++b) Gv.p[b] = tabs<T>(G).givens[b];
+        STAGE(3, launch_sweep_fwd<T>(blocks_at<T>(ws, G.off_U, G, G.rows_U), Gv, G.dims, s));
+    }
+    STAGE(4, launch_pack<T>(all_groups(plan, ws), kRegU, -1, alm, s));
     return HP2SPH_OK;
 }
 
@@ -1104,8 +1155,8 @@ int synthesis_pass(Group& G, const double* alm, double* out, const double* minus
     return HP2SPH_OK;
 }
 
-// FP32 analysis with one FP64 refinement of one group (Sec. 2.2, eq. uzawa,
-// with A the FP32 analysis and S the FP64 synthesis):
+// FP32 analysis with one FP64 refinement (Sec. 2.2, eq. uzawa, with A the
+// FP32 analysis and S the FP64 synthesis), every group at once:
 //   a0 = A32 f,  a1 = a0 + A32 (f - S a0).
 // The residual is formed after the ring transform, which is linear:
 // Ring(f - S a0) = Ring(f) - Ring(S a0).  Ring(f) is computed once in FP64;
@@ -1113,39 +1164,47 @@ int synthesis_pass(Group& G, const double* alm, double* out, const double* minus
 // (k_residual_fold), exactly what an inverse and a forward ring FFT would
 // give, without the two transforms.  The residual enters the FP32 stages
 // rounded to FP32 (FP32 colatitude fit and Legendre conversion).
-int refine_pass(hp2sph_plan_t plan, Group& G, const double* maps, double* alm, void* ws, hipStream_t s) {
-    Blocks4<float> Ua = blocks_at<float>(ws, plan->off_Ua, G, G.rows_U);   // a0, kept to the end
-    Blocks4<float> Ub = blocks_at<float>(ws, G.off_U, G, G.rows_U);        // the correction
-    Blocks4<double> U64 = blocks_at<double>(ws, G.off_U, G, G.rows_U);
-    Blocks4<double> Gs = blocks_at<double>(ws, G.off_D, G, G.rows_D);
-    Blocks4<double> Df = blocks_at<double>(ws, plan->off_Df, G, G.rows_D);
-    Blocks4<float> Dr = blocks_at<float>(ws, plan->off_Dr, G, G.rows_D);
-    const GemmList<float>& ga = G.ana32;
-    const GemmList<float>& gb = G.ana32_b64;
-    Blocks4<const float> Gv32;
-    for (int b = 0; b < 4; ++b) Gv32.p[b] = G.t32.givens[b];
-    // a0 = A32 f: FP64 ring coefficients, rounded to FP32 as the GEMM stages them
-    STAGE(0, launch_ring_forward<double>(maps, G.d_map_off, G.rings, G.t64.fft, Df, G.dims, s));
-    STAGE(1, launch_pole<double>(Df, G.dims, G.pole_w[0], G.pole_w[1], G.pole_w[2], s));
-    STAGE(2, (launch_gemm<float, double>(gb.dev, gb.tmap, gb.slots, Df.p[0], Ua.p[0], s)));
-    if (!G.tables) STAGE(3, launch_sweep_fwd<float>(Ua, Gv32, G.dims, s));
+int refine_all(hp2sph_plan_t plan, const double* maps, double* alm, void* ws, hipStream_t s) {
+    auto staged_sweeps = [&](int region, bool fwd) -> int {
+        for (auto& gp : plan->groups) {
+            Group& G = *gp;
+            if (G.tables) continue;
+            if (fwd) {
+                Blocks4<const float> Gv32;
+                for (int b = 0; b < 4; ++b) Gv32.p[b] = G.t32.givens[b];
+                const size_t off = region == kRegUa ? G.off_Ua : G.off_U;
+                STAGE(3, launch_sweep_fwd<float>(blocks_at<float>(ws, off, G, G.rows_U), Gv32, G.dims, s));
+            } else {
+                Blocks4<const double> Gv;
+                for (int b = 0; b < 4; ++b) Gv.p[b] = G.t64.givens[b];
+                STAGE(6, launch_sweep_bwd<double>(blocks_at<double>(ws, G.off_U, G, G.rows_U), Gv, G.dims, s));
+            }
+        }
+        return HP2SPH_OK;
+    };
+    const double* wsd = static_cast<const double*>(ws);
+    // a0 = A32 f: FP64 ring coefficients (region Df), rounded to FP32 as the
+    // GEMM stages them; a0 in region Ua
+    if (int e = ring_forward_all(plan, maps, kRegDf, ws, s)) return e;
+    STAGE(1, launch_pole<double>(all_groups(plan, ws), kRegDf, s));
+    const GemmList<float>& gb = plan->m_ana32_b64;
+    STAGE(2, (launch_gemm<float, double>(gb.dev, gb.tmap, gb.slots, wsd, static_cast<float*>(ws), s)));
+    if (int e = staged_sweeps(kRegUa, true)) return e;
     // S a0 up to the inverse ring transform (FP64): a0 widened to FP64 (and
-    // truncated at each map's lmax), then the synthesis GEMM
-    STAGE(5, launch_widen(cblocks(Ua), U64, G.d_lmax, G.dims, G.tables, s));
-    if (!G.tables) {
-        Blocks4<const double> Gv;
-        for (int b = 0; b < 4; ++b) Gv.p[b] = G.t64.givens[b];
-        STAGE(6, launch_sweep_bwd<double>(U64, Gv, G.dims, s));
-    }
-    const GemmList<double>& gs = G.tables ? G.syn64 : G.syn64_staged;
-    STAGE(7, launch_gemm<double>(gs.dev, gs.tmap, gs.slots, U64.p[0], Gs.p[0], s));
-    // residual ring coefficients, the correction A32 r, and a1 = a0 + A32 r
-    STAGE(10, launch_residual_fold(cblocks(Df), cblocks(Gs), Dr, G.rings, G.t64.fft, G.dims, s));
-    STAGE(1, launch_pole<float>(Dr, G.dims, G.pole_w[0], G.pole_w[1], G.pole_w[2], s));
-    STAGE(2, launch_gemm<float>(ga.dev, ga.tmap, ga.slots, Dr.p[0], Ub.p[0], s));
-    if (!G.tables) STAGE(3, launch_sweep_fwd<float>(Ub, Gv32, G.dims, s));
-    STAGE(4, launch_pack<float>(cblocks(Ua), cblocks(Ub), alm, G.d_alm_off, G.d_lmax, G.d_pack_tiles,
-                                G.n_pack_tiles, G.dims, s));
+    // truncated at each map's lmax) into region U, then the synthesis GEMM
+    // into region D
+    STAGE(5, launch_widen(all_groups(plan, ws), s));
+    if (int e = staged_sweeps(kRegU, false)) return e;
+    const GemmList<double>& gs = plan->m_syn64;
+    STAGE(7, launch_gemm<double>(gs.dev, gs.tmap, gs.slots, wsd, static_cast<double*>(ws), s));
+    // residual ring coefficients (region Dr), the correction A32 r (region
+    // U), and a1 = a0 + A32 r
+    STAGE(10, launch_residual_fold(all_groups(plan, ws, plan->fold_grid), s));
+    STAGE(1, launch_pole<float>(all_groups(plan, ws), kRegDr, s));
+    const GemmList<float>& ga = plan->m_ana32;
+    STAGE(2, launch_gemm<float>(ga.dev, ga.tmap, ga.slots, static_cast<const float*>(ws), static_cast<float*>(ws), s));
+    if (int e = staged_sweeps(kRegU, true)) return e;
+    STAGE(4, launch_pack<float>(all_groups(plan, ws), kRegUa, kRegU, alm, s));
     return HP2SPH_OK;
 }
 
@@ -1164,13 +1223,11 @@ int equal_weight_apply(hp2sph_plan_t plan, Group& G, Blocks4<double> W, double* 
         STAGE(3, launch_sweep_fwd<double>(U, Gv, G.dims, s));
     }
     if (add) {
-        Blocks4<double> Ua = blocks_at<double>(ws, plan->off_Ua, G, G.rows_U);
+        Blocks4<double> Ua = blocks_at<double>(ws, G.off_Ua, G, G.rows_U);
         STAGE(5, launch_unpack(alm, G.d_alm_off, G.d_lmax, Ua, G.dims, s));
-        STAGE(4, launch_pack<double>(cblocks(Ua), cblocks(U), alm, G.d_alm_off, G.d_lmax, G.d_pack_tiles,
-                                     G.n_pack_tiles, G.dims, s));
+        STAGE(4, launch_pack<double>(span_launch(plan, G.index, 1, ws), kRegUa, kRegU, alm, s));
     } else {
-        STAGE(4, launch_pack<double>(cblocks(U), Blocks4<const double>{}, alm, G.d_alm_off, G.d_lmax,
-                                     G.d_pack_tiles, G.n_pack_tiles, G.dims, s));
+        STAGE(4, launch_pack<double>(span_launch(plan, G.index, 1, ws), kRegU, -1, alm, s));
     }
     return HP2SPH_OK;
 }
@@ -1181,8 +1238,8 @@ int equal_weight_apply(hp2sph_plan_t plan, Group& G, Blocks4<double> W, double* 
 // Wf = W(f) computed once and W(S a) formed from the synthesis coefficients
 // (k_adjoint_residual): the residual map is never materialised.
 int jacobi_pass(hp2sph_plan_t plan, Group& G, const double* maps, double* alm, int niter, void* ws, hipStream_t s) {
-    Blocks4<double> Wf = blocks_at<double>(ws, plan->off_Wf, G, G.rows_D);
-    Blocks4<double> Wr = blocks_at<double>(ws, plan->off_Wr, G, G.rows_D);
+    Blocks4<double> Wf = blocks_at<double>(ws, G.off_Wf, G, G.rows_D);
+    Blocks4<double> Wr = blocks_at<double>(ws, G.off_Wr, G, G.rows_D);
     Blocks4<double> Gs = blocks_at<double>(ws, G.off_D, G, G.rows_D);
     const double scale = 4.0 * 3.14159265358979323846 / (12.0 * double(G.nside) * double(G.nside));
     STAGE(11, launch_ring_adjoint(maps, G.d_map_off, G.rings, G.t64.fft, Wf, G.dims, scale, s));
@@ -1190,7 +1247,7 @@ int jacobi_pass(hp2sph_plan_t plan, Group& G, const double* maps, double* alm, i
         // per-order tables: a stays in the U layout both GEMMs use (truncated
         // at each map's lmax) and is packed once at the end
         Blocks4<double> U = blocks_at<double>(ws, G.off_U, G, G.rows_U);
-        Blocks4<double> Ua = blocks_at<double>(ws, plan->off_Ua, G, G.rows_U);
+        Blocks4<double> Ua = blocks_at<double>(ws, G.off_Ua, G, G.rows_U);
         STAGE(12, launch_gemm<double>(G.adj64.dev, G.adj64.tmap, G.adj64.slots, Wf.p[0], U.p[0], s));
         STAGE(5, launch_accumulate(cblocks(U), Ua, G.d_lmax, G.dims, true, s));
         for (int it = 0; it < niter; ++it) {
@@ -1199,8 +1256,7 @@ int jacobi_pass(hp2sph_plan_t plan, Group& G, const double* maps, double* alm, i
             STAGE(12, launch_gemm<double>(G.adj64.dev, G.adj64.tmap, G.adj64.slots, Wr.p[0], U.p[0], s));
             STAGE(5, launch_accumulate(cblocks(U), Ua, G.d_lmax, G.dims, false, s));
         }
-        STAGE(4, launch_pack<double>(cblocks(Ua), Blocks4<const double>{}, alm, G.d_alm_off, G.d_lmax,
-                                     G.d_pack_tiles, G.n_pack_tiles, G.dims, s));
+        STAGE(4, launch_pack<double>(span_launch(plan, G.index, 1, ws), kRegUa, -1, alm, s));
         return HP2SPH_OK;
     }
     if (int e = equal_weight_apply(plan, G, Wf, alm, false, ws, s)) return e;
@@ -1210,6 +1266,215 @@ int jacobi_pass(hp2sph_plan_t plan, Group& G, const double* maps, double* alm, i
         if (int e = equal_weight_apply(plan, G, Wr, alm, true, ws, s)) return e;
     }
     return HP2SPH_OK;
+}
+
+// Byte offset and size of region r of a group.
+std::pair<size_t, size_t> region_span(const Group& G, int r) {
+    switch (r) {
+        case kRegD: return {G.off_D, G.bytes_D};
+        case kRegU: return {G.off_U, G.bytes_U};
+        case kRegDf: return {G.off_Df, G.bytes_D};
+        case kRegDr: return {G.off_Dr, G.bytes_D};
+        default: return {G.off_Ua, G.bytes_U};
+    }
+}
+
+// The problems one role's GEMM runs for every group, moved from their
+// group's region bases (B in region breg, C in region creg) to the workspace
+// base, into one list: one launch then serves all groups, its problems
+// sorted longest first across groups.  Every rebased problem is checked to
+// stay inside its group's regions (the per-group lists were checked against
+// the region sizes when they were built).
+template <class T, class TB, class Pick>
+void merge_role(hp2sph_plan_t plan, Pick pick, int breg, int creg, GemmList<T>& out) {
+    std::vector<GemmProblem<T>> v;
+    for (auto& gp : plan->groups) {
+        Group& G = *gp;
+        const GemmList<T>* L = pick(G);
+        if (!L || L->host.empty()) continue;
+        const auto bsp = region_span(G, breg);
+        const auto csp = region_span(G, creg);
+        for (GemmProblem<T> P : L->host) {
+            P.boff += int64_t(bsp.first / sizeof(TB));
+            P.coff += int64_t(csp.first / sizeof(T));
+            const int64_t bmax = P.boff + int64_t(P.K - 1) * P.ldb + int64_t((P.N - 1) >> 1) * P.bps + 1;
+            const int64_t cmax = P.coff + int64_t(P.M - 1) * P.ldc + int64_t((P.N - 1) >> 1) * P.cps + 1;
+            const bool b_in = P.K == 0 || (uint64_t(P.boff) * sizeof(TB) >= bsp.first &&
+                                           uint64_t(bmax + 1) * sizeof(TB) <= bsp.first + bsp.second);
+            const bool c_in = uint64_t(P.coff) * sizeof(T) >= csp.first &&
+                              uint64_t(cmax + 1) * sizeof(T) <= csp.first + csp.second;
+            if (!b_in || !c_in) throw std::runtime_error("merged GEMM problem outside its group's workspace regions");
+            v.push_back(P);
+        }
+    }
+    if (!v.empty()) upload_list(plan->owned, v, out);
+}
+
+// Device descriptors of the groups (regions at their final offsets), the
+// ring kernels' spans, the merged GEMM lists of the analysis and the
+// batch-wide per-map arrays.  Run once the workspace layout is fixed.
+void build_work_lists(hp2sph_plan_t plan) {
+    const int mode = plan->mode;
+    plan->gdesc.clear();
+    for (auto& gp : plan->groups) {
+        const Group& G = *gp;
+        GroupDesc d{};
+        d.g = G.dims;
+        d.rt = G.rings;
+        d.ft = G.t64.fft;
+        d.map_off = G.d_map_off;
+        d.alm_off = G.d_alm_off;
+        d.lmax = G.d_lmax;
+        d.pack_tiles = G.d_pack_tiles;
+        d.n_pack_tiles = G.n_pack_tiles;
+        d.tables = G.tables ? 1 : 0;
+        for (int i = 0; i < 3; ++i) d.pole_w[i] = G.pole_w[i];
+        for (int r = 0; r < kRegions; ++r)
+            for (int b = 0; b < 4; ++b) d.reg[r][b] = -1;
+        const bool has_df = mode == HP2SPH_F32_REFINE, has_ua = has_df || mode == HP2SPH_EQUAL_WEIGHT;
+        for (int b = 0; b < 4; ++b) {
+            d.reg[kRegD][b] = int64_t(G.off_D + G.blk_off_D[b]);
+            d.reg[kRegU][b] = int64_t(G.off_U + G.blk_off_U[b]);
+            if (has_df) {
+                d.reg[kRegDf][b] = int64_t(G.off_Df + G.blk_off_D[b]);
+                d.reg[kRegDr][b] = int64_t(G.off_Dr + G.blk_off_D[b]);
+            }
+            if (has_ua) d.reg[kRegUa][b] = int64_t(G.off_Ua + G.blk_off_U[b]);
+        }
+        plan->gdesc.push_back(d);
+    }
+    plan->d_gdesc = upload_int(plan->owned, plan->gdesc);
+    // spans of consecutive groups (descending nside) whose ring kernels run
+    // the same thread count
+    plan->ring_spans.clear();
+    for (int i = 0; i < int(plan->groups.size()); ++i) {
+        const int nt = ring_threads(plan->gdesc[i].ft.fft_max);
+        if (!plan->ring_spans.empty()) {
+            auto& last = plan->ring_spans.back();
+            if (ring_threads(plan->gdesc[last.first].ft.fft_max) == nt && last.second < kMaxGroups) {
+                ++last.second;
+                continue;
+            }
+        }
+        plan->ring_spans.push_back({i, 1});
+    }
+    switch (mode) {
+        case HP2SPH_F64:
+            merge_role<double, double>(plan, [](Group& G) { return &G.ana64; }, kRegD, kRegU, plan->m_ana64);
+            break;
+        case HP2SPH_F32:
+            merge_role<float, double>(plan, [](Group& G) { return &G.ana32_b64; }, kRegD, kRegU, plan->m_ana32_b64);
+            break;
+        case HP2SPH_F32_REFINE:
+            merge_role<float, double>(plan, [](Group& G) { return &G.ana32_b64; }, kRegDf, kRegUa,
+                                      plan->m_ana32_b64);
+            merge_role<double, double>(plan, [](Group& G) { return G.tables ? &G.syn64 : &G.syn64_staged; }, kRegU,
+                                       kRegD, plan->m_syn64);
+            merge_role<float, float>(plan, [](Group& G) { return &G.ana32; }, kRegDr, kRegU, plan->m_ana32);
+            break;
+        default:
+            break;   // the equal-weight analysis runs per group
+    }
+    std::vector<int64_t> ao(plan->alm_off.begin(), plan->alm_off.end()), co(plan->cl_off.begin(), plan->cl_off.end());
+    plan->d_alm_off = upload_int(plan->owned, ao);
+    plan->d_cl_off = upload_int(plan->owned, co);
+    plan->d_lmax = upload_int(plan->owned, plan->lmax);
+    plan->lmax_max = 0;
+    for (int32_t l : plan->lmax) plan->lmax_max = std::max(plan->lmax_max, int(l));
+}
+
+// ---------------------------------------------------------------------------
+// Tuning cache: the autotuner's choices keyed by plan shape
+// ---------------------------------------------------------------------------
+//
+// Key: the device's architecture and compute-unit count, the mode and, per
+// group, nside, number of maps and strategy.  Value: the schedule of every
+// tuned GEMM (in the order hp2sph_schedules reports them) and the fold's
+// work grid.  Kept per process; HP2SPH_TUNE_CACHE names a text file that is read
+// once and appended to (one "key = values" line per entry, the last line of
+// a key wins), so tuned shapes start tuned in later processes too.
+
+struct TuneChoice {
+    std::vector<int> sched;
+    int fold_grid = 0;
+};
+
+std::mutex g_tune_mu;
+std::map<std::string, TuneChoice>& tune_cache() {
+    static std::map<std::string, TuneChoice> m;
+    return m;
+}
+bool g_tune_file_read = false;
+
+int device_cus(int device) {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cus <= 0)
+        cus = 256;
+    return cus;
+}
+
+std::string tune_key(const hp2sph_plan_s* plan) {
+    hipDeviceProp_t prop{};
+    std::string arch = "unknown";
+    if (hipGetDeviceProperties(&prop, plan->device) == hipSuccess) arch = prop.gcnArchName;
+    std::string k = arch + "/" + std::to_string(device_cus(plan->device)) + "/mode" + std::to_string(plan->mode);
+    for (const auto& g : plan->groups)
+        k += "/" + std::to_string(g->nside) + "x" + std::to_string(g->dims.nmaps) + (g->tables ? "t" : "s");
+    return k;
+}
+
+void read_tune_file_locked() {
+    if (g_tune_file_read) return;
+    g_tune_file_read = true;
+    const char* path = std::getenv("HP2SPH_TUNE_CACHE");
+    if (!path || !*path) return;
+    FILE* f = std::fopen(path, "r");
+    if (!f) return;
+    char line[4096];
+    while (std::fgets(line, sizeof line, f)) {
+        std::string l(line);
+        const size_t eq = l.find(" = ");
+        if (eq == std::string::npos) continue;
+        TuneChoice c;
+        std::vector<long> v;
+        const char* q = l.c_str() + eq + 3;
+        char* end = nullptr;
+        for (long x = std::strtol(q, &end, 10); end != q; x = std::strtol(q, &end, 10)) {
+            v.push_back(x);
+            q = end;
+        }
+        if (v.empty()) continue;
+        c.fold_grid = int(v[0]);
+        for (size_t i = 1; i < v.size(); ++i) c.sched.push_back(int(v[i]));
+        tune_cache()[l.substr(0, eq)] = c;
+    }
+    std::fclose(f);
+}
+
+void store_tune(const hp2sph_plan_s* plan, const TuneChoice& c) {
+    const std::string key = tune_key(plan);
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    read_tune_file_locked();
+    tune_cache()[key] = c;
+    const char* path = std::getenv("HP2SPH_TUNE_CACHE");
+    if (!path || !*path) return;
+    if (FILE* f = std::fopen(path, "a")) {
+        std::string line = key + " = " + std::to_string(c.fold_grid);
+        for (int x : c.sched) line += " " + std::to_string(x);
+        line += "\n";
+        std::fputs(line.c_str(), f);
+        std::fclose(f);
+    }
+}
+
+bool lookup_tune(const hp2sph_plan_s* plan, TuneChoice& c) {
+    const std::string key = tune_key(plan);
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    read_tune_file_locked();
+    auto it = tune_cache().find(key);
+    if (it == tune_cache().end()) return false;
+    c = it->second;
+    return true;
 }
 
 bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
@@ -1238,33 +1503,44 @@ int check_workspace(hp2sph_plan_t plan, const void* workspace, size_t bytes) {
     return HP2SPH_OK;
 }
 
-// The grouped GEMMs hp2sph_analyze launches for one group, in launch order.
-void analysis_lists(const hp2sph_plan_s* plan, Group& G, std::vector<GemmSched*>& out) {
+// The grouped GEMMs hp2sph_analyze launches, in launch order: the merged
+// lists of the analysis modes, or each group's lists of the equal-weight
+// analysis.
+void analysis_lists(hp2sph_plan_t plan, std::vector<GemmSched*>& out) {
     auto add = [&](GemmSched& L, int n) {
         if (n > 0) out.push_back(&L);
     };
-    GemmList<double>& syn = G.tables ? G.syn64 : G.syn64_staged;
     switch (plan->mode) {
-        case HP2SPH_F64: add(G.ana64, G.ana64.n); break;
-        case HP2SPH_F32: add(G.ana32_b64, G.ana32_b64.n); break;
+        case HP2SPH_F64: add(plan->m_ana64, plan->m_ana64.n); break;
+        case HP2SPH_F32: add(plan->m_ana32_b64, plan->m_ana32_b64.n); break;
         case HP2SPH_F32_REFINE:
-            add(G.ana32_b64, G.ana32_b64.n);
-            add(syn, syn.n);
-            add(G.ana32, G.ana32.n);
+            add(plan->m_ana32_b64, plan->m_ana32_b64.n);
+            add(plan->m_syn64, plan->m_syn64.n);
+            add(plan->m_ana32, plan->m_ana32.n);
             break;
         default:   // equal weight: transposed evaluation, then the synthesis of each iteration
-            add(G.adj64, G.adj64.n);
-            add(syn, syn.n);
+            for (auto& g : plan->groups) {
+                Group& G = *g;
+                GemmList<double>& syn = G.tables ? G.syn64 : G.syn64_staged;
+                add(G.adj64, G.adj64.n);
+                add(syn, syn.n);
+            }
             break;
     }
 }
 
-// Every GEMM list the plan built (the analyses, synthesis and adjoint).
-void built_lists(Group& G, std::vector<GemmSched*>& out) {
-    for (GemmSched* L : {static_cast<GemmSched*>(&G.ana64), static_cast<GemmSched*>(&G.syn64),
-                         static_cast<GemmSched*>(&G.syn64_staged), static_cast<GemmSched*>(&G.adj64),
-                         static_cast<GemmSched*>(&G.ana32), static_cast<GemmSched*>(&G.ana32_b64)})
+// Every GEMM list the plan built (merged and per group).
+void built_lists(hp2sph_plan_t plan, std::vector<GemmSched*>& out) {
+    for (GemmSched* L : {static_cast<GemmSched*>(&plan->m_ana64), static_cast<GemmSched*>(&plan->m_syn64),
+                         static_cast<GemmSched*>(&plan->m_ana32_b64), static_cast<GemmSched*>(&plan->m_ana32)})
         if (L->maps[0]) out.push_back(L);
+    for (auto& g : plan->groups) {
+        Group& G = *g;
+        for (GemmSched* L : {static_cast<GemmSched*>(&G.ana64), static_cast<GemmSched*>(&G.syn64),
+                             static_cast<GemmSched*>(&G.syn64_staged), static_cast<GemmSched*>(&G.adj64),
+                             static_cast<GemmSched*>(&G.ana32), static_cast<GemmSched*>(&G.ana32_b64)})
+            if (L->maps[0]) out.push_back(L);
+    }
 }
 
 }  // namespace
@@ -1316,8 +1592,6 @@ int hp2sph_plan_create_ex(const int32_t* nside, const int32_t* lmax, int32_t bat
         plan->total_cl = co;
         std::map<int, std::vector<int>> bys;
         for (int b = 0; b < batch; ++b) bys[nside[b]].push_back(b);
-        size_t ws = 0;
-        size_t max_group = 0;
         for (auto it = bys.rbegin(); it != bys.rend(); ++it) {
             auto G = std::make_unique<Group>();
             G->nside = it->first;
@@ -1341,38 +1615,51 @@ int hp2sph_plan_create_ex(const int32_t* nside, const int32_t* lmax, int32_t bat
                                                std::to_string(order_table_bytes(*G, mode) >> 20) + " MiB, " +
                                                std::to_string(fre >> 20) + " MiB of device memory are free");
             build_group(plan.get(), *G);
-            G->off_D = 0;
-            G->off_U = align_up(G->bytes_D);
             G->tables = tables;
             set_layout(G->dims, tables);
             build_staged_lists(plan.get(), *G);
             if (tables) build_order_tables(plan.get(), *G);
-            max_group = std::max(max_group, G->off_U + align_up(G->bytes_U));
+            G->index = int(plan->groups.size());
             plan->groups.push_back(std::move(G));
         }
-        ws = max_group;   // groups run one after another and share the buffers
-        if (mode == HP2SPH_F32_REFINE) {
-            size_t max_D = 0, max_U = 0;
-            for (auto& g : plan->groups) {
-                max_D = std::max(max_D, align_up(g->bytes_D));
-                max_U = std::max(max_U, align_up(g->bytes_U));
+        if (int(plan->groups.size()) > kMaxGroups) return fail(HP2SPH_EINVAL, "too many distinct nside values");
+        // workspace: every group its own regions, back to back
+        size_t ws = 0;
+        auto take = [&](size_t bytes) {
+            const size_t at = ws;
+            ws += align_up(bytes);
+            return at;
+        };
+        for (auto& g : plan->groups) {
+            Group& G = *g;
+            G.off_D = take(G.bytes_D);
+            G.off_U = take(G.bytes_U);
+            if (mode == HP2SPH_F32_REFINE) {
+                G.off_Df = take(G.bytes_D);
+                G.off_Dr = take(G.bytes_D);
+                G.off_Ua = take(G.bytes_U);
+            } else if (mode == HP2SPH_EQUAL_WEIGHT) {
+                G.off_Ua = take(G.bytes_U);
+                G.off_Wf = take(G.bytes_D);
+                G.off_Wr = take(G.bytes_D);
             }
-            plan->off_Df = ws;
-            plan->off_Dr = ws + max_D;
-            plan->off_Ua = ws + 2 * max_D;
-            ws += 2 * max_D + max_U;
-        } else if (mode == HP2SPH_EQUAL_WEIGHT) {
-            size_t max_D = 0, max_U = 0;
-            for (auto& g : plan->groups) {
-                max_D = std::max(max_D, align_up(g->bytes_D));
-                max_U = std::max(max_U, align_up(g->bytes_U));
-            }
-            plan->off_Ua = ws;
-            plan->off_Wf = ws + max_U;
-            plan->off_Wr = ws + max_U + max_D;
-            ws += max_U + 2 * max_D;
         }
+        build_work_lists(plan.get());
         plan->ws_bytes = ws;
+        // a shape the autotuner has seen (in this process, or in the
+        // HP2SPH_TUNE_CACHE file) starts with its choices
+        {
+            TuneChoice c;
+            if (lookup_tune(plan.get(), c)) {
+                std::vector<GemmSched*> lists;
+                analysis_lists(plan.get(), lists);
+                if (c.sched.size() == lists.size()) {
+                    for (size_t i = 0; i < lists.size(); ++i)
+                        if (c.sched[i] >= 0 && c.sched[i] < HP2SPH_NSCHED) lists[i]->use(c.sched[i]);
+                    plan->fold_grid = c.fold_grid;
+                }
+            }
+        }
         // kernels with more than 64 KB of dynamic LDS
         if (configure_kernels() != hipSuccess) return fail(HP2SPH_EDEVICE, "hipFuncSetAttribute failed");
         // device address of this device's static workspace (for
@@ -1418,19 +1705,15 @@ int hp2sph_analyze(hp2sph_plan_t plan, const double* maps, double* alm, void* wo
     if (!aligned(maps, 16) || !aligned(alm, 16)) return fail(HP2SPH_EINVAL, "maps/alm not 16-byte aligned");
     if (int e = check_workspace(plan, workspace, workspace_bytes)) return e;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    for (auto& gp : plan->groups) {
-        Group& G = *gp;
-        if (plan->mode == HP2SPH_F64) {
-            if (int e = analysis_pass<double>(G, maps, alm, workspace, s)) return e;
-        } else if (plan->mode == HP2SPH_F32) {
-            if (int e = analysis_pass<float>(G, maps, alm, workspace, s)) return e;
-        } else if (plan->mode == HP2SPH_EQUAL_WEIGHT) {
-            if (int e = jacobi_pass(plan, G, maps, alm, kDefaultJacobi, workspace, s)) return e;
-        } else {
-            if (int e = refine_pass(plan, G, maps, alm, workspace, s)) return e;
-        }
+    switch (plan->mode) {
+        case HP2SPH_F64: return analysis_all<double>(plan, maps, alm, workspace, s);
+        case HP2SPH_F32: return analysis_all<float>(plan, maps, alm, workspace, s);
+        case HP2SPH_F32_REFINE: return refine_all(plan, maps, alm, workspace, s);
+        default:
+            for (auto& gp : plan->groups)
+                if (int e = jacobi_pass(plan, *gp, maps, alm, kDefaultJacobi, workspace, s)) return e;
+            return HP2SPH_OK;
     }
-    return HP2SPH_OK;
 }
 
 static_assert(kScratchBytes == HP2SPH_NOALLOC_WORKSPACE, "static workspace size of the C ABI");
@@ -1486,10 +1769,7 @@ int hp2sph_power_spectrum(hp2sph_plan_t plan, const double* alm, double* cl, voi
     if (!alm || !cl) return fail(HP2SPH_EINVAL, "alm/cl is null");
     if (!aligned(alm, 16) || !aligned(cl, 8)) return fail(HP2SPH_EINVAL, "alm/cl misaligned");
     hipStream_t s = static_cast<hipStream_t>(stream);
-    for (auto& gp : plan->groups) {
-        Group& G = *gp;
-        STAGE(9, launch_cl(alm, G.d_alm_off, G.d_lmax, cl, G.d_cl_off, G.dims.nmaps, G.lmax_max, s));
-    }
+    STAGE(9, launch_cl(alm, plan->d_alm_off, plan->d_lmax, cl, plan->d_cl_off, plan->batch, plan->lmax_max, s));
     return HP2SPH_OK;
 }
 
@@ -1521,7 +1801,7 @@ int hp2sph_set_schedule(hp2sph_plan_t plan, int32_t sched) {
     if (int e = check_plan(plan)) return e;
     if (sched < 0 || sched >= HP2SPH_NSCHED) return fail(HP2SPH_EINVAL, "unknown schedule");
     std::vector<GemmSched*> lists;
-    for (auto& g : plan->groups) built_lists(*g, lists);
+    built_lists(plan, lists);
     for (GemmSched* L : lists) L->use(sched);
     return HP2SPH_OK;
 }
@@ -1530,9 +1810,23 @@ int hp2sph_schedules(hp2sph_plan_t plan, int32_t* out, int32_t cap, int32_t* cou
     if (int e = check_plan(plan)) return e;
     if (!count || cap < 0 || (cap > 0 && !out)) return fail(HP2SPH_EINVAL, "bad arguments");
     std::vector<GemmSched*> lists;
-    for (auto& g : plan->groups) analysis_lists(plan, *g, lists);
+    analysis_lists(plan, lists);
     for (int i = 0; i < int(lists.size()) && i < cap; ++i) out[i] = lists[i]->sched;
     *count = int(lists.size());
+    return HP2SPH_OK;
+}
+
+int hp2sph_set_fold_grid(hp2sph_plan_t plan, int32_t grid) {
+    if (int e = check_plan(plan)) return e;
+    if (grid < 0 || (grid > 0 && grid < 8)) return fail(HP2SPH_EINVAL, "the fold grid is 0 or at least 8 workgroups");
+    plan->fold_grid = grid / 8 * 8;
+    return HP2SPH_OK;
+}
+
+int hp2sph_fold_grid(hp2sph_plan_t plan, int32_t* grid) {
+    if (int e = check_plan(plan)) return e;
+    if (!grid) return fail(HP2SPH_EINVAL, "null output");
+    *grid = plan->fold_grid;
     return HP2SPH_OK;
 }
 
@@ -1573,7 +1867,7 @@ int hp2sph_autotune(hp2sph_plan_t plan, const double* maps, double* alm, void* w
         return HP2SPH_OK;
     };
     std::vector<GemmSched*> lists;
-    for (auto& g : plan->groups) analysis_lists(plan, *g, lists);
+    analysis_lists(plan, lists);
     double best = 0.0;
     if (int e = timed(best)) return e;
     for (GemmSched* L : lists) {
@@ -1593,6 +1887,33 @@ int hp2sph_autotune(hp2sph_plan_t plan, const double* maps, double* alm, void* w
             }
             L->use(keep);
         }
+    }
+    // work grid of the refinement's fold: one workgroup per work item, or a
+    // persistent grid of 2 or 4 workgroups per compute unit walking the list
+    if (plan->mode == HP2SPH_F32_REFINE) {
+        const int cus = device_cus(plan->device);
+        const int cand[3] = {0, 2 * cus, 4 * cus};
+        int keep = plan->fold_grid;
+        for (int c : cand) {
+            if (c == keep) continue;
+            plan->fold_grid = c;
+            double t = 0.0;
+            if (int e = timed(t)) {
+                plan->fold_grid = keep;
+                return e;
+            }
+            if (t < best * (1.0 - 0.005)) {
+                best = t;
+                keep = c;
+            }
+            plan->fold_grid = keep;
+        }
+    }
+    {
+        TuneChoice c;
+        for (GemmSched* L : lists) c.sched.push_back(L->sched);
+        c.fold_grid = plan->fold_grid;
+        store_tune(plan, c);
     }
     // leave alm holding the analysis under the chosen schedules
     if (int e = hp2sph_analyze(plan, maps, alm, workspace, workspace_bytes, stream)) return e;

@@ -57,6 +57,55 @@ struct GroupDims {
     int modemajor;
 };
 
+// Workspace regions of one nside group (Dsym- or U-shaped, four blocks each):
+// D (Dsym; the synthesis GEMM output in the refinement), U (order-0/1 or
+// a_l^m coefficients; the FP64 a0 and then the FP32 correction in the
+// refinement), Df (FP64 ring coefficients of the maps), Dr (FP32 residual
+// coefficients), Ua (FP32 a0).  Every group of a plan has its own regions,
+// so that one launch can serve all groups.
+enum Region { kRegD = 0, kRegU = 1, kRegDf = 2, kRegDr = 3, kRegUa = 4, kRegions = 5 };
+
+// Everything the work-list kernels need of one group, in device memory (one
+// array per plan).  reg[r][b]: byte offset of block b of region r from the
+// workspace base (-1: the plan has no such region).
+struct GroupDesc {
+    GroupDims g;
+    RingTab rt;
+    FftTab<double> ft;
+    const int64_t* map_off;     // per member: first pixel of its map
+    const int64_t* alm_off;     // per member: first alm entry (complex)
+    const int32_t* lmax;        // per member
+    const int32_t* pack_tiles;  // (m, l0) of the pack tiles
+    int n_pack_tiles;
+    int tables;                 // per-order tables (mode-major columns)
+    double pole_w[3];
+    int64_t reg[kRegions][4];
+};
+
+// A work-list launch over groups first .. first + n - 1 of a plan's
+// GroupDesc array: group first + i owns work items [start[i], start[i] +
+// count[i]); every start is a multiple of 8, so an item's index modulo 8 is
+// the XCD the hardware deals its workgroup to (items past count are padding
+// and do nothing).  A launch of fewer workgroups than items (persistent)
+// walks the list with a stride of its grid size, a multiple of 8.
+constexpr int kMaxGroups = 16;
+struct GroupRange {
+    int first, n;
+    int32_t start[kMaxGroups + 1];
+    int32_t count[kMaxGroups];
+};
+
+// Host side of a work-list launch: the device descriptors, their host
+// copies (for the item counts), the group span, the workspace and the grid
+// cap (0: one workgroup per item; else the persistent grid size).
+struct GroupLaunch {
+    const GroupDesc* dev;
+    const GroupDesc* host;
+    int first, n;
+    char* ws;
+    int grid_cap;
+};
+
 // One product of a grouped GEMM: C[m][n] = sum_k A[k][m] B[k][n].
 // A is absolute (a set-up table); B and C are element offsets from the
 // launch's base pointers, so a problem list can be built once per plan and
@@ -154,11 +203,14 @@ int finalize_gemm_problems(GemmProblem<T>* p, int n);
 template <class T>
 std::vector<int32_t> xcd_tile_map(const GemmProblem<T>* p, int n);
 
+// Threads of the ring kernels for a plan whose largest FFT has fft_max points
+// (at most 16 complex values per thread).
+__host__ __device__ constexpr int ring_threads(int fft_max) { return fft_max <= 4096 ? 256 : 512; }
+
 // S1: per-ring real DFT, shift to unshifted longitudes, Nyquist rule and the
-// north/south combination, written into Dsym rows 1 .. 2 nside.
-template <class T>
-hipError_t launch_ring_forward(const double* maps, const int64_t* map_off, RingTab rt, FftTab<T> ft,
-                               Blocks4<T> D, const GroupDims& g, hipStream_t s);
+// north/south combination, written into Dsym rows 1 .. 2 nside of region
+// `reg` of every group of the launch (FP64).  Work item: (map, ring pair).
+hipError_t launch_ring_forward(const double* maps, const GroupLaunch& gl, int reg, hipStream_t s);
 
 // Equal-weight analysis, eq. (healsph): longitude sums of every ring for all
 // modes m = 0..p (aliased beyond each ring's Nyquist mode), combined per ring
@@ -175,15 +227,15 @@ hipError_t launch_adjoint_residual(Blocks4<const double> Wf, Blocks4<const doubl
                                    const GroupDims& g, double scale, hipStream_t s);
 
 // Refinement residual in ring-Fourier space: Dr = Df - Ring(Synth(Gs)) for
-// Dsym rows 1 .. 2 nside (Gs: synthesis GEMM output, Df: FP64 forward ring
-// coefficients of the maps), written in FP32.
-hipError_t launch_residual_fold(Blocks4<const double> Df, Blocks4<const double> Gs, Blocks4<float> Dr, RingTab rt,
-                                FftTab<double> ft, const GroupDims& g, hipStream_t s);
+// Dsym rows 1 .. 2 nside (Gs: synthesis GEMM output in region D, Df: FP64
+// forward ring coefficients of the maps), written in FP32 to region Dr.
+// Work item: (16 maps, ring pair).
+hipError_t launch_residual_fold(const GroupLaunch& gl, hipStream_t s);
 
-// S2: pole row h = 0 (quadratic extrapolation of the three nearest ring
-// means); zeroes every other entry of the pole row.
+// S2: pole row h = 0 of region `reg` (quadratic extrapolation of the three
+// nearest ring means); zeroes every other entry of the pole row.
 template <class T>
-hipError_t launch_pole(Blocks4<T> D, const GroupDims& g, double w0, double w1, double w2, hipStream_t s);
+hipError_t launch_pole(const GroupLaunch& gl, int reg, hipStream_t s);
 
 // Grouped GEMM over a device-resident problem list (finalized), one launch.
 // B is stored as TB (offsets boff in TB elements) and rounded to T.
@@ -218,19 +270,18 @@ hipError_t launch_sweep_fwd(Blocks4<T> U, Blocks4<const T> G, const GroupDims& g
 template <class T>
 hipError_t launch_sweep_bwd(Blocks4<T> U, Blocks4<const T> G, const GroupDims& g, hipStream_t s);
 
-// U (a_l^m after the sweeps) -> packed complex128 alm; with Ub.p[0] non-null
-// writes Ua + Ub (added in FP64).  `tiles`: the device copy of pack_tiles(p),
-// `ntiles` its number of (m, l0) pairs.
+// U (a_l^m after the sweeps, region reg_a) -> packed complex128 alm; with
+// reg_b >= 0 writes Ua + Ub (added in FP64).  Work item: (order m, 64 l, 32
+// maps), the group's pack tiles.
 template <class T>
-hipError_t launch_pack(Blocks4<const T> Ua, Blocks4<const T> Ub, double* alm, const int64_t* alm_off,
-                       const int32_t* lmax, const int32_t* tiles, int ntiles, const GroupDims& g, hipStream_t s);
+hipError_t launch_pack(const GroupLaunch& gl, int reg_a, int reg_b, double* alm, hipStream_t s);
 // (m, l0) of every pack tile: orders m = 0..p, l0 = m, m + 64, ... <= p.
 std::vector<int32_t> pack_tiles(int p);
 
-// FP32 U -> FP64 U in the same layout, zero outside m <= l <= lmax(map);
-// live_only leaves the rows l < m (never read by the per-order GEMMs) unwritten.
-hipError_t launch_widen(Blocks4<const float> Ua, Blocks4<double> U, const int32_t* lmax, const GroupDims& g,
-                        bool live_only, hipStream_t s);
+// FP32 U (region Ua) -> FP64 U (region U) in the same layout, zero outside
+// m <= l <= lmax(map); groups with per-order tables leave the rows l < m
+// (never read by their GEMMs) unwritten.
+hipError_t launch_widen(const GroupLaunch& gl, hipStream_t s);
 
 // Jacobi update in the U layout of per-order tables (mode-major only):
 // Uacc = (first ? 0 : Uacc) + U for m <= l <= lmax(map), zero above lmax,

@@ -240,16 +240,111 @@ __device__ __forceinline__ DftOut<T> ring_dft(C2<T>* buf, int L, int M_blue, con
 // XCDs in turn, so ring pairs are assigned to XCDs (h mod 8) and, within an
 // XCD, all maps of one ring pair run back to back: their writes (reads) of
 // the same Dsym rows then meet in that XCD's L2.
-__device__ __forceinline__ void ring_block(int nmaps, int npairs, int& map, int& h) {
-    const int id = blockIdx.x + gridDim.x * blockIdx.y;
+// `id` is the workgroup's index among the nmaps * npairs items of its group
+// (a multiple of 8 away from its launch index, so id mod 8 is its XCD).
+__device__ __forceinline__ void ring_block_id(int id, int nmaps, int npairs, int& map, int& h) {
     if ((npairs & 7) == 0) {
         const int x = id & 7, s = id >> 3;
         h = (s / nmaps) * 8 + x + 1;
         map = s % nmaps;
     } else {
-        map = blockIdx.x;
-        h = blockIdx.y + 1;
+        map = id % nmaps;
+        h = id / nmaps + 1;
     }
+}
+// The same for a launch of one group over an (nmaps, npairs) grid.
+__device__ __forceinline__ void ring_block(int nmaps, int npairs, int& map, int& h) {
+    ring_block_id(blockIdx.x + gridDim.x * blockIdx.y, nmaps, npairs, map, h);
+}
+
+// ---------------------------------------------------------------------------
+// Work lists over the nside groups of a plan
+// ---------------------------------------------------------------------------
+
+// Group (index into the plan's GroupDesc array) and item index within it of
+// work item `id` of a launch; false for a padding item.
+// Both are workgroup-uniform; readfirstlane makes that explicit, so that
+// the descriptor fields read through them stay in scalar registers.
+__device__ __forceinline__ bool locate_item(const GroupRange& gr, int id, int& gi, int& local) {
+    int i = 0;
+    while (i + 1 < gr.n && i + 1 < kMaxGroups && id >= gr.start[i + 1]) ++i;
+    i = __builtin_amdgcn_readfirstlane(i);
+    gi = gr.first + i;
+    local = __builtin_amdgcn_readfirstlane(id - gr.start[i]);
+    return local < gr.count[i];
+}
+
+// The four blocks of one workspace region of a group, read like a Blocks4
+// (R.p[b]): the block offsets stay in the group's descriptor in device
+// memory, so a block picked by a run-time index (the parity of a mode) is one
+// address computation and not a per-lane copy of a pointer array (copies of
+// dynamically indexed structs would live in scratch memory).
+template <class T>
+struct RegionBlocks {
+    struct Ptrs {
+        char* ws;
+        const int64_t* off;   // G.reg[r], null for an absent region
+        __device__ __forceinline__ T* operator[](int b) const {
+            return off ? reinterpret_cast<T*>(ws + off[b]) : nullptr;
+        }
+    } p;
+};
+template <class T>
+__device__ __forceinline__ RegionBlocks<T> region_blocks(char* ws, const GroupDesc& G, int reg) {
+    return RegionBlocks<T>{{ws, G.reg[reg]}};
+}
+
+// A workgroup-uniform value read from a descriptor, moved to scalar
+// registers word by word (readfirstlane), so that it does not occupy vector
+// registers for the rest of the kernel.
+template <class V>
+__device__ __forceinline__ V uniform(V v) {
+    static_assert(sizeof(V) % 4 == 0, "32-bit words");
+    uint32_t w[sizeof(V) / 4];
+    __builtin_memcpy(w, &v, sizeof(V));
+#pragma unroll
+    for (unsigned i = 0; i < sizeof(V) / 4; ++i) w[i] = __builtin_amdgcn_readfirstlane(w[i]);
+    V out;
+    __builtin_memcpy(&out, w, sizeof(V));
+    return out;
+}
+
+// What the ring transform of one group writes to: the group's shape and the
+// four blocks of its output region, as plain scalars.
+template <class T>
+struct RingOut {
+    int nmaps, nside, p;
+    int64_t N0, N1, cm0, cm1, ck0, ck1;
+    T *d0, *d1, *d2, *d3;
+};
+
+// Item ranges of a launch: `count_of(desc)` items per group, each group's
+// range starting at a multiple of 8.
+template <class F>
+static hipError_t make_range(const GroupLaunch& gl, F count_of, GroupRange& r) {
+    if (gl.n < 0 || gl.n > kMaxGroups) return hipErrorInvalidValue;
+    r = GroupRange{};
+    r.first = gl.first;
+    r.n = gl.n;
+    int64_t at = 0;
+    for (int i = 0; i < gl.n; ++i) {
+        const int64_t c = count_of(gl.host[gl.first + i]);
+        r.start[i] = int32_t(at);
+        r.count[i] = int32_t(c);
+        at += (c + 7) / 8 * 8;
+        if (at >= (int64_t(1) << 31)) return hipErrorInvalidValue;
+    }
+    r.start[gl.n] = int32_t(at);
+    return hipSuccess;
+}
+
+// Grid of a launch over the range: one workgroup per item, or the persistent
+// grid when it is smaller (a multiple of 8: the XCD of an item stays its
+// index mod 8).
+static unsigned list_grid(const GroupLaunch& gl, const GroupRange& r, bool persistent_ok) {
+    const int total = r.start[r.n];
+    if (persistent_ok && gl.grid_cap > 0 && gl.grid_cap < total) return unsigned(gl.grid_cap / 8 * 8);
+    return unsigned(total);
 }
 
 // Ring kernels run NT = fft_max / 16 threads (256 up to nside 1024, 512 at
@@ -258,7 +353,6 @@ __device__ __forceinline__ void ring_block(int nmaps, int npairs, int& map, int&
 constexpr int kRingMaxV = 16;
 constexpr int kRingKPT = 9;   // ceil((2 nside + 1) / NT) at the largest nside of each NT
 
-__host__ __device__ constexpr int ring_threads(int fft_max) { return fft_max <= 4096 ? 256 : 512; }
 
 // D_k, k <= p, of one ring from the half-length DFT R of its points (Step 1):
 // the real DFT X_k = E_k + e^{-2 pi i k / n} O_k from the transform of
@@ -316,27 +410,32 @@ __host__ __device__ constexpr int ring_buffer_slots(int fft_max) {
                                                                          : 2 * ring_half_slots(fft_max);
 }
 
+// Work item `id` of one group: ring pair h of map b (ring_block_id).
 template <class T, int NT>
-__global__ __launch_bounds__(NT) void k_ring_forward(const double* __restrict__ maps,
-                                                     const int64_t* __restrict__ map_off, RingTab rt, FftTab<T> ft,
-                                                     Blocks4<T> D, GroupDims g) {
-    extern __shared__ unsigned char smem_raw[];
-    C2<T>* buf = reinterpret_cast<C2<T>*>(smem_raw);
+__device__ __forceinline__ void ring_forward_item(const double* __restrict__ maps,
+                                                  const int64_t* __restrict__ map_off, const RingTab rt,
+                                                  const FftTab<T> ft, const RingOut<T> o, int id, C2<T>* buf) {
     int b, h;
-    ring_block(g.nmaps, 2 * g.nside, b, h);
-    const int ns = g.nside, p = g.p;
+    ring_block_id(id, o.nmaps, 2 * o.nside, b, h);
+    const int ns = o.nside, p = o.p;
     const double* m = maps + map_off[b];
     const bool equator = (h == 2 * ns);
+    // Row starts and column steps of the two k parities (workgroup-uniform);
+    // each lane picks its parity by a select.
+    T* const bp0 = o.d0 + int64_t(h) * o.N0 + int64_t(b) * o.cm0;
+    T* const bm0 = o.d1 + int64_t(h) * o.N0 + int64_t(b) * o.cm0;
+    T* const bp1 = o.d2 + int64_t(h) * o.N1 + int64_t(b) * o.cm1;
+    T* const bm1 = o.d3 + int64_t(h) * o.N1 + int64_t(b) * o.cm1;
+    const int64_t ck0 = o.ck0, ck1 = o.ck1;
     auto store = [&](int k, C2<T> dp, C2<T> dm) {
-        const int kpar = k & 1, kk = k >> 1;
-        const int64_t col = int64_t(b) * g.cm[kpar] + int64_t(kk) * g.ck[kpar];
-        const int64_t row = int64_t(h) * g.N[kpar];
-        T* bp = D.p[2 * kpar + 0];
-        T* bm = D.p[2 * kpar + 1];
-        bp[row + col] = dp.x;
-        bp[row + col + 1] = dp.y;
-        bm[row + col] = dm.x;
-        bm[row + col + 1] = dm.y;
+        const bool odd = (k & 1) != 0;
+        const int64_t col = int64_t(k >> 1) * (odd ? ck1 : ck0);
+        T* bp = (odd ? bp1 : bp0) + col;
+        T* bm = (odd ? bm1 : bm0) + col;
+        bp[0] = dp.x;
+        bp[1] = dp.y;
+        bm[0] = dm.x;
+        bm[1] = dm.y;
     };
     {
         // Both rings of a pair have n points and the same shift.  When their
@@ -392,6 +491,51 @@ __global__ __launch_bounds__(NT) void k_ring_forward(const double* __restrict__ 
         if (equator) store(k, DN[i], C2<T>{T(0), T(0)});
         else store(k, cscale(cadd(DN[i], DS[i]), T(0.5)), cscale(csub(DN[i], DS[i]), T(0.5)));
     }
+}
+
+// S1 over the work list of every group of the launch (FP64 ring
+// coefficients into region `reg`), one workgroup per item, or (PERSIST) a
+// grid that walks the list; there the barrier at the end of an item keeps
+// the next item's first LDS writes behind this item's last LDS reads.  The
+// loop costs registers (256 VGPRs against 192, one wave per SIMD instead of
+// two), so the persistent form is a candidate the autotuner measures.
+template <int NT>
+__device__ __forceinline__ void ring_forward_list_item(const double* __restrict__ maps,
+                                                       const GroupDesc* __restrict__ gd, const GroupRange& gr,
+                                                       char* ws, int reg, int id, C2<double>* buf) {
+    int gi, local;
+    if (!locate_item(gr, id, gi, local)) return;
+    const GroupDesc& G = gd[gi];
+    const GroupDims& g = G.g;
+    RingOut<double> o;
+    o.nmaps = uniform(g.nmaps);
+    o.nside = uniform(g.nside);
+    o.p = uniform(g.p);
+    o.N0 = uniform(g.N[0]);
+    o.N1 = uniform(g.N[1]);
+    o.cm0 = uniform(g.cm[0]);
+    o.cm1 = uniform(g.cm[1]);
+    o.ck0 = uniform(g.ck[0]);
+    o.ck1 = uniform(g.ck[1]);
+    o.d0 = reinterpret_cast<double*>(ws + uniform(G.reg[reg][0]));
+    o.d1 = reinterpret_cast<double*>(ws + uniform(G.reg[reg][1]));
+    o.d2 = reinterpret_cast<double*>(ws + uniform(G.reg[reg][2]));
+    o.d3 = reinterpret_cast<double*>(ws + uniform(G.reg[reg][3]));
+    ring_forward_item<double, NT>(maps, uniform(G.map_off), uniform(G.rt), uniform(G.ft), o, local, buf);
+}
+
+// S1 over the work list of every group of the launch (FP64 ring
+// coefficients into region `reg`), one workgroup per item.  (A persistent
+// form that walks the list does not fit: its loop keeps more values live
+// than the 256 VGPRs of a wave and spills to scratch memory, against 188
+// VGPRs and no scratch for one item per workgroup.)
+template <int NT>
+__global__ __launch_bounds__(NT) void k_ring_forward(const double* __restrict__ maps,
+                                                     const GroupDesc* __restrict__ gd, GroupRange gr, char* ws,
+                                                     int reg) {
+    extern __shared__ unsigned char smem_raw[];
+    C2<double>* buf = reinterpret_cast<C2<double>*>(smem_raw);
+    ring_forward_list_item<NT>(maps, gd, gr, ws, reg, blockIdx.x, buf);
 }
 
 // ---------------------------------------------------------------------------
@@ -508,15 +652,20 @@ static size_t ring_lds_bytes(int fft_max, size_t elem) {
     return size_t(ring_buffer_slots(std::max(fft_max, 256))) * elem;
 }
 
-template <class T>
-hipError_t launch_ring_forward(const double* maps, const int64_t* map_off, RingTab rt, FftTab<T> ft, Blocks4<T> D,
-                               const GroupDims& g, hipStream_t s) {
-    dim3 grid(g.nmaps, 2 * g.nside);
-    const size_t shm = ring_lds_bytes(ft.fft_max, sizeof(C2<T>));
-    if (ring_threads(ft.fft_max) == 256)
-        hipLaunchKernelGGL((k_ring_forward<T, 256>), grid, dim3(256), shm, s, maps, map_off, rt, ft, D, g);
+hipError_t launch_ring_forward(const double* maps, const GroupLaunch& gl, int reg, hipStream_t s) {
+    GroupRange r;
+    if (hipError_t e = make_range(gl, [](const GroupDesc& G) { return int64_t(G.g.nmaps) * 2 * G.g.nside; }, r);
+        e != hipSuccess)
+        return e;
+    if (r.start[r.n] == 0) return hipSuccess;
+    int fmax = 0;
+    for (int i = 0; i < gl.n; ++i) fmax = std::max(fmax, gl.host[gl.first + i].ft.fft_max);
+    const size_t shm = ring_lds_bytes(fmax, sizeof(C2<double>));
+    const dim3 grid(list_grid(gl, r, false));
+    if (ring_threads(fmax) == 256)
+        hipLaunchKernelGGL(k_ring_forward<256>, grid, dim3(256), shm, s, maps, gl.dev, r, gl.ws, reg);
     else
-        hipLaunchKernelGGL((k_ring_forward<T, 512>), grid, dim3(512), shm, s, maps, map_off, rt, ft, D, g);
+        hipLaunchKernelGGL(k_ring_forward<512>, grid, dim3(512), shm, s, maps, gl.dev, r, gl.ws, reg);
     return hipGetLastError();
 }
 
@@ -535,9 +684,8 @@ hipError_t launch_ring_adjoint(const double* maps, const int64_t* map_off, RingT
 // S2: pole row
 // ---------------------------------------------------------------------------
 
-template <class T>
-__global__ void k_pole(Blocks4<T> D, GroupDims g, double w0, double w1, double w2) {
-    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+template <class T, class BK>
+__device__ __forceinline__ void pole_item(BK D, const GroupDims& g, double w0, double w1, double w2, int64_t i) {
     const int64_t N0 = g.N[0], N1 = g.N[1];
     const int64_t total = 2 * N0 + 2 * N1;
     if (i >= total) return;
@@ -558,10 +706,25 @@ __global__ void k_pole(Blocks4<T> D, GroupDims g, double w0, double w1, double w
     P[col] = val;
 }
 
+// Work item: 256 consecutive pole-row entries of one group.
 template <class T>
-hipError_t launch_pole(Blocks4<T> D, const GroupDims& g, double w0, double w1, double w2, hipStream_t s) {
-    const int64_t total = 2 * g.N[0] + 2 * g.N[1];
-    hipLaunchKernelGGL(k_pole<T>, dim3(unsigned((total + 255) / 256)), dim3(256), 0, s, D, g, w0, w1, w2);
+__global__ __launch_bounds__(256) void k_pole(const GroupDesc* __restrict__ gd, GroupRange gr, char* ws, int reg) {
+    int gi, local;
+    if (!locate_item(gr, blockIdx.x, gi, local)) return;
+    const GroupDesc& G = gd[gi];
+    pole_item<T>(region_blocks<T>(ws, G, reg), G.g, G.pole_w[0], G.pole_w[1], G.pole_w[2],
+                 int64_t(local) * 256 + threadIdx.x);
+}
+
+template <class T>
+hipError_t launch_pole(const GroupLaunch& gl, int reg, hipStream_t s) {
+    GroupRange r;
+    if (hipError_t e = make_range(
+            gl, [](const GroupDesc& G) { return (2 * G.g.N[0] + 2 * G.g.N[1] + 255) / 256; }, r);
+        e != hipSuccess)
+        return e;
+    if (r.start[r.n] == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pole<T>, dim3(list_grid(gl, r, false)), dim3(256), 0, s, gl.dev, r, gl.ws, reg);
     return hipGetLastError();
 }
 
@@ -647,11 +810,13 @@ __device__ __forceinline__ V buffer_load(__amdgpu_buffer_rsrc_t r, int off) {
 // C[m][n] = sum_k A[k][m] B[k][n] for a list of problems; one 128 x 128 tile
 // of one problem per workgroup (4 waves of 64 x 64 each), k in steps of 16
 // through double-buffered LDS tiles, global loads issued ahead of use.  B and C columns come in (re, im)
-// pairs: column n lives at (n >> 1) * pair_stride + (n & 1).  A wave whose
-// 16-row blocks lie past the problem's last row skips their MFMAs (NI = number
-// of live 16-row blocks of the wave, a template argument so that the block
-// loops stay unrolled).
-template <class T, class TB, int NI>
+// pairs: column n lives at (n >> 1) * pair_stride + (n & 1).  A wave skips
+// the MFMAs of its 16-row blocks past the problem's last row and of its
+// 16-column blocks past the last column (NI, NJ = live row / column blocks of
+// the wave, template arguments so that the block loops stay unrolled; a
+// column tile that holds only the last few columns of a problem -- N = 146
+// for 73 maps -- then costs a fraction of a full tile).
+template <class T, class TB, int NI, int NJ>
 __device__ __forceinline__ void gemm_tile(const GemmProblem<T>& P, int m0, int n0, const TB* __restrict__ B,
                                           T* __restrict__ C, T (*As)[GBK][GBM + GPAD],
                                           T (*Bs)[GBK][GBN + GPAD]) {
@@ -724,15 +889,15 @@ __device__ __forceinline__ void gemm_tile(const GemmProblem<T>& P, int m0, int n
 #pragma unroll
             for (int kk = 0; kk < GBK / 4; ++kk) {
                 const int kr = kk * 4 + (lane >> 4);
-                T a[NI], b[4];
+                T a[NI], b[NJ];
 #pragma unroll
                 for (int i = 0; i < NI; ++i) a[i] = As[cur][kr][wm * 64 + i * 16 + (lane & 15)];
 #pragma unroll
-                for (int j = 0; j < 4; ++j) b[j] = Bs[cur][kr][wn * 64 + j * 16 + (lane & 15)];
+                for (int j = 0; j < NJ; ++j) b[j] = Bs[cur][kr][wn * 64 + j * 16 + (lane & 15)];
 #pragma unroll
                 for (int i = 0; i < NI; ++i)
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) acc[i][j] = Acc::mma(a[i], b[j], acc[i][j]);
+                    for (int j = 0; j < NJ; ++j) acc[i][j] = Acc::mma(a[i], b[j], acc[i][j]);
             }
         }
     };
@@ -761,7 +926,7 @@ __device__ __forceinline__ void gemm_tile(const GemmProblem<T>& P, int m0, int n
 #pragma unroll
     for (int i = 0; i < NI; ++i) {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < NJ; ++j) {
             const int nn = n0 + wn * 64 + j * 16 + (lane & 15);
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
@@ -771,6 +936,12 @@ __device__ __forceinline__ void gemm_tile(const GemmProblem<T>& P, int m0, int n
             }
         }
     }
+}
+
+// Live 16-wide blocks of a wave's 64 rows (columns) when `left` rows
+// (columns) of the problem remain from the wave's first one: 0..4.
+__device__ __forceinline__ int gemm_live_blocks(int left) {
+    return left <= 0 ? 0 : (left >= 64 ? 4 : (left + 15) / 16);
 }
 
 // TB: storage type of B (FP64 B is rounded to T as it is staged).
@@ -788,16 +959,30 @@ __global__ __launch_bounds__(256, sizeof(T) == 8 || sizeof(TB) == 8 ? 2 : 3) voi
     const int m0 = tm * GBM, n0 = tn * GBN;
     const TB* B = Bbase + P.boff;
     T* C = Cbase + P.coff;
-    // live 16-row blocks of this wave's 64 rows (wave-uniform)
+    // live 16-row and 16-column blocks of this wave's 64 x 64 (wave-uniform);
+    // three live column blocks run as four (the fourth multiplies the zeros
+    // the out-of-range B loads stage, and its stores are masked)
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int rows = P.M - m0 - (wave >> 1) * 64;
-    const int ni = rows <= 0 ? 0 : (rows >= 64 ? 4 : (rows + 15) / 16);
-    switch (ni) {
-        case 4: gemm_tile<T, TB, 4>(P, m0, n0, B, C, As, Bs); break;
-        case 3: gemm_tile<T, TB, 3>(P, m0, n0, B, C, As, Bs); break;
-        case 2: gemm_tile<T, TB, 2>(P, m0, n0, B, C, As, Bs); break;
-        case 1: gemm_tile<T, TB, 1>(P, m0, n0, B, C, As, Bs); break;
-        default: gemm_tile<T, TB, 0>(P, m0, n0, B, C, As, Bs); break;
+    const int ni = gemm_live_blocks(P.M - m0 - (wave >> 1) * 64);
+    int nj = gemm_live_blocks(P.N - n0 - (wave & 1) * 64);
+    if (nj == 3) nj = 4;
+    if (ni == 0 || nj == 0) {
+        gemm_tile<T, TB, 0, 4>(P, m0, n0, B, C, As, Bs);
+        return;
+    }
+    switch (nj * 8 + ni) {
+        case 4 * 8 + 4: gemm_tile<T, TB, 4, 4>(P, m0, n0, B, C, As, Bs); break;
+        case 4 * 8 + 3: gemm_tile<T, TB, 3, 4>(P, m0, n0, B, C, As, Bs); break;
+        case 4 * 8 + 2: gemm_tile<T, TB, 2, 4>(P, m0, n0, B, C, As, Bs); break;
+        case 4 * 8 + 1: gemm_tile<T, TB, 1, 4>(P, m0, n0, B, C, As, Bs); break;
+        case 2 * 8 + 4: gemm_tile<T, TB, 4, 2>(P, m0, n0, B, C, As, Bs); break;
+        case 2 * 8 + 3: gemm_tile<T, TB, 3, 2>(P, m0, n0, B, C, As, Bs); break;
+        case 2 * 8 + 2: gemm_tile<T, TB, 2, 2>(P, m0, n0, B, C, As, Bs); break;
+        case 2 * 8 + 1: gemm_tile<T, TB, 1, 2>(P, m0, n0, B, C, As, Bs); break;
+        case 1 * 8 + 4: gemm_tile<T, TB, 4, 1>(P, m0, n0, B, C, As, Bs); break;
+        case 1 * 8 + 3: gemm_tile<T, TB, 3, 1>(P, m0, n0, B, C, As, Bs); break;
+        case 1 * 8 + 2: gemm_tile<T, TB, 2, 1>(P, m0, n0, B, C, As, Bs); break;
+        default: gemm_tile<T, TB, 1, 1>(P, m0, n0, B, C, As, Bs); break;
     }
 }
 
@@ -1270,13 +1455,14 @@ __device__ __forceinline__ bool pack_index(const GroupDims& g, int blk, int64_t 
 constexpr int kPackL = 64, kPackMaps = 32;
 static_assert(kPackL * kPackMaps % 256 == 0, "a pack tile is a whole number of 256-thread sweeps");
 
-template <class T>
-__global__ __launch_bounds__(256) void k_pack(Blocks4<const T> Ua, Blocks4<const T> Ub, double* __restrict__ alm,
-                                              const int64_t* __restrict__ alm_off, const int32_t* __restrict__ lmaxv,
-                                              const int32_t* __restrict__ tiles, GroupDims g) {
-    __shared__ C2<double> tile[kPackL][kPackMaps + 1];
-    const int m = tiles[2 * blockIdx.x], l0 = tiles[2 * blockIdx.x + 1];
-    const int v0 = blockIdx.y * kPackMaps;
+// Pack tile `ti` (an (m, l0) pair of `tiles`) for the maps of map group `mg`.
+template <class T, class BK>
+__device__ __forceinline__ void pack_item(BK Ua, BK Ub, double* __restrict__ alm,
+                                          const int64_t* __restrict__ alm_off, const int32_t* __restrict__ lmaxv,
+                                          const int32_t* __restrict__ tiles, const GroupDims& g, int ti, int mg,
+                                          C2<double> (*tile)[kPackMaps + 1]) {
+    const int m = tiles[2 * ti], l0 = tiles[2 * ti + 1];
+    const int v0 = mg * kPackMaps;
     const int kpar = m & 1, kk = m >> 1;
     const bool two = Ub.p[0] != nullptr;
     // Branch-free, fully unrolled loads: an element outside the tile's maps or
@@ -1323,6 +1509,22 @@ __global__ __launch_bounds__(256) void k_pack(Blocks4<const T> Ua, Blocks4<const
     }
 }
 
+// Pack over the work list of every group of the launch: U of region reg_a
+// (plus region reg_b when >= 0).  Items are (pack tile, map group) with the
+// tile fastest; one workgroup per item.
+template <class T>
+__global__ __launch_bounds__(256) void k_pack(const GroupDesc* __restrict__ gd, GroupRange gr, char* ws, int reg_a,
+                                              int reg_b, double* __restrict__ alm) {
+    __shared__ C2<double> tile[kPackL][kPackMaps + 1];
+    int gi, local;
+    if (!locate_item(gr, blockIdx.x, gi, local)) return;
+    const GroupDesc& G = gd[gi];
+    RegionBlocks<const T> Ub{{ws, nullptr}};
+    if (reg_b >= 0) Ub = region_blocks<const T>(ws, G, reg_b);
+    pack_item<T>(region_blocks<const T>(ws, G, reg_a), Ub, alm, G.alm_off, G.lmax, G.pack_tiles, G.g,
+                 local % G.n_pack_tiles, local / G.n_pack_tiles, tile);
+}
+
 std::vector<int32_t> pack_tiles(int p) {
     std::vector<int32_t> t;
     for (int m = 0; m <= p; ++m)
@@ -1334,20 +1536,29 @@ std::vector<int32_t> pack_tiles(int p) {
 }
 
 template <class T>
-hipError_t launch_pack(Blocks4<const T> Ua, Blocks4<const T> Ub, double* alm, const int64_t* alm_off,
-                       const int32_t* lmax, const int32_t* tiles, int ntiles, const GroupDims& g, hipStream_t s) {
-    dim3 grid(unsigned(ntiles), unsigned((g.nmaps + kPackMaps - 1) / kPackMaps));
-    hipLaunchKernelGGL(k_pack<T>, grid, dim3(256), 0, s, Ua, Ub, alm, alm_off, lmax, tiles, g);
+hipError_t launch_pack(const GroupLaunch& gl, int reg_a, int reg_b, double* alm, hipStream_t s) {
+    GroupRange r;
+    if (hipError_t e = make_range(
+            gl,
+            [](const GroupDesc& G) {
+                return int64_t(G.n_pack_tiles) * ((G.g.nmaps + kPackMaps - 1) / kPackMaps);
+            },
+            r);
+        e != hipSuccess)
+        return e;
+    if (r.start[r.n] == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pack<T>, dim3(list_grid(gl, r, false)), dim3(256), 0, s, gl.dev, r, gl.ws, reg_a, reg_b,
+                       alm);
     return hipGetLastError();
 }
 
 // U (FP32) -> U (FP64) in the same layout, zero where l < m or l > lmax of
 // the column's map (what unpacking the packed a_lm would give).
-__global__ void k_widen(Blocks4<const float> Ua, Blocks4<double> U, const int32_t* __restrict__ lmaxv, GroupDims g,
-                        int live_only) {
-    const int blk = blockIdx.y, kpar = blk >> 1;
+template <class BA, class BU>
+__device__ __forceinline__ void widen_item(BA Ua, BU U, const int32_t* __restrict__ lmaxv, const GroupDims& g,
+                                           int live_only, int blk, int64_t e) {
+    const int kpar = blk >> 1;
     const int64_t pairs = g.N[kpar] >> 1;
-    const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (e >= int64_t(g.nl[blk]) * pairs) return;
     const int lp = int(e / pairs);
     const int64_t q = e % pairs;
@@ -1368,12 +1579,36 @@ __global__ void k_widen(Blocks4<const float> Ua, Blocks4<double> U, const int32_
     *reinterpret_cast<D2*>(U.p[blk] + o) = v;
 }
 
-hipError_t launch_widen(Blocks4<const float> Ua, Blocks4<double> U, const int32_t* lmax, const GroupDims& g,
-                        bool live_only, hipStream_t s) {
+// Workgroups of one block of a group in the widen launch: enough for its
+// largest block.
+__host__ __device__ inline int64_t widen_block_wgs(const GroupDims& g) {
     int64_t most = 0;
-    for (int b = 0; b < 4; ++b) most = std::max<int64_t>(most, int64_t(g.nl[b]) * (g.N[b >> 1] >> 1));
-    hipLaunchKernelGGL(k_widen, dim3(unsigned((most + 255) / 256), 4), dim3(256), 0, s, Ua, U, lmax, g,
-                       live_only ? 1 : 0);
+    for (int b = 0; b < 4; ++b) {
+        const int64_t n = int64_t(g.nl[b]) * (g.N[b >> 1] >> 1);
+        most = most > n ? most : n;
+    }
+    return (most + 255) / 256;
+}
+
+// Widen over the work list of every group (region Ua -> region U); item
+// (block, 256 consecutive entries) with the entries fastest.
+__global__ __launch_bounds__(256) void k_widen(const GroupDesc* __restrict__ gd, GroupRange gr, char* ws) {
+    int gi, local;
+    if (!locate_item(gr, blockIdx.x, gi, local)) return;
+    const GroupDesc& G = gd[gi];
+    const int64_t per = widen_block_wgs(G.g);
+    const int blk = int(local / per);
+    widen_item(region_blocks<const float>(ws, G, kRegUa), region_blocks<double>(ws, G, kRegU), G.lmax, G.g,
+               G.tables, blk, (local % per) * 256 + threadIdx.x);
+}
+
+hipError_t launch_widen(const GroupLaunch& gl, hipStream_t s) {
+    GroupRange r;
+    if (hipError_t e = make_range(gl, [](const GroupDesc& G) { return 4 * widen_block_wgs(G.g); }, r);
+        e != hipSuccess)
+        return e;
+    if (r.start[r.n] == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_widen, dim3(list_grid(gl, r, false)), dim3(256), 0, s, gl.dev, r, gl.ws);
     return hipGetLastError();
 }
 
@@ -1626,14 +1861,14 @@ hipError_t launch_ring_inverse(Blocks4<const double> D, RingTab rt, FftTab<doubl
 
 constexpr int kFoldMaps = 16;
 
-template <int NT>
-__global__ __launch_bounds__(NT) void k_residual_fold(Blocks4<const double> Df, Blocks4<const double> Gs,
-                                                      Blocks4<float> Dr, RingTab rt, GroupDims g) {
+// Work item `id` of one group: ring pair h of map group mg (ring_block_id).
+template <int NT, class BD, class BR>
+__device__ __forceinline__ void residual_fold_item(BD Df, BD Gs, BR Dr, const RingTab& rt, const GroupDims& g, int id,
+                                                   C2<double>* partN, C2<double>* partS) {
     constexpr int SL = NT / kFoldMaps;   // k slots per map
-    __shared__ C2<double> partN[NT], partS[NT];
     const int mgroups = (g.nmaps + kFoldMaps - 1) / kFoldMaps;
     int mg, h;
-    ring_block(mgroups, 2 * g.nside, mg, h);
+    ring_block_id(id, mgroups, 2 * g.nside, mg, h);
     const int m8 = threadIdx.x % kFoldMaps, slot = threadIdx.x / kFoldMaps;
     const int map = mg * kFoldMaps + m8;
     const bool valid = map < g.nmaps;
@@ -1749,12 +1984,46 @@ __global__ __launch_bounds__(NT) void k_residual_fold(Blocks4<const double> Df, 
     }
 }
 
-hipError_t launch_residual_fold(Blocks4<const double> Df, Blocks4<const double> Gs, Blocks4<float> Dr, RingTab rt,
-                                FftTab<double> ft, const GroupDims& g, hipStream_t s) {
-    (void)ft;
-    const int mgroups = (g.nmaps + kFoldMaps - 1) / kFoldMaps;
-    dim3 grid(mgroups, 2 * g.nside);
-    hipLaunchKernelGGL(k_residual_fold<256>, grid, dim3(256), 0, s, Df, Gs, Dr, rt, g);
+// The fold over the work list of every group (regions Df and D -> Dr), one
+// workgroup per item or (PERSIST) a grid that walks the list with a barrier
+// between items (a candidate the autotuner measures).
+template <int NT>
+__device__ __forceinline__ void residual_fold_list_item(const GroupDesc* __restrict__ gd, const GroupRange& gr,
+                                                        char* ws, int id, C2<double>* partN, C2<double>* partS) {
+    int gi, local;
+    if (!locate_item(gr, id, gi, local)) return;
+    const GroupDesc& G = gd[gi];
+    residual_fold_item<NT>(region_blocks<const double>(ws, G, kRegDf), region_blocks<const double>(ws, G, kRegD),
+                           region_blocks<float>(ws, G, kRegDr), G.rt, G.g, local, partN, partS);
+}
+
+template <int NT, bool PERSIST>
+__global__ __launch_bounds__(NT) void k_residual_fold(const GroupDesc* __restrict__ gd, GroupRange gr, char* ws) {
+    __shared__ C2<double> partN[NT], partS[NT];
+    if constexpr (PERSIST) {
+        const int total = gr.start[gr.n];
+        for (int id = blockIdx.x; id < total; id += gridDim.x) {
+            residual_fold_list_item<NT>(gd, gr, ws, id, partN, partS);
+            __syncthreads();
+        }
+    } else {
+        residual_fold_list_item<NT>(gd, gr, ws, blockIdx.x, partN, partS);
+    }
+}
+
+hipError_t launch_residual_fold(const GroupLaunch& gl, hipStream_t s) {
+    GroupRange r;
+    if (hipError_t e = make_range(
+            gl, [](const GroupDesc& G) { return int64_t((G.g.nmaps + kFoldMaps - 1) / kFoldMaps) * 2 * G.g.nside; },
+            r);
+        e != hipSuccess)
+        return e;
+    if (r.start[r.n] == 0) return hipSuccess;
+    const unsigned grid = list_grid(gl, r, true);
+    if (int64_t(grid) < int64_t(r.start[r.n]))
+        hipLaunchKernelGGL((k_residual_fold<256, true>), dim3(grid), dim3(256), 0, s, gl.dev, r, gl.ws);
+    else
+        hipLaunchKernelGGL((k_residual_fold<256, false>), dim3(grid), dim3(256), 0, s, gl.dev, r, gl.ws);
     return hipGetLastError();
 }
 
@@ -1955,8 +2224,8 @@ void* scratch_ptr(int device) {
 hipError_t configure_kernels() {
     const int bytes = 160 * 1024;
     const void* fns[] = {
-        reinterpret_cast<const void*>(&k_ring_forward<double, 256>),
-        reinterpret_cast<const void*>(&k_ring_forward<double, 512>),
+        reinterpret_cast<const void*>(&k_ring_forward<256>),
+        reinterpret_cast<const void*>(&k_ring_forward<512>),
         reinterpret_cast<const void*>(&k_ring_inverse<256>),
         reinterpret_cast<const void*>(&k_ring_inverse<512>),
         reinterpret_cast<const void*>(&k_ring_adjoint<256>),
@@ -1971,10 +2240,8 @@ hipError_t configure_kernels() {
 }
 
 // explicit instantiations
-template hipError_t launch_ring_forward<double>(const double*, const int64_t*, RingTab, FftTab<double>,
-                                                Blocks4<double>, const GroupDims&, hipStream_t);
-template hipError_t launch_pole<double>(Blocks4<double>, const GroupDims&, double, double, double, hipStream_t);
-template hipError_t launch_pole<float>(Blocks4<float>, const GroupDims&, double, double, double, hipStream_t);
+template hipError_t launch_pole<double>(const GroupLaunch&, int, hipStream_t);
+template hipError_t launch_pole<float>(const GroupLaunch&, int, hipStream_t);
 template hipError_t launch_gemm<double, double>(const GemmProblem<double>*, const int32_t*, int, const double*,
                                                double*, hipStream_t);
 template hipError_t launch_gemm<float, float>(const GemmProblem<float>*, const int32_t*, int, const float*, float*,
@@ -1992,9 +2259,7 @@ template hipError_t launch_scatter_tables<double>(const double*, int, int, int, 
 template hipError_t launch_sweep_fwd<double>(Blocks4<double>, Blocks4<const double>, const GroupDims&, hipStream_t);
 template hipError_t launch_sweep_fwd<float>(Blocks4<float>, Blocks4<const float>, const GroupDims&, hipStream_t);
 template hipError_t launch_sweep_bwd<double>(Blocks4<double>, Blocks4<const double>, const GroupDims&, hipStream_t);
-template hipError_t launch_pack<double>(Blocks4<const double>, Blocks4<const double>, double*, const int64_t*,
-                                        const int32_t*, const int32_t*, int, const GroupDims&, hipStream_t);
-template hipError_t launch_pack<float>(Blocks4<const float>, Blocks4<const float>, double*, const int64_t*,
-                                       const int32_t*, const int32_t*, int, const GroupDims&, hipStream_t);
+template hipError_t launch_pack<double>(const GroupLaunch&, int, int, double*, hipStream_t);
+template hipError_t launch_pack<float>(const GroupLaunch&, int, int, double*, hipStream_t);
 
 }  // namespace hp2sph

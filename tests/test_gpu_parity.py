@@ -264,3 +264,30 @@ def test_several_tiles_nside128(mode, strategy):
     err = rel_err(a, ref)
     print(f"{mode} {strategy} nside 128 x 3: {err:.3e}")
     assert err < (TOL64 if mode == "f64" else TOL_REFINE)
+
+
+@pytest.mark.parametrize("mode", ["f64", "f32_refine"])
+def test_batch_widths_match_single_maps_bitwise(mode):
+    """Per-order GEMMs of 2 B columns: B = 9, 20, 40, 73 maps leave 18, 40,
+    80 (one full and one partial 64-column wave half) and 146 columns (a
+    second column tile with 18 live columns), so every count of live
+    16-column blocks per wave is met.  Each column of a GEMM is computed
+    alone, so every map of the batch must equal its single-map analysis bit
+    for bit (and the single maps agree with the oracle)."""
+    nside = 8
+    route = O.analyze if mode == "f64" else O.analyze_refined
+    maps = [white_map(nside, 1500 + v) for v in range(73)]
+    singles = []
+    for v in range(73):
+        plan = P.Plan(nside, batch=1, mode=mode, strategy="tables")
+        singles.append(plan.analyze(_dev(maps[v])).cpu().numpy())
+        plan.close()
+    for v in (0, 40, 72):
+        assert rel_err(singles[v], route(maps[v], nside)) < (TOL64 if mode == "f64" else TOL_REFINE)
+    sz = O.alm_size(2 * nside)
+    for batch in (9, 20, 40, 73):
+        plan = P.Plan(nside, batch=batch, mode=mode, strategy="tables")
+        a = plan.analyze(_dev(np.concatenate(maps[:batch]))).cpu().numpy()
+        plan.close()
+        for v in range(batch):
+            assert np.array_equal(a[v * sz:(v + 1) * sz], singles[v]), (batch, v)

@@ -118,3 +118,43 @@ def test_schedule_and_autotune_argument_errors():
     with pytest.raises(P.HP2SPHError):
         plan.autotune(maps, reps=P.MAX_TUNE_REPS + 1)
     plan.close()
+
+
+@pytest.mark.parametrize("mode", ["f32_refine", "f64"])
+def test_work_lists_over_mixed_groups(mode):
+    """Every stage runs as one work list over all nside groups.  The batch
+    mixes per-order-table groups (>= 8 maps) and staged ones; the fold's
+    persistent grids only change which workgroup takes which item (items keep
+    their XCD), so every grid gives the same a_lm bit for bit; and each map
+    agrees with its own single-map analysis (bitwise for the staged groups,
+    whose single-map plans run the same strategy) and with the oracle."""
+    nsides = [32] * 9 + [16, 8, 16] + [64] * 8 + [4]
+    maps_np = [white_map(ns, 1900 + i) for i, ns in enumerate(nsides)]
+    maps = torch.from_numpy(np.concatenate(maps_np)).cuda()
+    plan = P.Plan(nsides, mode=mode)
+    assert plan.fold_grid == 0
+    ref = _run_clean(plan, maps, False)
+    for grid in (8, 64, 256, 2048):
+        plan.set_fold_grid(grid)
+        assert plan.fold_grid == grid
+        got = _run_clean(plan, maps, False)
+        print(f"{mode} fold grid {grid}: equal={torch.equal(got, ref)}")
+        assert torch.equal(got, ref), grid
+    with pytest.raises(P.HP2SPHError):
+        plan.set_fold_grid(3)
+    with pytest.raises(P.HP2SPHError):
+        plan.set_fold_grid(-8)
+    ref = ref.numpy()
+    offs = plan.alm_offsets
+    plan.close()
+    for i, ns in enumerate(nsides):
+        single = P.Plan(ns, mode=mode)
+        a = single.analyze(torch.from_numpy(maps_np[i]).cuda()).cpu().numpy()
+        single.close()
+        mine = ref[offs[i]:offs[i + 1]]
+        if nsides.count(ns) < 8:
+            assert np.array_equal(mine, a), i
+        if mode == "f64":
+            assert rel_err(mine, O.analyze(maps_np[i], ns)) < 1e-12
+        else:
+            assert rel_err(mine, O.analyze_refined(maps_np[i], ns)) < 1e-6
