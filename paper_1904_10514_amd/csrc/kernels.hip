@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <mutex>
+#include <type_traits>
 
 namespace hp2sph {
 
@@ -112,6 +113,13 @@ __device__ __forceinline__ void dft_regs(C2<T>* v) {
     dit_stages<T, R, 1>(v);
 }
 
+// The LDS buffer as the input of a pass (entry i at slot lpad(i)).
+template <class T>
+struct LdsLoad {
+    const C2<T>* buf;
+    __device__ __forceinline__ C2<T> operator()(int i) const { return buf[lpad(i)]; }
+};
+
 // One Stockham pass of radix R over M points with NT threads: group j reads
 // entries j + r M/R (from `load`), multiplies entry r by w^r with
 // w = e^{-2 pi i (j mod Ns) / (Ns R)}, transforms, and stores output r at
@@ -121,27 +129,80 @@ __device__ __forceinline__ void dft_regs(C2<T>* v) {
 // threads are threadIdx.x mod NT: a workgroup of 2 NT threads can run two
 // transforms of the same length side by side (every thread meets every
 // barrier).
-template <class T, int R, int NT, int MAXV, class Load>
-__device__ __forceinline__ void stockham_pass(C2<T>* buf, int M, int lgNs, const T* tw, int fft_max, Load load) {
+//
+// LDS addressing: Ns is 1 or a multiple of 16 (radix-16 passes first), and
+// an output run base + r Ns then sits at lpad(base) + r s with s = 1 (Ns = 1:
+// base is a multiple of R, which divides 16, so base + r never crosses a
+// pad) or s = 17 Ns / 16; likewise the inputs j + r G of an LDS pass sit at
+// lpad(j) + r 17 G / 16 when G = M / R is a multiple of 16 (M >= 256).  The
+// slot of entry r is then one base address plus a stride, and with the
+// transform length a template argument (MS > 0; 0: known at run time) the
+// strides are immediate offsets of the LDS instructions.
+// Twiddles w, w^2, w^4, w^8 of each of a thread's groups in one pass,
+// loaded ahead of the pass (a pass of a transform whose length is a
+// template argument gets them from the pass before it, so the table loads
+// are in flight across that pass instead of stalling this one).
+template <class T, int R, int MAXV>
+struct PassTw {
+    C2<T> w[MAXV / R][4];
+};
+
+template <class T, int R, int NT, int MAXV>
+__device__ __forceinline__ void load_pass_tw(PassTw<T, R, MAXV>& t, const T* tw, int fft_max, int lgNs, int G) {
+    const int Ns = 1 << lgNs;
+#pragma unroll
+    for (int i = 0; i < MAXV / R; ++i) {
+        const int j = (threadIdx.x & (NT - 1)) + NT * i;
+        if (j < G) {
+            const int st = (fft_max >> lgNs) / R * (j & (Ns - 1));
+            t.w[i][0] = ldc(tw, st);
+            if constexpr (R > 2) t.w[i][1] = ldc(tw, 2 * st);
+            if constexpr (R > 4) t.w[i][2] = ldc(tw, 4 * st);
+            if constexpr (R > 8) t.w[i][3] = ldc(tw, 8 * st);
+        }
+    }
+}
+
+template <class T, int R, int NT, int MAXV, int MS, bool PRE = false, class Load>
+__device__ __forceinline__ void stockham_pass(C2<T>* buf, int M_rt, int lgNs, const T* tw, int fft_max, Load load,
+                                              const PassTw<T, R, MAXV>& pre = PassTw<T, R, MAXV>{}) {
     constexpr int NG = MAXV / R;
+    const int M = MS > 0 ? MS : M_rt;
     const int G = M / R, Ns = 1 << lgNs;
+    constexpr bool lds_in = std::is_same<Load, LdsLoad<T>>::value;
+    const bool linear_in = lds_in && (MS > 0 ? (MS / R) % 16 == 0 : M >= 256);
+    const int sin_ = G + (G >> 4);                     // input stride (slots) when linear
+    const int sout = Ns == 1 ? 1 : Ns + (Ns >> 4);      // output stride (slots)
     C2<T> v[MAXV];
 #pragma unroll
     for (int i = 0; i < NG; ++i) {
         const int j = (threadIdx.x & (NT - 1)) + NT * i;
         if (j < G) {
+            if (linear_in) {
+                const C2<T>* src = buf + lpad(j);
 #pragma unroll
-            for (int r = 0; r < R; ++r) v[i * R + r] = load(j + r * G);
+                for (int r = 0; r < R; ++r) v[i * R + r] = src[r * sin_];
+            } else {
+#pragma unroll
+                for (int r = 0; r < R; ++r) v[i * R + r] = load(j + r * G);
+            }
             if (lgNs > 0) {
                 // w^r, r = 1..R-1, w = e^{-2 pi i (j mod Ns) / (Ns R)}: the
                 // powers 1, 2, 4, 8 from the table, the others as products of
                 // two or three of them (a few ulp)
-                const int st = (fft_max >> lgNs) / R * (j & (Ns - 1));
                 C2<T> w[R];
-                w[1] = ldc(tw, st);
-                if constexpr (R > 2) w[2] = ldc(tw, 2 * st);
-                if constexpr (R > 4) w[4] = ldc(tw, 4 * st);
-                if constexpr (R > 8) w[8] = ldc(tw, 8 * st);
+                if constexpr (PRE) {
+                    w[1] = pre.w[i][0];
+                    if constexpr (R > 2) w[2] = pre.w[i][1];
+                    if constexpr (R > 4) w[4] = pre.w[i][2];
+                    if constexpr (R > 8) w[8] = pre.w[i][3];
+                } else {
+                    const int st = (fft_max >> lgNs) / R * (j & (Ns - 1));
+                    w[1] = ldc(tw, st);
+                    if constexpr (R > 2) w[2] = ldc(tw, 2 * st);
+                    if constexpr (R > 4) w[4] = ldc(tw, 4 * st);
+                    if constexpr (R > 8) w[8] = ldc(tw, 8 * st);
+                }
                 if constexpr (R > 3) w[3] = cmul(w[2], w[1]);
                 if constexpr (R > 4) {
                     w[5] = cmul(w[4], w[1]);
@@ -164,40 +225,83 @@ __device__ __forceinline__ void stockham_pass(C2<T>* buf, int M, int lgNs, const
         const int j = (threadIdx.x & (NT - 1)) + NT * i;
         if (j < G) {
             const int base = ((j >> lgNs) << lgNs) * R + (j & (Ns - 1));
+            C2<T>* dst = buf + lpad(base);
 #pragma unroll
-            for (int r = 0; r < R; ++r) buf[lpad(base + r * Ns)] = v[i * R + r];
+            for (int r = 0; r < R; ++r) dst[r * sout] = v[i * R + r];
         }
     }
     __syncthreads();
 }
 
-template <class T, int NT, int MAXV, class Load>
+template <class T, int NT, int MAXV, int MS, class Load>
 __device__ __forceinline__ void stockham_dispatch(int bits, C2<T>* buf, int M, int lgNs, const T* tw, int fft_max,
                                                   Load load) {
     switch (bits) {
-        case 4: stockham_pass<T, 16, NT, MAXV>(buf, M, lgNs, tw, fft_max, load); break;
-        case 3: stockham_pass<T, 8, NT, MAXV>(buf, M, lgNs, tw, fft_max, load); break;
-        case 2: stockham_pass<T, 4, NT, MAXV>(buf, M, lgNs, tw, fft_max, load); break;
-        default: stockham_pass<T, 2, NT, MAXV>(buf, M, lgNs, tw, fft_max, load); break;
+        case 4: stockham_pass<T, 16, NT, MAXV, MS>(buf, M, lgNs, tw, fft_max, load); break;
+        case 3: stockham_pass<T, 8, NT, MAXV, MS>(buf, M, lgNs, tw, fft_max, load); break;
+        case 2: stockham_pass<T, 4, NT, MAXV, MS>(buf, M, lgNs, tw, fft_max, load); break;
+        default: stockham_pass<T, 2, NT, MAXV, MS>(buf, M, lgNs, tw, fft_max, load); break;
     }
 }
 
-// Forward DFT of M = 2^e points (2 <= M <= NT * MAXV) in LDS:
+// Forward DFT of M = 2^e points (2 <= M <= NT * MAXV) in LDS, with M a
+// template argument (MS > 0) or known at run time (MS = 0):
 // X_s = sum_q x_q e^{-2 pi i q s / M}.  The first pass takes its input from
 // `load0(q)` (which may read the buffer); on return the buffer holds X in
 // natural order at slots lpad(s).  Radix-16 passes, the remainder last.
 // Table tw: e^{-2 pi i t / fft_max}, t < fft_max, M divides fft_max.
+constexpr int static_log2(int v) { return v <= 1 ? 0 : 1 + static_log2(v >> 1); }
+// Radix of pass p of a transform of 2^E points: 16, the remainder last.
+constexpr int pass_radix(int E, int p) {
+    return p < (E + 3) / 4 - 1 ? 16 : (1 << (E - 4 * ((E + 3) / 4 - 1)));
+}
+
+template <class T, int NT, int MAXV, int MS, class Load0>
+__device__ __forceinline__ void fft_lds_n(C2<T>* buf, int M_rt, const T* tw, int fft_max, Load0 load0) {
+    const LdsLoad<T> lds_load{buf};
+    if constexpr (MS > 0) {
+        // compile-time pass sequence; each pass prefetches the twiddles of
+        // the next one (passes of radix 16, and a last pass of radix 8)
+        constexpr int E = static_log2(MS), P = (E + 3) / 4;
+        static_assert(P <= 4, "at most four passes");
+        constexpr int R0 = pass_radix(E, 0), R1 = pass_radix(E, 1), R2 = pass_radix(E, 2), R3 = pass_radix(E, 3);
+        constexpr bool pre1 = P > 1 && R1 >= 8, pre2 = P > 2 && R2 >= 8, pre3 = P > 3 && R3 >= 8;
+        PassTw<T, R1, MAXV> t1;
+        if constexpr (pre1) load_pass_tw<T, R1, NT, MAXV>(t1, tw, fft_max, 4, MS / R1);
+        stockham_pass<T, R0, NT, MAXV, MS>(buf, MS, 0, tw, fft_max, load0);
+        if constexpr (P > 1) {
+            PassTw<T, R2, MAXV> t2;
+            if constexpr (pre2) load_pass_tw<T, R2, NT, MAXV>(t2, tw, fft_max, 8, MS / R2);
+            stockham_pass<T, R1, NT, MAXV, MS, pre1>(buf, MS, 4, tw, fft_max, lds_load, t1);
+            if constexpr (P > 2) {
+                PassTw<T, R3, MAXV> t3;
+                if constexpr (pre3) load_pass_tw<T, R3, NT, MAXV>(t3, tw, fft_max, 12, MS / R3);
+                stockham_pass<T, R2, NT, MAXV, MS, pre2>(buf, MS, 8, tw, fft_max, lds_load, t2);
+                if constexpr (P > 3) stockham_pass<T, R3, NT, MAXV, MS, pre3>(buf, MS, 12, tw, fft_max, lds_load, t3);
+            }
+        }
+    } else {
+        const int M = M_rt;
+        const int e = ilog2(M);
+        const int P = (e + 3) >> 2;
+        const int last = e - 4 * (P - 1);
+        // straight-line pass sequence (at most 4 passes for M <= 2^16)
+        stockham_dispatch<T, NT, MAXV, MS>(P == 1 ? last : 4, buf, M, 0, tw, fft_max, load0);
+        if (P > 1) stockham_dispatch<T, NT, MAXV, MS>(P == 2 ? last : 4, buf, M, 4, tw, fft_max, lds_load);
+        if (P > 2) stockham_dispatch<T, NT, MAXV, MS>(P == 3 ? last : 4, buf, M, 8, tw, fft_max, lds_load);
+        if (P > 3) stockham_dispatch<T, NT, MAXV, MS>(last, buf, M, 12, tw, fft_max, lds_load);
+    }
+}
+
+// fft_lds_n with the length NT * MAXV / 2 (the transforms of the equatorial
+// rings and the half-buffer transforms) and NT * MAXV (the largest Bluestein
+// transforms) compiled for their length.
 template <class T, int NT, int MAXV, class Load0>
 __device__ __forceinline__ void fft_lds(C2<T>* buf, int M, const T* tw, int fft_max, Load0 load0) {
-    const int e = ilog2(M);
-    const int P = (e + 3) >> 2;
-    const int last = e - 4 * (P - 1);
-    auto lds_load = [buf](int i) { return buf[lpad(i)]; };
-    // straight-line pass sequence (at most 4 passes for M <= 2^16)
-    stockham_dispatch<T, NT, MAXV>(P == 1 ? last : 4, buf, M, 0, tw, fft_max, load0);
-    if (P > 1) stockham_dispatch<T, NT, MAXV>(P == 2 ? last : 4, buf, M, 4, tw, fft_max, lds_load);
-    if (P > 2) stockham_dispatch<T, NT, MAXV>(P == 3 ? last : 4, buf, M, 8, tw, fft_max, lds_load);
-    if (P > 3) stockham_dispatch<T, NT, MAXV>(last, buf, M, 12, tw, fft_max, lds_load);
+    constexpr int kFull = NT * MAXV;
+    if (M == kFull) fft_lds_n<T, NT, MAXV, kFull>(buf, M, tw, fft_max, load0);
+    else if (M == kFull / 2) fft_lds_n<T, NT, MAXV, kFull / 2>(buf, M, tw, fft_max, load0);
+    else fft_lds_n<T, NT, MAXV, 0>(buf, M, tw, fft_max, load0);
 }
 
 // Forward DFT of length L (a power of two, or any L through Bluestein's
@@ -307,6 +411,21 @@ __device__ __forceinline__ V uniform(V v) {
     V out;
     __builtin_memcpy(&out, w, sizeof(V));
     return out;
+}
+
+// The four block pointers of one region as scalars: at(i) picks one by
+// selects, so a per-lane block index needs no indexable (scratch) copy.
+template <class T>
+struct Quad {
+    T *b0, *b1, *b2, *b3;
+    __device__ __forceinline__ T* at(int i) const { return i == 0 ? b0 : (i == 1 ? b1 : (i == 2 ? b2 : b3)); }
+    __device__ __forceinline__ bool null() const { return b0 == nullptr; }
+};
+template <class T>
+__device__ __forceinline__ Quad<T> region_quad(char* ws, const GroupDesc& G, int reg) {
+    if (reg < 0) return Quad<T>{nullptr, nullptr, nullptr, nullptr};
+    return Quad<T>{reinterpret_cast<T*>(ws + uniform(G.reg[reg][0])), reinterpret_cast<T*>(ws + uniform(G.reg[reg][1])),
+                   reinterpret_cast<T*>(ws + uniform(G.reg[reg][2])), reinterpret_cast<T*>(ws + uniform(G.reg[reg][3]))};
 }
 
 // What the ring transform of one group writes to: the group's shape and the
@@ -1456,15 +1575,15 @@ constexpr int kPackL = 64, kPackMaps = 32;
 static_assert(kPackL * kPackMaps % 256 == 0, "a pack tile is a whole number of 256-thread sweeps");
 
 // Pack tile `ti` (an (m, l0) pair of `tiles`) for the maps of map group `mg`.
-template <class T, class BK>
-__device__ __forceinline__ void pack_item(BK Ua, BK Ub, double* __restrict__ alm,
+template <class T>
+__device__ __forceinline__ void pack_item(Quad<const T> Ua, Quad<const T> Ub, double* __restrict__ alm,
                                           const int64_t* __restrict__ alm_off, const int32_t* __restrict__ lmaxv,
                                           const int32_t* __restrict__ tiles, const GroupDims& g, int ti, int mg,
                                           C2<double> (*tile)[kPackMaps + 1]) {
     const int m = tiles[2 * ti], l0 = tiles[2 * ti + 1];
     const int v0 = mg * kPackMaps;
     const int kpar = m & 1, kk = m >> 1;
-    const bool two = Ub.p[0] != nullptr;
+    const bool two = !Ub.null();
     // Branch-free, fully unrolled loads: an element outside the tile's maps or
     // degrees reads the tile's first element (map v0, degree l0, both in range)
     // and is dropped when the tile is filled, so all of a thread's loads are in
@@ -1482,8 +1601,8 @@ __device__ __forceinline__ void pack_item(BK Ua, BK Ub, double* __restrict__ alm
         const int blk = 2 * kpar + ((l & 1) == (g.lmin[2 * kpar] & 1) ? 0 : 1);
         const int lp = (l - g.lmin[blk]) >> 1;
         const int64_t o = int64_t(lp) * g.N[kpar] + int64_t(v) * g.cm[kpar] + int64_t(kk) * g.ck[kpar];
-        ra[it] = *reinterpret_cast<const P2*>(Ua.p[blk] + o);
-        if (two) rb[it] = *reinterpret_cast<const P2*>(Ub.p[blk] + o);
+        ra[it] = *reinterpret_cast<const P2*>(Ua.at(blk) + o);
+        if (two) rb[it] = *reinterpret_cast<const P2*>(Ub.at(blk) + o);
     }
 #pragma unroll
     for (int it = 0; it < kIt; ++it) {
@@ -1496,14 +1615,25 @@ __device__ __forceinline__ void pack_item(BK Ua, BK Ub, double* __restrict__ alm
         }
         tile[li][vi] = z;
     }
+    // the maps' band limits and alm offsets of the store phase, read while
+    // the other lanes fill the tile
+    int Ls[kIt];
+    int64_t base[kIt];
+#pragma unroll
+    for (int it = 0; it < kIt; ++it) {
+        const int v = v0 + (threadIdx.x + 256 * it) / kPackL;
+        const int vv = v < g.nmaps ? v : v0;
+        Ls[it] = v < g.nmaps ? lmaxv[vv] : -1;
+        base[it] = alm_off[vv];
+    }
     __syncthreads();
-    for (int i = threadIdx.x; i < kPackL * kPackMaps; i += 256) {
+#pragma unroll
+    for (int it = 0; it < kIt; ++it) {
+        const int i = threadIdx.x + 256 * it;
         const int li = i % kPackL, vi = i / kPackL;
-        const int v = v0 + vi, l = l0 + li;
-        if (v >= g.nmaps) continue;
-        const int L = lmaxv[v];
+        const int l = l0 + li, L = Ls[it];
         if (l > L) continue;
-        const int64_t o = 2 * (alm_off[v] + int64_t(m) * (2 * L + 1 - m) / 2 + l);
+        const int64_t o = 2 * (base[it] + int64_t(m) * (2 * L + 1 - m) / 2 + l);
         const C2<double> z = tile[li][vi];
         *reinterpret_cast<D2*>(alm + o) = D2{z.x, z.y};
     }
@@ -1519,10 +1649,9 @@ __global__ __launch_bounds__(256) void k_pack(const GroupDesc* __restrict__ gd, 
     int gi, local;
     if (!locate_item(gr, blockIdx.x, gi, local)) return;
     const GroupDesc& G = gd[gi];
-    RegionBlocks<const T> Ub{{ws, nullptr}};
-    if (reg_b >= 0) Ub = region_blocks<const T>(ws, G, reg_b);
-    pack_item<T>(region_blocks<const T>(ws, G, reg_a), Ub, alm, G.alm_off, G.lmax, G.pack_tiles, G.g,
-                 local % G.n_pack_tiles, local / G.n_pack_tiles, tile);
+    const int nt = uniform(G.n_pack_tiles);
+    pack_item<T>(region_quad<const T>(ws, G, reg_a), region_quad<const T>(ws, G, reg_b), alm, uniform(G.alm_off),
+                 uniform(G.lmax), uniform(G.pack_tiles), G.g, local % nt, local / nt, tile);
 }
 
 std::vector<int32_t> pack_tiles(int p) {
