@@ -546,7 +546,13 @@ def main():
             cr = f64["plan"].power_spectrum(ref).view(nmaps, -1)
             rel = ((c - cr).abs()[:, 2:] / cr[:, 2:]).amax(dim=0)
             da = (a - ref).abs().view(nmaps, -1).amax(dim=1) / ref.abs().view(nmaps, -1).amax(dim=1)
+            # degrees whose C_l stays above 1e-12 of the largest (every map):
+            # beyond them a noiseless beamed spectrum falls below FP64
+            # rounding of the sums and a relative error carries no meaning
+            big = (cr[:, 2:] >= 1e-12 * cr[:, 2:].amax(dim=1, keepdim=True)).all(dim=0)
+            l_cut = int(2 + (big.nonzero().max() if bool(big.any()) else 0))
             return {"max_abs_da_over_max_a": float(da.max()), "max_rel_dcl_l_ge_2": float(rel.max()),
+                    "l_cut": l_cut, "max_rel_dcl_2_to_l_cut": float(rel[:l_cut - 1].max()),
                     "median_over_l_of_max_rel_dcl": float(rel.median()),
                     "rel_dcl_by_band": {f"{lo}-{hi}": float(rel[lo - 2:hi - 1].max())
                                         for lo, hi in ((2, 100), (100, 500), (500, 1000), (1000, 1500), (1500, lmax))}}

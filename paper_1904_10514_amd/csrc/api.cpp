@@ -1325,8 +1325,14 @@ void build_work_lists(hp2sph_plan_t plan) {
         d.map_off = G.d_map_off;
         d.alm_off = G.d_alm_off;
         d.lmax = G.d_lmax;
-        d.pack_tiles = G.d_pack_tiles;
-        d.n_pack_tiles = G.n_pack_tiles;
+        if (G.dims.modemajor) {
+            d.pack_tiles = G.d_pack_tiles;
+            d.n_pack_tiles = G.n_pack_tiles;
+        } else {
+            std::vector<int32_t> pt = pack_tiles_mapmajor(G.dims.p);
+            d.n_pack_tiles = int(pt.size() / 2);
+            d.pack_tiles = upload_int(plan->owned, pt);
+        }
         d.tables = G.tables ? 1 : 0;
         for (int i = 0; i < 3; ++i) d.pole_w[i] = G.pole_w[i];
         for (int r = 0; r < kRegions; ++r)

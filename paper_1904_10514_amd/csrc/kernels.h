@@ -275,8 +275,12 @@ hipError_t launch_sweep_bwd(Blocks4<T> U, Blocks4<const T> G, const GroupDims& g
 // maps), the group's pack tiles.
 template <class T>
 hipError_t launch_pack(const GroupLaunch& gl, int reg_a, int reg_b, double* alm, hipStream_t s);
-// (m, l0) of every pack tile: orders m = 0..p, l0 = m, m + 64, ... <= p.
+// (m, l0) of every pack tile of the mode-major layout (per-order tables):
+// orders m = 0..p, l0 = m, m + 64, ... <= p.
 std::vector<int32_t> pack_tiles(int p);
+// (m0, l0) of every pack tile of the map-major layout (staged strategy): 16
+// orders m0, m0 + 2, .. of one parity, l0 = m0, m0 + 64, ... <= p.
+std::vector<int32_t> pack_tiles_mapmajor(int p);
 
 // FP32 U (region Ua) -> FP64 U (region U) in the same layout, zero outside
 // m <= l <= lmax(map); groups with per-order tables leave the rows l < m

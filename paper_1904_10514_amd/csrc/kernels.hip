@@ -1654,6 +1654,85 @@ __global__ __launch_bounds__(256) void k_pack(const GroupDesc* __restrict__ gd, 
                  uniform(G.lmax), uniform(G.pack_tiles), G.g, local % nt, local / nt, tile);
 }
 
+// Map-major layout (staged strategy): a map's orders of one parity are
+// contiguous in each U row, so a tile is one map, 16 orders m0, m0 + 2, ..
+// of one parity and 64 consecutive l: each row read is one contiguous run of
+// 16 (re, im) pairs, each order's 64 a_l^m one contiguous run of alm.
+constexpr int kPackOrders = 16;
+
+template <class T>
+__device__ __forceinline__ void pack_mm_item(Quad<const T> Ua, Quad<const T> Ub, double* __restrict__ alm,
+                                             const int64_t* __restrict__ alm_off, const int32_t* __restrict__ lmaxv,
+                                             const int32_t* __restrict__ tiles, const GroupDims& g, int ti, int v,
+                                             C2<double> (*tile)[kPackOrders + 1]) {
+    const int m0 = tiles[2 * ti], l0 = tiles[2 * ti + 1];
+    const int kpar = m0 & 1, kk0 = m0 >> 1;
+    const bool two = !Ub.null();
+    const int p = g.p, lmin_even = g.lmin[2 * kpar];
+    const int64_t N = g.N[kpar], colmap = int64_t(v) * g.cm[kpar], ck = g.ck[kpar];
+    constexpr int kIt = kPackL * kPackOrders / 256;
+    using P2 = typename Vec2<T>::type;
+    P2 ra[kIt], rb[kIt];
+#pragma unroll
+    for (int it = 0; it < kIt; ++it) {
+        const int i = threadIdx.x + 256 * it;
+        const int o = i % kPackOrders, li = i / kPackOrders;   // orders fastest: one contiguous run per row
+        const int m = m0 + 2 * o, l = l0 + li;
+        const bool ok = m <= p && l <= p;
+        const int lq = ok ? l : l0, kk = ok ? kk0 + o : kk0;
+        const int sel = (lq & 1) == (lmin_even & 1) ? 0 : 1;
+        const int blk = 2 * kpar + sel;
+        const int lp = (lq - g.lmin[blk]) >> 1;
+        const int64_t off = int64_t(lp) * N + colmap + int64_t(kk) * ck;
+        ra[it] = *reinterpret_cast<const P2*>(Ua.at(blk) + off);
+        if (two) rb[it] = *reinterpret_cast<const P2*>(Ub.at(blk) + off);
+    }
+#pragma unroll
+    for (int it = 0; it < kIt; ++it) {
+        const int i = threadIdx.x + 256 * it;
+        const int o = i % kPackOrders, li = i / kPackOrders;
+        C2<double> z = {double(ra[it][0]), double(ra[it][1])};
+        if (two) z = {z.x + double(rb[it][0]), z.y + double(rb[it][1])};
+        tile[li][o] = z;
+    }
+    const int L = lmaxv[v];
+    const int64_t base = alm_off[v];
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < kIt; ++it) {
+        const int i = threadIdx.x + 256 * it;
+        const int li = i % kPackL, o = i / kPackL;   // degrees fastest: one contiguous run of alm per order
+        const int m = m0 + 2 * o, l = l0 + li;
+        if (m > L || l < m || l > L) continue;
+        const int64_t at = 2 * (base + int64_t(m) * (2 * L + 1 - m) / 2 + l);
+        const C2<double> z = tile[li][o];
+        *reinterpret_cast<D2*>(alm + at) = D2{z.x, z.y};
+    }
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_pack_mm(const GroupDesc* __restrict__ gd, GroupRange gr, char* ws, int reg_a,
+                                                 int reg_b, double* __restrict__ alm) {
+    __shared__ C2<double> tile[kPackL][kPackOrders + 1];
+    int gi, local;
+    if (!locate_item(gr, blockIdx.x, gi, local)) return;
+    const GroupDesc& G = gd[gi];
+    const int nt = uniform(G.n_pack_tiles);
+    pack_mm_item<T>(region_quad<const T>(ws, G, reg_a), region_quad<const T>(ws, G, reg_b), alm, uniform(G.alm_off),
+                    uniform(G.lmax), uniform(G.pack_tiles), G.g, local % nt, local / nt, tile);
+}
+
+std::vector<int32_t> pack_tiles_mapmajor(int p) {
+    std::vector<int32_t> t;
+    for (int kpar = 0; kpar < 2; ++kpar)
+        for (int m0 = kpar; m0 <= p; m0 += 2 * kPackOrders)
+            for (int l0 = m0; l0 <= p; l0 += kPackL) {
+                t.push_back(m0);
+                t.push_back(l0);
+            }
+    return t;
+}
+
 std::vector<int32_t> pack_tiles(int p) {
     std::vector<int32_t> t;
     for (int m = 0; m <= p; ++m)
@@ -1664,21 +1743,36 @@ std::vector<int32_t> pack_tiles(int p) {
     return t;
 }
 
+// One launch per run of consecutive groups with the same column layout.
 template <class T>
 hipError_t launch_pack(const GroupLaunch& gl, int reg_a, int reg_b, double* alm, hipStream_t s) {
-    GroupRange r;
-    if (hipError_t e = make_range(
-            gl,
-            [](const GroupDesc& G) {
-                return int64_t(G.n_pack_tiles) * ((G.g.nmaps + kPackMaps - 1) / kPackMaps);
-            },
-            r);
-        e != hipSuccess)
-        return e;
-    if (r.start[r.n] == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_pack<T>, dim3(list_grid(gl, r, false)), dim3(256), 0, s, gl.dev, r, gl.ws, reg_a, reg_b,
-                       alm);
-    return hipGetLastError();
+    for (int i = 0; i < gl.n;) {
+        const bool mm = gl.host[gl.first + i].g.modemajor != 0;
+        int j = i + 1;
+        while (j < gl.n && (gl.host[gl.first + j].g.modemajor != 0) == mm) ++j;
+        GroupLaunch run = gl;
+        run.first = gl.first + i;
+        run.n = j - i;
+        GroupRange r;
+        hipError_t e = mm ? make_range(run,
+                                       [](const GroupDesc& G) {
+                                           return int64_t(G.n_pack_tiles) * ((G.g.nmaps + kPackMaps - 1) / kPackMaps);
+                                       },
+                                       r)
+                          : make_range(run, [](const GroupDesc& G) { return int64_t(G.n_pack_tiles) * G.g.nmaps; }, r);
+        if (e != hipSuccess) return e;
+        if (r.start[r.n] > 0) {
+            if (mm)
+                hipLaunchKernelGGL(k_pack<T>, dim3(list_grid(run, r, false)), dim3(256), 0, s, run.dev, r, run.ws,
+                                   reg_a, reg_b, alm);
+            else
+                hipLaunchKernelGGL(k_pack_mm<T>, dim3(list_grid(run, r, false)), dim3(256), 0, s, run.dev, r, run.ws,
+                                   reg_a, reg_b, alm);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
+        i = j;
+    }
+    return hipSuccess;
 }
 
 // U (FP32) -> U (FP64) in the same layout, zero where l < m or l > lmax of
@@ -1989,17 +2083,23 @@ hipError_t launch_ring_inverse(Blocks4<const double> D, RingTab rt, FftTab<doubl
 // is one contiguous run of 16 maps.
 
 constexpr int kFoldMaps = 16;
+// Maps per fold workgroup: 16 consecutive maps share a (row, mode) run in the
+// mode-major layout; in the map-major layout (staged strategy) a map's modes
+// are contiguous, so there a workgroup takes one map and its lanes walk
+// consecutive modes.
+__host__ __device__ inline int fold_maps(const GroupDims& g) { return g.modemajor ? kFoldMaps : 1; }
 
 // Work item `id` of one group: ring pair h of map group mg (ring_block_id).
 template <int NT, class BD, class BR>
 __device__ __forceinline__ void residual_fold_item(BD Df, BD Gs, BR Dr, const RingTab& rt, const GroupDims& g, int id,
                                                    C2<double>* partN, C2<double>* partS) {
-    constexpr int SL = NT / kFoldMaps;   // k slots per map
-    const int mgroups = (g.nmaps + kFoldMaps - 1) / kFoldMaps;
+    const int FM = fold_maps(g);          // maps per workgroup (16 or 1)
+    const int SL = NT / FM;               // k slots per map
+    const int mgroups = (g.nmaps + FM - 1) / FM;
     int mg, h;
     ring_block_id(id, mgroups, 2 * g.nside, mg, h);
-    const int m8 = threadIdx.x % kFoldMaps, slot = threadIdx.x / kFoldMaps;
-    const int map = mg * kFoldMaps + m8;
+    const int m8 = threadIdx.x % FM, slot = threadIdx.x / FM;
+    const int map = mg * FM + m8;
     const bool valid = map < g.nmaps;
     const int ns = g.nside, p = g.p;
     const bool equator = (h == 2 * ns);
@@ -2074,8 +2174,8 @@ __device__ __forceinline__ void residual_fold_item(BD Df, BD Gs, BR Dr, const Ri
         if (slot < T1) {
             C2<double> hn = zero, hs = zero;
             for (int q = 0; q < c; ++q) {
-                hn = cadd(hn, partN[(q * T1 + slot) * kFoldMaps + m8]);
-                hs = cadd(hs, partS[(q * T1 + slot) * kFoldMaps + m8]);
+                hn = cadd(hn, partN[(q * T1 + slot) * FM + m8]);
+                hs = cadd(hs, partS[(q * T1 + slot) * FM + m8]);
             }
             emit(slot, coeff(slot, hn), coeff(slot, hs));
         }
@@ -2143,7 +2243,10 @@ __global__ __launch_bounds__(NT) void k_residual_fold(const GroupDesc* __restric
 hipError_t launch_residual_fold(const GroupLaunch& gl, hipStream_t s) {
     GroupRange r;
     if (hipError_t e = make_range(
-            gl, [](const GroupDesc& G) { return int64_t((G.g.nmaps + kFoldMaps - 1) / kFoldMaps) * 2 * G.g.nside; },
+            gl,
+            [](const GroupDesc& G) {
+                return int64_t((G.g.nmaps + fold_maps(G.g) - 1) / fold_maps(G.g)) * 2 * G.g.nside;
+            },
             r);
         e != hipSuccess)
         return e;
