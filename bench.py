@@ -221,14 +221,21 @@ def make_inputs(torch, P, W, nside, nmaps):
     return maps
 
 
+P_OPTIONS = ("fold_grid", "pack_maps")
+
+
 def autotune(plan, maps, out, enabled):
     """Set-up step outside the timed region: the plan's autotuner picks the
-    GEMM workgroup schedules on these maps."""
+    GEMM workgroup schedules and the launch options (fold grid, pack tile
+    shape) on these maps."""
+    def options():
+        return {name: plan.option(name) for name in P_OPTIONS}
     if not enabled:
-        return {"enabled": False, "schedules": plan.schedules}
+        return {"enabled": False, "schedules": plan.schedules, "options": options()}
     t0 = time.perf_counter()
     ms, _ = plan.autotune(maps, reps=3, out=out)
-    return {"enabled": True, "schedules": plan.schedules, "best_ms": ms, "seconds": time.perf_counter() - t0}
+    return {"enabled": True, "schedules": plan.schedules, "options": options(), "best_ms": ms,
+            "seconds": time.perf_counter() - t0}
 
 
 def map0_sha256(maps, npix):

@@ -302,8 +302,8 @@ int hp2sph_set_schedule(hp2sph_plan_t plan, int32_t sched);
  * order; the analysis modes merge every nside group into one GEMM per role),
  * times hp2sph_analyze of the caller's maps under each candidate schedule of
  * that GEMM, the others held at their current choice, and keeps the fastest;
- * then the same for the work grid of the refinement's fold
- * (hp2sph_set_fold_grid).  A candidate replaces the current choice only
+ * then the same for the launch options of the fold and the pack
+ * (hp2sph_set_option).  A candidate replaces the current choice only
  * when it is more than 0.5 % faster (the run-to-run spread of a timed
  * analysis).  Each timing is the fastest of `reps` analyses (HIP events on
  * `stream`, after one untimed analysis).  Synchronous: returns after the last
@@ -329,20 +329,29 @@ int hp2sph_autotune(hp2sph_plan_t plan, const double* maps, double* alm, void* w
 int hp2sph_schedules(hp2sph_plan_t plan, int32_t* out, int32_t cap, int32_t* count);
 
 /*
- * Work grid of the refinement's residual fold.  The stages of an analysis
- * run as one launch over a work list that holds every nside group of the
- * plan (items grouped by nside, largest first; a fold item is one ring pair
- * of 16 maps).  Grid 0: one workgroup per item (the default).  Grid g >= 8:
- * a persistent launch of g workgroups (rounded down to a multiple of 8, so
- * that each item keeps its XCD) that walk the list.  Results are bitwise the
- * same under every grid.  hp2sph_autotune chooses it after the GEMM
- * schedules (candidates 0, 2 and 4 workgroups per compute unit) and
- * remembers its choice per plan shape.  Host state only, like
- * hp2sph_set_schedule.  Errors: ESTATE, EINVAL (a grid below 0 or between 1
- * and 7), null output.
+ * Launch options of the work-list stages.  The stages of an analysis run as
+ * one launch over a work list that holds every nside group of the plan
+ * (items grouped by nside, largest first).  Results are bitwise the same
+ * under every value.  hp2sph_autotune chooses them after the GEMM schedules
+ * and remembers its choices per plan shape.  Host state only, like
+ * hp2sph_set_schedule.
+ *   HP2SPH_OPT_FOLD_GRID  work grid of the refinement's residual fold (an
+ *       item is one ring pair of 16 maps, or of one map in the staged
+ *       layout): 0 for one workgroup per item (the default), or g >= 8 for a
+ *       persistent launch of g workgroups (rounded down to a multiple of 8,
+ *       so that each item keeps its XCD) that walk the list; the autotuner
+ *       tries 0, 2 and 4 workgroups per compute unit.
+ *   HP2SPH_OPT_PACK_MAPS  maps per pack tile (tile shape of the a_lm pack in
+ *       the mode-major layout of the per-order tables: 64 degrees x 16, 32 or
+ *       64 maps; 32 by default); the autotuner tries all three.
+ * Errors: ESTATE, EINVAL (unknown option, value out of range, null output).
  */
-int hp2sph_set_fold_grid(hp2sph_plan_t plan, int32_t grid);
-int hp2sph_fold_grid(hp2sph_plan_t plan, int32_t* grid);
+enum {
+    HP2SPH_OPT_FOLD_GRID = 0,
+    HP2SPH_OPT_PACK_MAPS = 1
+};
+int hp2sph_set_option(hp2sph_plan_t plan, int32_t option, int32_t value);
+int hp2sph_get_option(hp2sph_plan_t plan, int32_t option, int32_t* value);
 
 /*
  * Host-only inspection of a schedule (no GPU needed): the workgroup -> (problem,

@@ -54,11 +54,12 @@ EXPORTED = [
     "hp2sph_power_spectrum", "hp2sph_plan_destroy", "hp2sph_last_error", "hp2sph_host_table",
     "hp2sph_profile", "hp2sph_profile_read", "hp2sph_plan_create_ex", "hp2sph_plan_strategy",
     "hp2sph_analyze_iterative", "hp2sph_set_schedule", "hp2sph_autotune", "hp2sph_schedules",
-    "hp2sph_schedule_map", "hp2sph_gemm_check", "hp2sph_analyze_noalloc", "hp2sph_set_fold_grid",
-    "hp2sph_fold_grid",
+    "hp2sph_schedule_map", "hp2sph_gemm_check", "hp2sph_analyze_noalloc", "hp2sph_set_option",
+    "hp2sph_get_option",
 ]
 STRATEGIES = {"auto": 0, "staged": 1, "tables": 2}
 SCHEDULES = ["xcd_round_robin", "xcd_balanced", "linear", "linear_rows"]
+OPTIONS = ["fold_grid", "pack_maps"]
 MAX_TUNE_REPS = 100
 NSTAGES = 13
 STAGES = ["ring_forward", "pole", "gemm_analysis", "sweep_analysis", "pack", "unpack",
@@ -88,8 +89,8 @@ _lib.hp2sph_schedule_map.argtypes = [_i32, _vp, _vp, _vp, _i32, _vp, ctypes.c_in
 _lib.hp2sph_host_table.argtypes = [_i32, _i32, _i32, _vp, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
 _lib.hp2sph_gemm_check.argtypes = [_i32, _i32, _i32, _i32] + [ctypes.POINTER(ctypes.c_int64)] * 3
 _lib.hp2sph_analyze_noalloc.argtypes = [_vp, _vp, _vp, _vp]
-_lib.hp2sph_set_fold_grid.argtypes = [_vp, _i32]
-_lib.hp2sph_fold_grid.argtypes = [_vp, ctypes.POINTER(_i32)]
+_lib.hp2sph_set_option.argtypes = [_vp, _i32, _i32]
+_lib.hp2sph_get_option.argtypes = [_vp, _i32, ctypes.POINTER(_i32)]
 NOALLOC_WORKSPACE = 256 << 20
 for _f in EXPORTED:
     if _f not in ("hp2sph_last_error",):
@@ -291,7 +292,7 @@ class Plan:
 
     def autotune(self, maps, reps=3, out=None):
         """Time the analysis of `maps` under each candidate GEMM schedule and
-        fold grid and keep the fastest (synchronous).  Returns (ms per
+        launch option and keep the fastest (synchronous).  Returns (ms per
         analysis, alm)."""
         _torch()
         self._maps(maps)
@@ -310,17 +311,21 @@ class Plan:
         _check(_lib.hp2sph_schedules(self._h, buf, n.value, ctypes.byref(n)), "schedules")
         return [SCHEDULES[buf[i]] for i in range(n.value)]
 
-    def set_fold_grid(self, grid):
-        """Work grid of the refinement's fold: 0 for one workgroup per work
-        item, else a persistent grid of that many workgroups."""
-        _check(_lib.hp2sph_set_fold_grid(self._h, int(grid)), "set_fold_grid")
+    def set_option(self, name, value):
+        """Launch option of a work-list stage (one of OPTIONS): 'fold_grid'
+        (0, or a persistent grid of that many workgroups) or 'pack_maps'
+        (maps per pack tile: 16, 32 or 64)."""
+        if name not in OPTIONS:
+            raise ValueError(f"option must be one of {OPTIONS}")
+        _check(_lib.hp2sph_set_option(self._h, OPTIONS.index(name), int(value)), "set_option")
 
-    @property
-    def fold_grid(self):
-        """Work grid of the fold in use."""
-        g = _i32(0)
-        _check(_lib.hp2sph_fold_grid(self._h, ctypes.byref(g)), "fold_grid")
-        return g.value
+    def option(self, name):
+        """Value of a launch option in use."""
+        if name not in OPTIONS:
+            raise ValueError(f"option must be one of {OPTIONS}")
+        v = _i32(0)
+        _check(_lib.hp2sph_get_option(self._h, OPTIONS.index(name), ctypes.byref(v)), "get_option")
+        return v.value
 
     def profile(self, enable):
         """Start (True, clears the accumulators) or stop per-stage event timing."""

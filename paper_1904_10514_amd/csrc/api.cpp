@@ -209,6 +209,7 @@ struct hp2sph_plan_s {
     hp2sph::GroupDesc* d_gdesc = nullptr;
     std::vector<std::pair<int, int>> ring_spans;
     int fold_grid = 0;
+    int pack_maps = 32;               // maps per pack tile (mode-major layout): 16, 32 or 64
     // per-map offsets of the whole batch (C_l in one launch)
     int64_t* d_alm_off = nullptr;
     int64_t* d_cl_off = nullptr;
@@ -1078,10 +1079,16 @@ DevTables<float>& tabs<float>(Group& G) { return G.t32; }
 
 // Work-list launch over groups [first, first + n) of the plan.
 GroupLaunch span_launch(hp2sph_plan_t plan, int first, int n, void* ws, int grid_cap = 0) {
-    return GroupLaunch{plan->d_gdesc, plan->gdesc.data(), first, n, static_cast<char*>(ws), grid_cap};
+    return GroupLaunch{plan->d_gdesc, plan->gdesc.data(), first, n, static_cast<char*>(ws), grid_cap, 0};
 }
 GroupLaunch all_groups(hp2sph_plan_t plan, void* ws, int grid_cap = 0) {
     return span_launch(plan, 0, int(plan->groups.size()), ws, grid_cap);
+}
+// The pack launch over groups [first, first + n), with the plan's tile shape.
+GroupLaunch pack_launch(hp2sph_plan_t plan, int first, int n, void* ws) {
+    GroupLaunch gl = span_launch(plan, first, n, ws);
+    gl.variant = plan->pack_maps;
+    return gl;
 }
 
 // S1 of every group into region `reg`: one launch per span of groups that
@@ -1120,7 +1127,7 @@ int analysis_all(hp2sph_plan_t plan, const double* maps, double* alm, void* ws, 
         for (int b = 0; b < 4; ++b) Gv.p[b] = tabs<T>(G).givens[b];
         STAGE(3, launch_sweep_fwd<T>(blocks_at<T>(ws, G.off_U, G, G.rows_U), Gv, G.dims, s));
     }
-    STAGE(4, launch_pack<T>(all_groups(plan, ws), kRegU, -1, alm, s));
+    STAGE(4, launch_pack<T>(pack_launch(plan, 0, int(plan->groups.size()), ws), kRegU, -1, alm, s));
     return HP2SPH_OK;
 }
 
@@ -1204,7 +1211,7 @@ int refine_all(hp2sph_plan_t plan, const double* maps, double* alm, void* ws, hi
     const GemmList<float>& ga = plan->m_ana32;
     STAGE(2, launch_gemm<float>(ga.dev, ga.tmap, ga.slots, static_cast<const float*>(ws), static_cast<float*>(ws), s));
     if (int e = staged_sweeps(kRegU, true)) return e;
-    STAGE(4, launch_pack<float>(all_groups(plan, ws), kRegUa, kRegU, alm, s));
+    STAGE(4, launch_pack<float>(pack_launch(plan, 0, int(plan->groups.size()), ws), kRegUa, kRegU, alm, s));
     return HP2SPH_OK;
 }
 
@@ -1225,9 +1232,9 @@ int equal_weight_apply(hp2sph_plan_t plan, Group& G, Blocks4<double> W, double* 
     if (add) {
         Blocks4<double> Ua = blocks_at<double>(ws, G.off_Ua, G, G.rows_U);
         STAGE(5, launch_unpack(alm, G.d_alm_off, G.d_lmax, Ua, G.dims, s));
-        STAGE(4, launch_pack<double>(span_launch(plan, G.index, 1, ws), kRegUa, kRegU, alm, s));
+        STAGE(4, launch_pack<double>(pack_launch(plan, G.index, 1, ws), kRegUa, kRegU, alm, s));
     } else {
-        STAGE(4, launch_pack<double>(span_launch(plan, G.index, 1, ws), kRegU, -1, alm, s));
+        STAGE(4, launch_pack<double>(pack_launch(plan, G.index, 1, ws), kRegU, -1, alm, s));
     }
     return HP2SPH_OK;
 }
@@ -1256,7 +1263,7 @@ int jacobi_pass(hp2sph_plan_t plan, Group& G, const double* maps, double* alm, i
             STAGE(12, launch_gemm<double>(G.adj64.dev, G.adj64.tmap, G.adj64.slots, Wr.p[0], U.p[0], s));
             STAGE(5, launch_accumulate(cblocks(U), Ua, G.d_lmax, G.dims, false, s));
         }
-        STAGE(4, launch_pack<double>(span_launch(plan, G.index, 1, ws), kRegUa, -1, alm, s));
+        STAGE(4, launch_pack<double>(pack_launch(plan, G.index, 1, ws), kRegUa, -1, alm, s));
         return HP2SPH_OK;
     }
     if (int e = equal_weight_apply(plan, G, Wf, alm, false, ws, s)) return e;
@@ -1395,14 +1402,15 @@ void build_work_lists(hp2sph_plan_t plan) {
 //
 // Key: the device's architecture and compute-unit count, the mode and, per
 // group, nside, number of maps and strategy.  Value: the schedule of every
-// tuned GEMM (in the order hp2sph_schedules reports them) and the fold's
-// work grid.  Kept per process; HP2SPH_TUNE_CACHE names a text file that is read
+// tuned GEMM (in the order hp2sph_schedules reports them), the fold's work
+// grid and the pack's tile shape.  Kept per process; HP2SPH_TUNE_CACHE names a text file that is read
 // once and appended to (one "key = values" line per entry, the last line of
 // a key wins), so tuned shapes start tuned in later processes too.
 
 struct TuneChoice {
     std::vector<int> sched;
     int fold_grid = 0;
+    int pack_maps = 32;
 };
 
 std::mutex g_tune_mu;
@@ -1449,9 +1457,10 @@ void read_tune_file_locked() {
             v.push_back(x);
             q = end;
         }
-        if (v.empty()) continue;
+        if (v.size() < 2) continue;
         c.fold_grid = int(v[0]);
-        for (size_t i = 1; i < v.size(); ++i) c.sched.push_back(int(v[i]));
+        c.pack_maps = int(v[1]);
+        for (size_t i = 2; i < v.size(); ++i) c.sched.push_back(int(v[i]));
         tune_cache()[l.substr(0, eq)] = c;
     }
     std::fclose(f);
@@ -1465,7 +1474,7 @@ void store_tune(const hp2sph_plan_s* plan, const TuneChoice& c) {
     const char* path = std::getenv("HP2SPH_TUNE_CACHE");
     if (!path || !*path) return;
     if (FILE* f = std::fopen(path, "a")) {
-        std::string line = key + " = " + std::to_string(c.fold_grid);
+        std::string line = key + " = " + std::to_string(c.fold_grid) + " " + std::to_string(c.pack_maps);
         for (int x : c.sched) line += " " + std::to_string(x);
         line += "\n";
         std::fputs(line.c_str(), f);
@@ -1663,6 +1672,7 @@ int hp2sph_plan_create_ex(const int32_t* nside, const int32_t* lmax, int32_t bat
                     for (size_t i = 0; i < lists.size(); ++i)
                         if (c.sched[i] >= 0 && c.sched[i] < HP2SPH_NSCHED) lists[i]->use(c.sched[i]);
                     plan->fold_grid = c.fold_grid;
+                    if (c.pack_maps == 16 || c.pack_maps == 32 || c.pack_maps == 64) plan->pack_maps = c.pack_maps;
                 }
             }
         }
@@ -1822,18 +1832,30 @@ int hp2sph_schedules(hp2sph_plan_t plan, int32_t* out, int32_t cap, int32_t* cou
     return HP2SPH_OK;
 }
 
-int hp2sph_set_fold_grid(hp2sph_plan_t plan, int32_t grid) {
+int hp2sph_set_option(hp2sph_plan_t plan, int32_t option, int32_t value) {
     if (int e = check_plan(plan)) return e;
-    if (grid < 0 || (grid > 0 && grid < 8)) return fail(HP2SPH_EINVAL, "the fold grid is 0 or at least 8 workgroups");
-    plan->fold_grid = grid / 8 * 8;
-    return HP2SPH_OK;
+    switch (option) {
+        case HP2SPH_OPT_FOLD_GRID:
+            if (value < 0 || (value > 0 && value < 8))
+                return fail(HP2SPH_EINVAL, "the fold grid is 0 or at least 8 workgroups");
+            plan->fold_grid = value / 8 * 8;
+            return HP2SPH_OK;
+        case HP2SPH_OPT_PACK_MAPS:
+            if (value != 16 && value != 32 && value != 64) return fail(HP2SPH_EINVAL, "maps per pack tile: 16, 32 or 64");
+            plan->pack_maps = value;
+            return HP2SPH_OK;
+        default: return fail(HP2SPH_EINVAL, "unknown option");
+    }
 }
 
-int hp2sph_fold_grid(hp2sph_plan_t plan, int32_t* grid) {
+int hp2sph_get_option(hp2sph_plan_t plan, int32_t option, int32_t* value) {
     if (int e = check_plan(plan)) return e;
-    if (!grid) return fail(HP2SPH_EINVAL, "null output");
-    *grid = plan->fold_grid;
-    return HP2SPH_OK;
+    if (!value) return fail(HP2SPH_EINVAL, "null output");
+    switch (option) {
+        case HP2SPH_OPT_FOLD_GRID: *value = plan->fold_grid; return HP2SPH_OK;
+        case HP2SPH_OPT_PACK_MAPS: *value = plan->pack_maps; return HP2SPH_OK;
+        default: return fail(HP2SPH_EINVAL, "unknown option");
+    }
 }
 
 int hp2sph_autotune(hp2sph_plan_t plan, const double* maps, double* alm, void* workspace, size_t workspace_bytes,
@@ -1915,10 +1937,29 @@ int hp2sph_autotune(hp2sph_plan_t plan, const double* maps, double* alm, void* w
             plan->fold_grid = keep;
         }
     }
+    // tile shape of the pack (maps per tile)
+    {
+        int keep = plan->pack_maps;
+        for (int c : {32, 16, 64}) {
+            if (c == keep) continue;
+            plan->pack_maps = c;
+            double t = 0.0;
+            if (int e = timed(t)) {
+                plan->pack_maps = keep;
+                return e;
+            }
+            if (t < best * (1.0 - 0.005)) {
+                best = t;
+                keep = c;
+            }
+            plan->pack_maps = keep;
+        }
+    }
     {
         TuneChoice c;
         for (GemmSched* L : lists) c.sched.push_back(L->sched);
         c.fold_grid = plan->fold_grid;
+        c.pack_maps = plan->pack_maps;
         store_tune(plan, c);
     }
     // leave alm holding the analysis under the chosen schedules

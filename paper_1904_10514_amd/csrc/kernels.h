@@ -96,14 +96,17 @@ struct GroupRange {
 };
 
 // Host side of a work-list launch: the device descriptors, their host
-// copies (for the item counts), the group span, the workspace and the grid
-// cap (0: one workgroup per item; else the persistent grid size).
+// copies (for the item counts), the group span, the workspace, the grid
+// cap (0: one workgroup per item; else the persistent grid size) and the
+// kernel variant where a stage has several (the pack's maps per tile: 16,
+// 32 or 64; 0 for the default).
 struct GroupLaunch {
     const GroupDesc* dev;
     const GroupDesc* host;
     int first, n;
     char* ws;
     int grid_cap;
+    int variant;
 };
 
 // One product of a grouped GEMM: C[m][n] = sum_k A[k][m] B[k][n].

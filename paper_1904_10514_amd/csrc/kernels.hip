@@ -1571,15 +1571,17 @@ __device__ __forceinline__ bool pack_index(const GroupDims& g, int blk, int64_t 
 // read row by row (each row a contiguous run of maps in the mode-major
 // layout) and every map's 64 a_l^m are written as one contiguous run of
 // alm.  With Ub given, writes Ua + Ub (the refined a_lm), added in FP64.
+// Tiles of 64 degrees and PM maps (PM = 16, 32 or 64: the tile shapes the
+// autotuner chooses among; 32 by default).
 constexpr int kPackL = 64, kPackMaps = 32;
-static_assert(kPackL * kPackMaps % 256 == 0, "a pack tile is a whole number of 256-thread sweeps");
 
 // Pack tile `ti` (an (m, l0) pair of `tiles`) for the maps of map group `mg`.
-template <class T>
+template <class T, int kPackMaps>
 __device__ __forceinline__ void pack_item(Quad<const T> Ua, Quad<const T> Ub, double* __restrict__ alm,
                                           const int64_t* __restrict__ alm_off, const int32_t* __restrict__ lmaxv,
                                           const int32_t* __restrict__ tiles, const GroupDims& g, int ti, int mg,
                                           C2<double> (*tile)[kPackMaps + 1]) {
+    static_assert(kPackL * kPackMaps % 256 == 0, "a pack tile is a whole number of 256-thread sweeps");
     const int m = tiles[2 * ti], l0 = tiles[2 * ti + 1];
     const int v0 = mg * kPackMaps;
     const int kpar = m & 1, kk = m >> 1;
@@ -1642,16 +1644,16 @@ __device__ __forceinline__ void pack_item(Quad<const T> Ua, Quad<const T> Ub, do
 // Pack over the work list of every group of the launch: U of region reg_a
 // (plus region reg_b when >= 0).  Items are (pack tile, map group) with the
 // tile fastest; one workgroup per item.
-template <class T>
+template <class T, int PM>
 __global__ __launch_bounds__(256) void k_pack(const GroupDesc* __restrict__ gd, GroupRange gr, char* ws, int reg_a,
                                               int reg_b, double* __restrict__ alm) {
-    __shared__ C2<double> tile[kPackL][kPackMaps + 1];
+    __shared__ C2<double> tile[kPackL][PM + 1];
     int gi, local;
     if (!locate_item(gr, blockIdx.x, gi, local)) return;
     const GroupDesc& G = gd[gi];
     const int nt = uniform(G.n_pack_tiles);
-    pack_item<T>(region_quad<const T>(ws, G, reg_a), region_quad<const T>(ws, G, reg_b), alm, uniform(G.alm_off),
-                 uniform(G.lmax), uniform(G.pack_tiles), G.g, local % nt, local / nt, tile);
+    pack_item<T, PM>(region_quad<const T>(ws, G, reg_a), region_quad<const T>(ws, G, reg_b), alm, uniform(G.alm_off),
+                     uniform(G.lmax), uniform(G.pack_tiles), G.g, local % nt, local / nt, tile);
 }
 
 // Map-major layout (staged strategy): a map's orders of one parity are
@@ -1754,17 +1756,22 @@ hipError_t launch_pack(const GroupLaunch& gl, int reg_a, int reg_b, double* alm,
         run.first = gl.first + i;
         run.n = j - i;
         GroupRange r;
+        const int pm = gl.variant == 16 || gl.variant == 64 ? gl.variant : kPackMaps;
         hipError_t e = mm ? make_range(run,
-                                       [](const GroupDesc& G) {
-                                           return int64_t(G.n_pack_tiles) * ((G.g.nmaps + kPackMaps - 1) / kPackMaps);
+                                       [pm](const GroupDesc& G) {
+                                           return int64_t(G.n_pack_tiles) * ((G.g.nmaps + pm - 1) / pm);
                                        },
                                        r)
                           : make_range(run, [](const GroupDesc& G) { return int64_t(G.n_pack_tiles) * G.g.nmaps; }, r);
         if (e != hipSuccess) return e;
         if (r.start[r.n] > 0) {
-            if (mm)
-                hipLaunchKernelGGL(k_pack<T>, dim3(list_grid(run, r, false)), dim3(256), 0, s, run.dev, r, run.ws,
-                                   reg_a, reg_b, alm);
+            const dim3 grid(list_grid(run, r, false));
+            if (mm && pm == 16)
+                hipLaunchKernelGGL((k_pack<T, 16>), grid, dim3(256), 0, s, run.dev, r, run.ws, reg_a, reg_b, alm);
+            else if (mm && pm == 64)
+                hipLaunchKernelGGL((k_pack<T, 64>), grid, dim3(256), 0, s, run.dev, r, run.ws, reg_a, reg_b, alm);
+            else if (mm)
+                hipLaunchKernelGGL((k_pack<T, 32>), grid, dim3(256), 0, s, run.dev, r, run.ws, reg_a, reg_b, alm);
             else
                 hipLaunchKernelGGL(k_pack_mm<T>, dim3(list_grid(run, r, false)), dim3(256), 0, s, run.dev, r, run.ws,
                                    reg_a, reg_b, alm);
