@@ -344,11 +344,18 @@ int hp2sph_schedules(hp2sph_plan_t plan, int32_t* out, int32_t cap, int32_t* cou
  *   HP2SPH_OPT_PACK_MAPS  maps per pack tile (tile shape of the a_lm pack in
  *       the mode-major layout of the per-order tables: 64 degrees x 16, 32 or
  *       64 maps; 32 by default); the autotuner tries all three.
+ *   HP2SPH_OPT_RING_ORDER  order in which the ring transform's items (one
+ *       ring pair of one map each) meet the workgroups: 0 (default) deals ring
+ *       pairs to the 8 XCDs in turn and runs the maps of a pair back to back
+ *       on its XCD; 1 runs pairs in order, maps of a pair back to back; 2
+ *       runs maps in order, all pairs of a map back to back.  The autotuner
+ *       tries all three (not for HP2SPH_EQUAL_WEIGHT plans).
  * Errors: ESTATE, EINVAL (unknown option, value out of range, null output).
  */
 enum {
     HP2SPH_OPT_FOLD_GRID = 0,
-    HP2SPH_OPT_PACK_MAPS = 1
+    HP2SPH_OPT_PACK_MAPS = 1,
+    HP2SPH_OPT_RING_ORDER = 2
 };
 int hp2sph_set_option(hp2sph_plan_t plan, int32_t option, int32_t value);
 int hp2sph_get_option(hp2sph_plan_t plan, int32_t option, int32_t* value);

@@ -210,6 +210,7 @@ struct hp2sph_plan_s {
     std::vector<std::pair<int, int>> ring_spans;
     int fold_grid = 0;
     int pack_maps = 32;               // maps per pack tile (mode-major layout): 16, 32 or 64
+    int ring_order = 0;               // item order of the ring transform: 0 (XCD-aware), 1, 2
     // per-map offsets of the whole batch (C_l in one launch)
     int64_t* d_alm_off = nullptr;
     int64_t* d_cl_off = nullptr;
@@ -1084,6 +1085,13 @@ GroupLaunch span_launch(hp2sph_plan_t plan, int first, int n, void* ws, int grid
 GroupLaunch all_groups(hp2sph_plan_t plan, void* ws, int grid_cap = 0) {
     return span_launch(plan, 0, int(plan->groups.size()), ws, grid_cap);
 }
+// The ring-transform launch over groups [first, first + n), with the plan's
+// item order.
+GroupLaunch ring_launch(hp2sph_plan_t plan, int first, int n, void* ws) {
+    GroupLaunch gl = span_launch(plan, first, n, ws);
+    gl.variant = plan->ring_order;
+    return gl;
+}
 // The pack launch over groups [first, first + n), with the plan's tile shape.
 GroupLaunch pack_launch(hp2sph_plan_t plan, int first, int n, void* ws) {
     GroupLaunch gl = span_launch(plan, first, n, ws);
@@ -1095,7 +1103,7 @@ GroupLaunch pack_launch(hp2sph_plan_t plan, int first, int n, void* ws) {
 // share the ring kernels' thread count.
 int ring_forward_all(hp2sph_plan_t plan, const double* maps, int reg, void* ws, hipStream_t s) {
     for (const auto& sp : plan->ring_spans)
-        STAGE(0, launch_ring_forward(maps, span_launch(plan, sp.first, sp.second, ws), reg, s));
+        STAGE(0, launch_ring_forward(maps, ring_launch(plan, sp.first, sp.second, ws), reg, s));
     return HP2SPH_OK;
 }
 
@@ -1403,7 +1411,7 @@ void build_work_lists(hp2sph_plan_t plan) {
 // Key: the device's architecture and compute-unit count, the mode and, per
 // group, nside, number of maps and strategy.  Value: the schedule of every
 // tuned GEMM (in the order hp2sph_schedules reports them), the fold's work
-// grid and the pack's tile shape.  Kept per process; HP2SPH_TUNE_CACHE names a text file that is read
+// grid, the pack's tile shape and the ring transform's item order.  Kept per process; HP2SPH_TUNE_CACHE names a text file that is read
 // once and appended to (one "key = values" line per entry, the last line of
 // a key wins), so tuned shapes start tuned in later processes too.
 
@@ -1411,6 +1419,7 @@ struct TuneChoice {
     std::vector<int> sched;
     int fold_grid = 0;
     int pack_maps = 32;
+    int ring_order = 0;
 };
 
 std::mutex g_tune_mu;
@@ -1457,10 +1466,11 @@ void read_tune_file_locked() {
             v.push_back(x);
             q = end;
         }
-        if (v.size() < 2) continue;
+        if (v.size() < 3) continue;
         c.fold_grid = int(v[0]);
         c.pack_maps = int(v[1]);
-        for (size_t i = 2; i < v.size(); ++i) c.sched.push_back(int(v[i]));
+        c.ring_order = int(v[2]);
+        for (size_t i = 3; i < v.size(); ++i) c.sched.push_back(int(v[i]));
         tune_cache()[l.substr(0, eq)] = c;
     }
     std::fclose(f);
@@ -1474,7 +1484,8 @@ void store_tune(const hp2sph_plan_s* plan, const TuneChoice& c) {
     const char* path = std::getenv("HP2SPH_TUNE_CACHE");
     if (!path || !*path) return;
     if (FILE* f = std::fopen(path, "a")) {
-        std::string line = key + " = " + std::to_string(c.fold_grid) + " " + std::to_string(c.pack_maps);
+        std::string line = key + " = " + std::to_string(c.fold_grid) + " " + std::to_string(c.pack_maps) + " " +
+                           std::to_string(c.ring_order);
         for (int x : c.sched) line += " " + std::to_string(x);
         line += "\n";
         std::fputs(line.c_str(), f);
@@ -1673,6 +1684,7 @@ int hp2sph_plan_create_ex(const int32_t* nside, const int32_t* lmax, int32_t bat
                         if (c.sched[i] >= 0 && c.sched[i] < HP2SPH_NSCHED) lists[i]->use(c.sched[i]);
                     plan->fold_grid = c.fold_grid;
                     if (c.pack_maps == 16 || c.pack_maps == 32 || c.pack_maps == 64) plan->pack_maps = c.pack_maps;
+                    if (c.ring_order >= 0 && c.ring_order <= 2) plan->ring_order = c.ring_order;
                 }
             }
         }
@@ -1844,6 +1856,10 @@ int hp2sph_set_option(hp2sph_plan_t plan, int32_t option, int32_t value) {
             if (value != 16 && value != 32 && value != 64) return fail(HP2SPH_EINVAL, "maps per pack tile: 16, 32 or 64");
             plan->pack_maps = value;
             return HP2SPH_OK;
+        case HP2SPH_OPT_RING_ORDER:
+            if (value < 0 || value > 2) return fail(HP2SPH_EINVAL, "ring item order: 0, 1 or 2");
+            plan->ring_order = value;
+            return HP2SPH_OK;
         default: return fail(HP2SPH_EINVAL, "unknown option");
     }
 }
@@ -1854,6 +1870,7 @@ int hp2sph_get_option(hp2sph_plan_t plan, int32_t option, int32_t* value) {
     switch (option) {
         case HP2SPH_OPT_FOLD_GRID: *value = plan->fold_grid; return HP2SPH_OK;
         case HP2SPH_OPT_PACK_MAPS: *value = plan->pack_maps; return HP2SPH_OK;
+        case HP2SPH_OPT_RING_ORDER: *value = plan->ring_order; return HP2SPH_OK;
         default: return fail(HP2SPH_EINVAL, "unknown option");
     }
 }
@@ -1937,22 +1954,25 @@ int hp2sph_autotune(hp2sph_plan_t plan, const double* maps, double* alm, void* w
             plan->fold_grid = keep;
         }
     }
-    // tile shape of the pack (maps per tile)
-    {
-        int keep = plan->pack_maps;
-        for (int c : {32, 16, 64}) {
+    // tile shape of the pack (maps per tile), item order of the ring transform
+    for (int which = 0; which < 2; ++which) {
+        if (which == 1 && plan->mode == HP2SPH_EQUAL_WEIGHT) break;   // no forward ring transform there
+        int& opt = which == 0 ? plan->pack_maps : plan->ring_order;
+        const std::vector<int> cand = which == 0 ? std::vector<int>{32, 16, 64} : std::vector<int>{0, 1, 2};
+        int keep = opt;
+        for (int c : cand) {
             if (c == keep) continue;
-            plan->pack_maps = c;
+            opt = c;
             double t = 0.0;
             if (int e = timed(t)) {
-                plan->pack_maps = keep;
+                opt = keep;
                 return e;
             }
             if (t < best * (1.0 - 0.005)) {
                 best = t;
                 keep = c;
             }
-            plan->pack_maps = keep;
+            opt = keep;
         }
     }
     {
@@ -1960,6 +1980,7 @@ int hp2sph_autotune(hp2sph_plan_t plan, const double* maps, double* alm, void* w
         for (GemmSched* L : lists) c.sched.push_back(L->sched);
         c.fold_grid = plan->fold_grid;
         c.pack_maps = plan->pack_maps;
+        c.ring_order = plan->ring_order;
         store_tune(plan, c);
     }
     // leave alm holding the analysis under the chosen schedules

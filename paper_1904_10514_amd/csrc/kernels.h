@@ -99,7 +99,7 @@ struct GroupRange {
 // copies (for the item counts), the group span, the workspace, the grid
 // cap (0: one workgroup per item; else the persistent grid size) and the
 // kernel variant where a stage has several (the pack's maps per tile: 16,
-// 32 or 64; 0 for the default).
+// 32 or 64; the ring transform's item order 0, 1 or 2; 0 for the default).
 struct GroupLaunch {
     const GroupDesc* dev;
     const GroupDesc* host;
@@ -212,7 +212,8 @@ __host__ __device__ constexpr int ring_threads(int fft_max) { return fft_max <= 
 
 // S1: per-ring real DFT, shift to unshifted longitudes, Nyquist rule and the
 // north/south combination, written into Dsym rows 1 .. 2 nside of region
-// `reg` of every group of the launch (FP64).  Work item: (map, ring pair).
+// `reg` of every group of the launch (FP64).  Work item: (map, ring pair), in
+// the order gl.variant selects (0: XCD-aware, 1: pair-major, 2: map-major).
 hipError_t launch_ring_forward(const double* maps, const GroupLaunch& gl, int reg, hipStream_t s);
 
 // Equal-weight analysis, eq. (healsph): longitude sums of every ring for all

@@ -346,7 +346,21 @@ __device__ __forceinline__ DftOut<T> ring_dft(C2<T>* buf, int L, int M_blue, con
 // the same Dsym rows then meet in that XCD's L2.
 // `id` is the workgroup's index among the nmaps * npairs items of its group
 // (a multiple of 8 away from its launch index, so id mod 8 is its XCD).
-__device__ __forceinline__ void ring_block_id(int id, int nmaps, int npairs, int& map, int& h) {
+//   order 0 (default): ring pair h on XCD h mod 8, the maps of a pair back to
+//     back there (their writes of one Dsym row meet in that XCD's L2);
+//   order 1: pairs in order, the maps of a pair back to back, no XCD placement;
+//   order 2: maps in order, all pairs of a map back to back.
+__device__ __forceinline__ void ring_block_id(int id, int nmaps, int npairs, int& map, int& h, int order = 0) {
+    if (order == 1) {
+        map = id % nmaps;
+        h = id / nmaps + 1;
+        return;
+    }
+    if (order == 2) {
+        map = id / npairs;
+        h = id % npairs + 1;
+        return;
+    }
     if ((npairs & 7) == 0) {
         const int x = id & 7, s = id >> 3;
         h = (s / nmaps) * 8 + x + 1;
@@ -533,9 +547,10 @@ __host__ __device__ constexpr int ring_buffer_slots(int fft_max) {
 template <class T, int NT>
 __device__ __forceinline__ void ring_forward_item(const double* __restrict__ maps,
                                                   const int64_t* __restrict__ map_off, const RingTab rt,
-                                                  const FftTab<T> ft, const RingOut<T> o, int id, C2<T>* buf) {
+                                                  const FftTab<T> ft, const RingOut<T> o, int id, C2<T>* buf,
+                                                  int order) {
     int b, h;
-    ring_block_id(id, o.nmaps, 2 * o.nside, b, h);
+    ring_block_id(id, o.nmaps, 2 * o.nside, b, h, order);
     const int ns = o.nside, p = o.p;
     const double* m = maps + map_off[b];
     const bool equator = (h == 2 * ns);
@@ -621,7 +636,7 @@ __device__ __forceinline__ void ring_forward_item(const double* __restrict__ map
 template <int NT>
 __device__ __forceinline__ void ring_forward_list_item(const double* __restrict__ maps,
                                                        const GroupDesc* __restrict__ gd, const GroupRange& gr,
-                                                       char* ws, int reg, int id, C2<double>* buf) {
+                                                       char* ws, int reg, int id, C2<double>* buf, int order) {
     int gi, local;
     if (!locate_item(gr, id, gi, local)) return;
     const GroupDesc& G = gd[gi];
@@ -640,7 +655,7 @@ __device__ __forceinline__ void ring_forward_list_item(const double* __restrict_
     o.d1 = reinterpret_cast<double*>(ws + uniform(G.reg[reg][1]));
     o.d2 = reinterpret_cast<double*>(ws + uniform(G.reg[reg][2]));
     o.d3 = reinterpret_cast<double*>(ws + uniform(G.reg[reg][3]));
-    ring_forward_item<double, NT>(maps, uniform(G.map_off), uniform(G.rt), uniform(G.ft), o, local, buf);
+    ring_forward_item<double, NT>(maps, uniform(G.map_off), uniform(G.rt), uniform(G.ft), o, local, buf, order);
 }
 
 // S1 over the work list of every group of the launch (FP64 ring
@@ -651,10 +666,10 @@ __device__ __forceinline__ void ring_forward_list_item(const double* __restrict_
 template <int NT>
 __global__ __launch_bounds__(NT) void k_ring_forward(const double* __restrict__ maps,
                                                      const GroupDesc* __restrict__ gd, GroupRange gr, char* ws,
-                                                     int reg) {
+                                                     int reg, int order) {
     extern __shared__ unsigned char smem_raw[];
     C2<double>* buf = reinterpret_cast<C2<double>*>(smem_raw);
-    ring_forward_list_item<NT>(maps, gd, gr, ws, reg, blockIdx.x, buf);
+    ring_forward_list_item<NT>(maps, gd, gr, ws, reg, blockIdx.x, buf, order);
 }
 
 // ---------------------------------------------------------------------------
@@ -781,10 +796,11 @@ hipError_t launch_ring_forward(const double* maps, const GroupLaunch& gl, int re
     for (int i = 0; i < gl.n; ++i) fmax = std::max(fmax, gl.host[gl.first + i].ft.fft_max);
     const size_t shm = ring_lds_bytes(fmax, sizeof(C2<double>));
     const dim3 grid(list_grid(gl, r, false));
+    const int order = gl.variant >= 0 && gl.variant <= 2 ? gl.variant : 0;
     if (ring_threads(fmax) == 256)
-        hipLaunchKernelGGL(k_ring_forward<256>, grid, dim3(256), shm, s, maps, gl.dev, r, gl.ws, reg);
+        hipLaunchKernelGGL(k_ring_forward<256>, grid, dim3(256), shm, s, maps, gl.dev, r, gl.ws, reg, order);
     else
-        hipLaunchKernelGGL(k_ring_forward<512>, grid, dim3(512), shm, s, maps, gl.dev, r, gl.ws, reg);
+        hipLaunchKernelGGL(k_ring_forward<512>, grid, dim3(512), shm, s, maps, gl.dev, r, gl.ws, reg, order);
     return hipGetLastError();
 }
 

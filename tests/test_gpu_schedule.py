@@ -125,24 +125,26 @@ def test_work_lists_over_mixed_groups(mode):
     """Every stage runs as one work list over all nside groups.  The batch
     mixes per-order-table groups (>= 8 maps) and staged ones; the fold's
     persistent grids only change which workgroup takes which item (items keep
-    their XCD) and the pack's tile shapes only which workgroup moves which
-    a_lm, so every option gives the same a_lm bit for bit; and each map
+    their XCD), the pack's tile shapes only which workgroup moves which
+    a_lm and the ring orders only which workgroup transforms which ring pair,
+    so every option gives the same a_lm bit for bit; and each map
     agrees with its own single-map analysis (bitwise for the staged groups,
     whose single-map plans run the same strategy) and with the oracle."""
     nsides = [32] * 9 + [16, 8, 16] + [64] * 8 + [4]
     maps_np = [white_map(ns, 1900 + i) for i, ns in enumerate(nsides)]
     maps = torch.from_numpy(np.concatenate(maps_np)).cuda()
     plan = P.Plan(nsides, mode=mode)
-    assert plan.option("fold_grid") == 0 and plan.option("pack_maps") == 32
+    assert plan.option("fold_grid") == 0 and plan.option("pack_maps") == 32 and plan.option("ring_order") == 0
     ref = _run_clean(plan, maps, False)
     for name, value in [("fold_grid", 8), ("fold_grid", 64), ("fold_grid", 256), ("fold_grid", 2048),
-                        ("pack_maps", 16), ("pack_maps", 64), ("fold_grid", 0)]:
+                        ("pack_maps", 16), ("pack_maps", 64), ("fold_grid", 0), ("ring_order", 1),
+                        ("ring_order", 2)]:
         plan.set_option(name, value)
         assert plan.option(name) == value
         got = _run_clean(plan, maps, False)
         print(f"{mode} {name} {value}: equal={torch.equal(got, ref)}")
         assert torch.equal(got, ref), (name, value)
-    for name, value in [("fold_grid", 3), ("fold_grid", -8), ("pack_maps", 8), ("pack_maps", 48)]:
+    for name, value in [("fold_grid", 3), ("fold_grid", -8), ("pack_maps", 8), ("pack_maps", 48), ("ring_order", 3)]:
         with pytest.raises(P.HP2SPHError):
             plan.set_option(name, value)
     with pytest.raises(ValueError):
