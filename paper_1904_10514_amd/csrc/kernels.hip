@@ -1800,57 +1800,85 @@ hipError_t launch_pack(const GroupLaunch& gl, int reg_a, int reg_b, double* alm,
 
 // U (FP32) -> U (FP64) in the same layout, zero where l < m or l > lmax of
 // the column's map (what unpacking the packed a_lm would give).
+// Widen item: row lp of block blk, pairs q0 + 2 t, q0 + 2 t + 1 (t the
+// thread) of that row, each pair one FP32 (re, im) -> FP64 (re, im).
 template <class BA, class BU>
 __device__ __forceinline__ void widen_item(BA Ua, BU U, const int32_t* __restrict__ lmaxv, const GroupDims& g,
-                                           int live_only, int blk, int64_t e) {
+                                           int live_only, int blk, int lp, int q0) {
     const int kpar = blk >> 1;
-    const int64_t pairs = g.N[kpar] >> 1;
-    if (e >= int64_t(g.nl[blk]) * pairs) return;
-    const int lp = int(e / pairs);
-    const int64_t q = e % pairs;
-    int map, kk;
+    const int pairs = int(g.N[kpar] >> 1);
+    const int l = g.lmin[blk] + 2 * lp;
+    const int q = q0 + 2 * int(threadIdx.x);
+    if (q >= pairs) return;
+    const int64_t o = int64_t(lp) * g.N[kpar] + 2 * int64_t(q);
+    const float* src = Ua.p[blk] + o;
+    double* dst = U.p[blk] + o;
+    const int nmaps = g.nmaps, per = g.Npm[kpar] >> 1, nk = g.nk[blk];
+    // the two pairs' (map, k'): consecutive maps of one mode (mode-major) or
+    // consecutive modes of one map (map-major)
+    int map0, kk0;
     if (g.modemajor) {
-        kk = int(q / g.nmaps);
-        map = int(q % g.nmaps);
+        kk0 = q / nmaps;
+        map0 = q - kk0 * nmaps;
     } else {
-        const int per = g.Npm[kpar] >> 1;
-        map = int(q / per);
-        kk = int(q % per);
+        map0 = q / per;
+        kk0 = q - map0 * per;
     }
-    const int l = g.lmin[blk] + 2 * lp, m = 2 * kk + kpar;
-    if (live_only && l < m) return;   // rows below the order are never read
-    const int64_t o = int64_t(lp) * g.N[kpar] + 2 * q;
-    D2 v = {0.0, 0.0};
-    if (kk < g.nk[blk] && l >= m && l <= lmaxv[map]) v = {double(Ua.p[blk][o]), double(Ua.p[blk][o + 1])};
-    *reinterpret_cast<D2*>(U.p[blk] + o) = v;
+    const bool two = q + 1 < pairs;
+    // two 8-byte loads: a row of an odd-width block starts 8 bytes off a
+    // 16-byte boundary
+    const float2 v0 = *reinterpret_cast<const float2*>(src);
+    const float2 v1 = two ? *reinterpret_cast<const float2*>(src + 2) : make_float2(0.f, 0.f);
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        if (i == 1 && !two) break;
+        int map = map0, kk = kk0;
+        if (i == 1) {
+            if (g.modemajor) {
+                if (++map == nmaps) { map = 0; ++kk; }
+            } else {
+                if (++kk == per) { kk = 0; ++map; }
+            }
+        }
+        const int m = 2 * kk + kpar;
+        if (live_only && l < m) continue;   // rows below the order are never read
+        D2 w = {0.0, 0.0};
+        if (kk < nk && l >= m && l <= lmaxv[map])
+            w = i == 0 ? D2{double(v0.x), double(v0.y)} : D2{double(v1.x), double(v1.y)};
+        *reinterpret_cast<D2*>(dst + 2 * i) = w;
+    }
 }
 
-// Workgroups of one block of a group in the widen launch: enough for its
-// largest block.
-__host__ __device__ inline int64_t widen_block_wgs(const GroupDims& g) {
-    int64_t most = 0;
-    for (int b = 0; b < 4; ++b) {
-        const int64_t n = int64_t(g.nl[b]) * (g.N[b >> 1] >> 1);
-        most = most > n ? most : n;
-    }
-    return (most + 255) / 256;
+// Widen items of a group: 4 blocks x (largest block's rows) x (512-pair
+// chunks of the longest row), the ranges of a smaller block padded.
+__host__ __device__ inline int widen_chunks(const GroupDims& g) {
+    const int64_t most = g.N[0] > g.N[1] ? g.N[0] : g.N[1];
+    return int((most / 2 + 511) / 512);
+}
+__host__ __device__ inline int widen_rows(const GroupDims& g) {
+    int r = 0;
+    for (int b = 0; b < 4; ++b) r = r > g.nl[b] ? r : g.nl[b];
+    return r;
 }
 
-// Widen over the work list of every group (region Ua -> region U); item
-// (block, 256 consecutive entries) with the entries fastest.
+// Widen over the work list of every group (region Ua -> region U).
 __global__ __launch_bounds__(256) void k_widen(const GroupDesc* __restrict__ gd, GroupRange gr, char* ws) {
     int gi, local;
     if (!locate_item(gr, blockIdx.x, gi, local)) return;
     const GroupDesc& G = gd[gi];
-    const int64_t per = widen_block_wgs(G.g);
-    const int blk = int(local / per);
+    const int ch = widen_chunks(G.g), rows = widen_rows(G.g);
+    const int blk = local / (rows * ch);
+    const int rem = local - blk * rows * ch;
+    const int lp = rem / ch, c = rem - lp * ch;
+    if (lp >= G.g.nl[blk]) return;
     widen_item(region_blocks<const float>(ws, G, kRegUa), region_blocks<double>(ws, G, kRegU), G.lmax, G.g,
-               G.tables, blk, (local % per) * 256 + threadIdx.x);
+               G.tables, blk, lp, c * 512);
 }
 
 hipError_t launch_widen(const GroupLaunch& gl, hipStream_t s) {
     GroupRange r;
-    if (hipError_t e = make_range(gl, [](const GroupDesc& G) { return 4 * widen_block_wgs(G.g); }, r);
+    if (hipError_t e = make_range(
+            gl, [](const GroupDesc& G) { return int64_t(4) * widen_rows(G.g) * widen_chunks(G.g); }, r);
         e != hipSuccess)
         return e;
     if (r.start[r.n] == 0) return hipSuccess;
