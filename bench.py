@@ -27,7 +27,7 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-METRIC = "maps analysed/s at nside=1024, L=2048: batched FP32+refine vs plain FP64"
+METRIC = "maps analysed/s at nside={nside}, L={lmax}: batched FP32+refine vs plain FP64"
 
 # MI355X published peaks.  The VALU figure for FP32 (157.3) counts packed
 # FP32 instructions, which this build never emits (packed-fp32-ops is off):
@@ -578,7 +578,7 @@ def main():
         cpu = cpu_baseline(f0, nside, full=args.cpu_full)
 
     line = {
-        "metric": METRIC,
+        "metric": METRIC.format(nside=nside, lmax=lmax),
         "value": value,
         "unit": "maps/s",
         "n_gpus": 1,
