@@ -221,7 +221,7 @@ def make_inputs(torch, P, W, nside, nmaps):
     return maps
 
 
-P_OPTIONS = ("fold_grid", "pack_maps", "ring_order")
+P_OPTIONS = ("fold_grid", "pack_maps", "ring_order", "ring_threads")
 
 
 def autotune(plan, maps, out, enabled):

@@ -332,7 +332,9 @@ int hp2sph_schedules(hp2sph_plan_t plan, int32_t* out, int32_t cap, int32_t* cou
  * Launch options of the work-list stages.  The stages of an analysis run as
  * one launch over a work list that holds every nside group of the plan
  * (items grouped by nside, largest first).  Results are bitwise the same
- * under every value.  hp2sph_autotune chooses them after the GEMM schedules
+ * under every value of the first three; HP2SPH_OPT_RING_THREADS changes the
+ * FFT's pass structure, so its results agree to rounding (a few ulp of the
+ * ring coefficients), not bit for bit.  hp2sph_autotune chooses them after the GEMM schedules
  * and remembers its choices per plan shape.  Host state only, like
  * hp2sph_set_schedule.
  *   HP2SPH_OPT_FOLD_GRID  work grid of the refinement's residual fold (an
@@ -350,12 +352,19 @@ int hp2sph_schedules(hp2sph_plan_t plan, int32_t* out, int32_t cap, int32_t* cou
  *       on its XCD; 1 runs pairs in order, maps of a pair back to back; 2
  *       runs maps in order, all pairs of a map back to back.  The autotuner
  *       tries all three (not for HP2SPH_EQUAL_WEIGHT plans).
+ *   HP2SPH_OPT_RING_THREADS  workgroup size of the ring transform for the
+ *       groups up to nside 1024: 256 (default: up to 16 complex values per
+ *       thread, radix-16 passes) or 512 (up to 8 values per thread, radix-8
+ *       passes: one pass more, twice the waves per compute unit).  Groups
+ *       at nside 2048 always run 512 threads with 16 values each.  The
+ *       autotuner tries both (not for HP2SPH_EQUAL_WEIGHT plans).
  * Errors: ESTATE, EINVAL (unknown option, value out of range, null output).
  */
 enum {
     HP2SPH_OPT_FOLD_GRID = 0,
     HP2SPH_OPT_PACK_MAPS = 1,
-    HP2SPH_OPT_RING_ORDER = 2
+    HP2SPH_OPT_RING_ORDER = 2,
+    HP2SPH_OPT_RING_THREADS = 3
 };
 int hp2sph_set_option(hp2sph_plan_t plan, int32_t option, int32_t value);
 int hp2sph_get_option(hp2sph_plan_t plan, int32_t option, int32_t* value);

@@ -59,7 +59,7 @@ EXPORTED = [
 ]
 STRATEGIES = {"auto": 0, "staged": 1, "tables": 2}
 SCHEDULES = ["xcd_round_robin", "xcd_balanced", "linear", "linear_rows"]
-OPTIONS = ["fold_grid", "pack_maps", "ring_order"]
+OPTIONS = ["fold_grid", "pack_maps", "ring_order", "ring_threads"]
 MAX_TUNE_REPS = 100
 NSTAGES = 13
 STAGES = ["ring_forward", "pole", "gemm_analysis", "sweep_analysis", "pack", "unpack",
@@ -314,8 +314,9 @@ class Plan:
     def set_option(self, name, value):
         """Launch option of a work-list stage (one of OPTIONS): 'fold_grid'
         (0, or a persistent grid of that many workgroups), 'pack_maps' (maps
-        per pack tile: 16, 32 or 64) or 'ring_order' (item order of the ring
-        transform: 0, 1 or 2)."""
+        per pack tile: 16, 32 or 64), 'ring_order' (item order of the ring
+        transform: 0, 1 or 2) or 'ring_threads' (workgroup size of the ring
+        transform up to nside 1024: 256 or 512)."""
         if name not in OPTIONS:
             raise ValueError(f"option must be one of {OPTIONS}")
         _check(_lib.hp2sph_set_option(self._h, OPTIONS.index(name), int(value)), "set_option")

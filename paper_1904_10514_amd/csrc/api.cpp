@@ -211,6 +211,7 @@ struct hp2sph_plan_s {
     int fold_grid = 0;
     int pack_maps = 32;               // maps per pack tile (mode-major layout): 16, 32 or 64
     int ring_order = 0;               // item order of the ring transform: 0 (XCD-aware), 1, 2
+    int ring_threads = 256;           // threads of the ring transform up to nside 1024: 256 or 512
     // per-map offsets of the whole batch (C_l in one launch)
     int64_t* d_alm_off = nullptr;
     int64_t* d_cl_off = nullptr;
@@ -1090,6 +1091,7 @@ GroupLaunch all_groups(hp2sph_plan_t plan, void* ws, int grid_cap = 0) {
 GroupLaunch ring_launch(hp2sph_plan_t plan, int first, int n, void* ws) {
     GroupLaunch gl = span_launch(plan, first, n, ws);
     gl.variant = plan->ring_order;
+    gl.threads = plan->ring_threads;
     return gl;
 }
 // The pack launch over groups [first, first + n), with the plan's tile shape.
@@ -1420,6 +1422,7 @@ struct TuneChoice {
     int fold_grid = 0;
     int pack_maps = 32;
     int ring_order = 0;
+    int ring_threads = 256;
 };
 
 std::mutex g_tune_mu;
@@ -1440,7 +1443,10 @@ std::string tune_key(const hp2sph_plan_s* plan) {
     hipDeviceProp_t prop{};
     std::string arch = "unknown";
     if (hipGetDeviceProperties(&prop, plan->device) == hipSuccess) arch = prop.gcnArchName;
-    std::string k = arch + "/" + std::to_string(device_cus(plan->device)) + "/mode" + std::to_string(plan->mode);
+    // "v2": entries hold the fold grid, pack tile, ring order, ring threads,
+    // then the GEMM schedules
+    std::string k = "v2/" + arch + "/" + std::to_string(device_cus(plan->device)) + "/mode" +
+                    std::to_string(plan->mode);
     for (const auto& g : plan->groups)
         k += "/" + std::to_string(g->nside) + "x" + std::to_string(g->dims.nmaps) + (g->tables ? "t" : "s");
     return k;
@@ -1466,11 +1472,12 @@ void read_tune_file_locked() {
             v.push_back(x);
             q = end;
         }
-        if (v.size() < 3) continue;
+        if (v.size() < 4) continue;
         c.fold_grid = int(v[0]);
         c.pack_maps = int(v[1]);
         c.ring_order = int(v[2]);
-        for (size_t i = 3; i < v.size(); ++i) c.sched.push_back(int(v[i]));
+        c.ring_threads = int(v[3]);
+        for (size_t i = 4; i < v.size(); ++i) c.sched.push_back(int(v[i]));
         tune_cache()[l.substr(0, eq)] = c;
     }
     std::fclose(f);
@@ -1485,7 +1492,7 @@ void store_tune(const hp2sph_plan_s* plan, const TuneChoice& c) {
     if (!path || !*path) return;
     if (FILE* f = std::fopen(path, "a")) {
         std::string line = key + " = " + std::to_string(c.fold_grid) + " " + std::to_string(c.pack_maps) + " " +
-                           std::to_string(c.ring_order);
+                           std::to_string(c.ring_order) + " " + std::to_string(c.ring_threads);
         for (int x : c.sched) line += " " + std::to_string(x);
         line += "\n";
         std::fputs(line.c_str(), f);
@@ -1685,6 +1692,7 @@ int hp2sph_plan_create_ex(const int32_t* nside, const int32_t* lmax, int32_t bat
                     plan->fold_grid = c.fold_grid;
                     if (c.pack_maps == 16 || c.pack_maps == 32 || c.pack_maps == 64) plan->pack_maps = c.pack_maps;
                     if (c.ring_order >= 0 && c.ring_order <= 2) plan->ring_order = c.ring_order;
+                    if (c.ring_threads == 256 || c.ring_threads == 512) plan->ring_threads = c.ring_threads;
                 }
             }
         }
@@ -1860,6 +1868,10 @@ int hp2sph_set_option(hp2sph_plan_t plan, int32_t option, int32_t value) {
             if (value < 0 || value > 2) return fail(HP2SPH_EINVAL, "ring item order: 0, 1 or 2");
             plan->ring_order = value;
             return HP2SPH_OK;
+        case HP2SPH_OPT_RING_THREADS:
+            if (value != 256 && value != 512) return fail(HP2SPH_EINVAL, "ring transform threads: 256 or 512");
+            plan->ring_threads = value;
+            return HP2SPH_OK;
         default: return fail(HP2SPH_EINVAL, "unknown option");
     }
 }
@@ -1871,6 +1883,7 @@ int hp2sph_get_option(hp2sph_plan_t plan, int32_t option, int32_t* value) {
         case HP2SPH_OPT_FOLD_GRID: *value = plan->fold_grid; return HP2SPH_OK;
         case HP2SPH_OPT_PACK_MAPS: *value = plan->pack_maps; return HP2SPH_OK;
         case HP2SPH_OPT_RING_ORDER: *value = plan->ring_order; return HP2SPH_OK;
+        case HP2SPH_OPT_RING_THREADS: *value = plan->ring_threads; return HP2SPH_OK;
         default: return fail(HP2SPH_EINVAL, "unknown option");
     }
 }
@@ -1954,11 +1967,17 @@ int hp2sph_autotune(hp2sph_plan_t plan, const double* maps, double* alm, void* w
             plan->fold_grid = keep;
         }
     }
-    // tile shape of the pack (maps per tile), item order of the ring transform
-    for (int which = 0; which < 2; ++which) {
-        if (which == 1 && plan->mode == HP2SPH_EQUAL_WEIGHT) break;   // no forward ring transform there
-        int& opt = which == 0 ? plan->pack_maps : plan->ring_order;
-        const std::vector<int> cand = which == 0 ? std::vector<int>{32, 16, 64} : std::vector<int>{0, 1, 2};
+    // tile shape of the pack (maps per tile), item order and thread count of
+    // the ring transform (512 threads only changes groups up to nside 1024)
+    bool small_rings = false;
+    for (const auto& d : plan->gdesc) small_rings = small_rings || ring_threads(d.ft.fft_max) == 256;
+    for (int which = 0; which < 3; ++which) {
+        if (which >= 1 && plan->mode == HP2SPH_EQUAL_WEIGHT) break;   // no forward ring transform there
+        if (which == 2 && !small_rings) break;
+        int& opt = which == 0 ? plan->pack_maps : which == 1 ? plan->ring_order : plan->ring_threads;
+        const std::vector<int> cand = which == 0   ? std::vector<int>{32, 16, 64}
+                                      : which == 1 ? std::vector<int>{0, 1, 2}
+                                                   : std::vector<int>{256, 512};
         int keep = opt;
         for (int c : cand) {
             if (c == keep) continue;
@@ -1981,6 +2000,7 @@ int hp2sph_autotune(hp2sph_plan_t plan, const double* maps, double* alm, void* w
         c.fold_grid = plan->fold_grid;
         c.pack_maps = plan->pack_maps;
         c.ring_order = plan->ring_order;
+        c.ring_threads = plan->ring_threads;
         store_tune(plan, c);
     }
     // leave alm holding the analysis under the chosen schedules

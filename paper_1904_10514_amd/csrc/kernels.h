@@ -107,6 +107,7 @@ struct GroupLaunch {
     char* ws;
     int grid_cap;
     int variant;
+    int threads = 0;   // ring transform: 512 runs nside <= 1024 with 512 threads (8 values each)
 };
 
 // One product of a grouped GEMM: C[m][n] = sum_k A[k][m] B[k][n].

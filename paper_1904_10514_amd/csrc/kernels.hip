@@ -130,10 +130,11 @@ struct LdsLoad {
 // transforms of the same length side by side (every thread meets every
 // barrier).
 //
-// LDS addressing: Ns is 1 or a multiple of 16 (radix-16 passes first), and
-// an output run base + r Ns then sits at lpad(base) + r s with s = 1 (Ns = 1:
-// base is a multiple of R, which divides 16, so base + r never crosses a
-// pad) or s = 17 Ns / 16; likewise the inputs j + r G of an LDS pass sit at
+// LDS addressing: when Ns is 1 or a multiple of 16 (radix-16 passes, and
+// every radix-8 pass but the second), an output run base + r Ns sits at
+// lpad(base) + r s with s = 1 (Ns = 1: base is a multiple of R, which
+// divides 16, so base + r never crosses a pad) or s = 17 Ns / 16 (after a
+// first radix-8 pass, Ns = 8, each output takes its own slot); likewise the inputs j + r G of an LDS pass sit at
 // lpad(j) + r 17 G / 16 when G = M / R is a multiple of 16 (M >= 256).  The
 // slot of entry r is then one base address plus a stride, and with the
 // transform length a template argument (MS > 0; 0: known at run time) the
@@ -220,14 +221,20 @@ __device__ __forceinline__ void stockham_pass(C2<T>* buf, int M_rt, int lgNs, co
         }
     }
     __syncthreads();
+    const bool linear_out = Ns == 1 || (Ns & 15) == 0;
 #pragma unroll
     for (int i = 0; i < NG; ++i) {
         const int j = (threadIdx.x & (NT - 1)) + NT * i;
         if (j < G) {
             const int base = ((j >> lgNs) << lgNs) * R + (j & (Ns - 1));
-            C2<T>* dst = buf + lpad(base);
+            if (linear_out) {
+                C2<T>* dst = buf + lpad(base);
 #pragma unroll
-            for (int r = 0; r < R; ++r) dst[r * sout] = v[i * R + r];
+                for (int r = 0; r < R; ++r) dst[r * sout] = v[i * R + r];
+            } else {
+#pragma unroll
+                for (int r = 0; r < R; ++r) buf[lpad(base + r * Ns)] = v[i * R + r];
+            }
         }
     }
     __syncthreads();
@@ -237,7 +244,9 @@ template <class T, int NT, int MAXV, int MS, class Load>
 __device__ __forceinline__ void stockham_dispatch(int bits, C2<T>* buf, int M, int lgNs, const T* tw, int fft_max,
                                                   Load load) {
     switch (bits) {
-        case 4: stockham_pass<T, 16, NT, MAXV, MS>(buf, M, lgNs, tw, fft_max, load); break;
+        case 4:
+            if constexpr (MAXV >= 16) stockham_pass<T, 16, NT, MAXV, MS>(buf, M, lgNs, tw, fft_max, load);
+            break;
         case 3: stockham_pass<T, 8, NT, MAXV, MS>(buf, M, lgNs, tw, fft_max, load); break;
         case 2: stockham_pass<T, 4, NT, MAXV, MS>(buf, M, lgNs, tw, fft_max, load); break;
         default: stockham_pass<T, 2, NT, MAXV, MS>(buf, M, lgNs, tw, fft_max, load); break;
@@ -248,48 +257,55 @@ __device__ __forceinline__ void stockham_dispatch(int bits, C2<T>* buf, int M, i
 // template argument (MS > 0) or known at run time (MS = 0):
 // X_s = sum_q x_q e^{-2 pi i q s / M}.  The first pass takes its input from
 // `load0(q)` (which may read the buffer); on return the buffer holds X in
-// natural order at slots lpad(s).  Radix-16 passes, the remainder last.
+// natural order at slots lpad(s).  Passes of radix 16 (8 when a thread holds
+// MAXV = 8 values), the remainder last.
 // Table tw: e^{-2 pi i t / fft_max}, t < fft_max, M divides fft_max.
 constexpr int static_log2(int v) { return v <= 1 ? 0 : 1 + static_log2(v >> 1); }
-// Radix of pass p of a transform of 2^E points: 16, the remainder last.
-constexpr int pass_radix(int E, int p) {
-    return p < (E + 3) / 4 - 1 ? 16 : (1 << (E - 4 * ((E + 3) / 4 - 1)));
+// log2 of the radix of the full passes with MAXV values per thread.
+constexpr int radix_bits(int maxv) { return maxv >= 16 ? 4 : 3; }
+// Radix of pass p of a transform of 2^E points: 2^RB, the remainder last.
+constexpr int pass_radix(int E, int p, int RB) {
+    return p < (E + RB - 1) / RB - 1 ? (1 << RB) : (1 << (E - RB * ((E + RB - 1) / RB - 1)));
 }
 
 template <class T, int NT, int MAXV, int MS, class Load0>
 __device__ __forceinline__ void fft_lds_n(C2<T>* buf, int M_rt, const T* tw, int fft_max, Load0 load0) {
     const LdsLoad<T> lds_load{buf};
+    constexpr int RB = radix_bits(MAXV);
     if constexpr (MS > 0) {
         // compile-time pass sequence; each pass prefetches the twiddles of
-        // the next one (passes of radix 16, and a last pass of radix 8)
-        constexpr int E = static_log2(MS), P = (E + 3) / 4;
+        // the next one (full passes, and a last pass of radix 8 or less)
+        constexpr int E = static_log2(MS), P = (E + RB - 1) / RB;
         static_assert(P <= 4, "at most four passes");
-        constexpr int R0 = pass_radix(E, 0), R1 = pass_radix(E, 1), R2 = pass_radix(E, 2), R3 = pass_radix(E, 3);
+        constexpr int R0 = pass_radix(E, 0, RB), R1 = pass_radix(E, 1, RB), R2 = pass_radix(E, 2, RB),
+                      R3 = pass_radix(E, 3, RB);
         constexpr bool pre1 = P > 1 && R1 >= 8, pre2 = P > 2 && R2 >= 8, pre3 = P > 3 && R3 >= 8;
         PassTw<T, R1, MAXV> t1;
-        if constexpr (pre1) load_pass_tw<T, R1, NT, MAXV>(t1, tw, fft_max, 4, MS / R1);
+        if constexpr (pre1) load_pass_tw<T, R1, NT, MAXV>(t1, tw, fft_max, RB, MS / R1);
         stockham_pass<T, R0, NT, MAXV, MS>(buf, MS, 0, tw, fft_max, load0);
         if constexpr (P > 1) {
             PassTw<T, R2, MAXV> t2;
-            if constexpr (pre2) load_pass_tw<T, R2, NT, MAXV>(t2, tw, fft_max, 8, MS / R2);
-            stockham_pass<T, R1, NT, MAXV, MS, pre1>(buf, MS, 4, tw, fft_max, lds_load, t1);
+            if constexpr (pre2) load_pass_tw<T, R2, NT, MAXV>(t2, tw, fft_max, 2 * RB, MS / R2);
+            stockham_pass<T, R1, NT, MAXV, MS, pre1>(buf, MS, RB, tw, fft_max, lds_load, t1);
             if constexpr (P > 2) {
                 PassTw<T, R3, MAXV> t3;
-                if constexpr (pre3) load_pass_tw<T, R3, NT, MAXV>(t3, tw, fft_max, 12, MS / R3);
-                stockham_pass<T, R2, NT, MAXV, MS, pre2>(buf, MS, 8, tw, fft_max, lds_load, t2);
-                if constexpr (P > 3) stockham_pass<T, R3, NT, MAXV, MS, pre3>(buf, MS, 12, tw, fft_max, lds_load, t3);
+                if constexpr (pre3) load_pass_tw<T, R3, NT, MAXV>(t3, tw, fft_max, 3 * RB, MS / R3);
+                stockham_pass<T, R2, NT, MAXV, MS, pre2>(buf, MS, 2 * RB, tw, fft_max, lds_load, t2);
+                if constexpr (P > 3)
+                    stockham_pass<T, R3, NT, MAXV, MS, pre3>(buf, MS, 3 * RB, tw, fft_max, lds_load, t3);
             }
         }
     } else {
         const int M = M_rt;
         const int e = ilog2(M);
-        const int P = (e + 3) >> 2;
-        const int last = e - 4 * (P - 1);
-        // straight-line pass sequence (at most 4 passes for M <= 2^16)
-        stockham_dispatch<T, NT, MAXV, MS>(P == 1 ? last : 4, buf, M, 0, tw, fft_max, load0);
-        if (P > 1) stockham_dispatch<T, NT, MAXV, MS>(P == 2 ? last : 4, buf, M, 4, tw, fft_max, lds_load);
-        if (P > 2) stockham_dispatch<T, NT, MAXV, MS>(P == 3 ? last : 4, buf, M, 8, tw, fft_max, lds_load);
-        if (P > 3) stockham_dispatch<T, NT, MAXV, MS>(last, buf, M, 12, tw, fft_max, lds_load);
+        const int P = (e + RB - 1) / RB;
+        const int last = e - RB * (P - 1);
+        // straight-line pass sequence (at most 4 passes: M <= 2^16, or 2^12
+        // with radix-8 passes)
+        stockham_dispatch<T, NT, MAXV, MS>(P == 1 ? last : RB, buf, M, 0, tw, fft_max, load0);
+        if (P > 1) stockham_dispatch<T, NT, MAXV, MS>(P == 2 ? last : RB, buf, M, RB, tw, fft_max, lds_load);
+        if (P > 2) stockham_dispatch<T, NT, MAXV, MS>(P == 3 ? last : RB, buf, M, 2 * RB, tw, fft_max, lds_load);
+        if (P > 3) stockham_dispatch<T, NT, MAXV, MS>(last, buf, M, 3 * RB, tw, fft_max, lds_load);
     }
 }
 
@@ -482,9 +498,14 @@ static unsigned list_grid(const GroupLaunch& gl, const GroupRange& r, bool persi
 
 // Ring kernels run NT = fft_max / 16 threads (256 up to nside 1024, 512 at
 // nside 2048), so that every FFT of up to fft_max points keeps at most 16
-// complex values per thread.
+// complex values per thread.  The forward transform can also run 512
+// threads up to nside 1024 with at most MAXV = 8 values per thread (radix-8
+// passes: one more pass, half the registers per thread, twice the waves).
 constexpr int kRingMaxV = 16;
-constexpr int kRingKPT = 9;   // ceil((2 nside + 1) / NT) at the largest nside of each NT
+// Output modes k <= p per thread: ceil((2 nside + 1) / NT) with
+// NT MAXV = 4 nside at the largest nside of each kernel.
+constexpr int ring_kpt(int maxv) { return maxv / 2 + 1; }
+constexpr int kRingKPT = ring_kpt(kRingMaxV);
 
 
 // D_k, k <= p, of one ring from the half-length DFT R of its points (Step 1):
@@ -515,9 +536,9 @@ __device__ __forceinline__ C2<T> ring_coeff(const DftOut<T>& R, int k, int n, bo
     return d;
 }
 
-template <class T, int NT>
+template <class T, int NT, int MAXV>
 __device__ __forceinline__ void ring_spectrum(const double* x, int n, bool shifted, int p, FftTab<T> ft, C2<T>* buf,
-                              C2<T> (&D)[kRingKPT]) {
+                              C2<T> (&D)[ring_kpt(MAXV)]) {
     const int L = n >> 1, j = n >> 2;
     const int Mb = ft.chirpm[j];
     const T* chirp = ft.chirp + 2 * ft.chirpoff[j];
@@ -528,9 +549,9 @@ __device__ __forceinline__ void ring_spectrum(const double* x, int n, bool shift
         const D2 v = *reinterpret_cast<const D2*>(x + 2 * q);
         return {T(v.x), T(v.y)};
     };
-    const DftOut<T> R = ring_dft<T, NT, kRingMaxV>(buf, L, Mb, chirp, chirpfft, ft.twiddle, ft.fft_max, src);
+    const DftOut<T> R = ring_dft<T, NT, MAXV>(buf, L, Mb, chirp, chirpfft, ft.twiddle, ft.fft_max, src);
 #pragma unroll
-    for (int i = 0; i < kRingKPT; ++i) D[i] = ring_coeff(R, threadIdx.x + i * NT, n, shifted, p, roots);
+    for (int i = 0; i < ring_kpt(MAXV); ++i) D[i] = ring_coeff(R, threadIdx.x + i * NT, n, shifted, p, roots);
     // The next transform's first pass synchronises before it writes the buffer.
 }
 
@@ -544,7 +565,7 @@ __host__ __device__ constexpr int ring_buffer_slots(int fft_max) {
 }
 
 // Work item `id` of one group: ring pair h of map b (ring_block_id).
-template <class T, int NT>
+template <class T, int NT, int MAXV>
 __device__ __forceinline__ void ring_forward_item(const double* __restrict__ maps,
                                                   const int64_t* __restrict__ map_off, const RingTab rt,
                                                   const FftTab<T> ft, const RingOut<T> o, int id, C2<T>* buf,
@@ -592,14 +613,14 @@ __device__ __forceinline__ void ring_forward_item(const double* __restrict__ map
                 return {T(v.x), T(v.y)};
             };
             const int hs = ring_half_slots(ft.fft_max);
-            DftOut<T> R = ring_dft<T, NH, kRingMaxV>(buf + half * hs, L, ft.chirpm[j], chirp, chirpfft, ft.twiddle,
-                                                     ft.fft_max, src);
+            DftOut<T> R = ring_dft<T, NH, MAXV>(buf + half * hs, L, ft.chirpm[j], chirp, chirpfft, ft.twiddle,
+                                                ft.fft_max, src);
             __syncthreads();   // both spectra are in LDS
             DftOut<T> RN = R, RS = R;
             RN.buf = buf;
             RS.buf = buf + hs;
 #pragma unroll
-            for (int i = 0; i < kRingKPT; ++i) {
+            for (int i = 0; i < ring_kpt(MAXV); ++i) {
                 const int k = threadIdx.x + i * NT;
                 if (k > p) continue;
                 const C2<T> dn = ring_coeff(RN, k, n, shifted, p, roots);
@@ -609,17 +630,17 @@ __device__ __forceinline__ void ring_forward_item(const double* __restrict__ map
             return;
         }
     }
-    C2<T> DN[kRingKPT], DS[kRingKPT];
+    C2<T> DN[ring_kpt(MAXV)], DS[ring_kpt(MAXV)];
     {
         const int r0 = h - 1;
-        ring_spectrum<T, NT>(m + rt.start[r0], rt.n[r0], rt.shifted[r0] != 0, p, ft, buf, DN);
+        ring_spectrum<T, NT, MAXV>(m + rt.start[r0], rt.n[r0], rt.shifted[r0] != 0, p, ft, buf, DN);
     }
     if (!equator) {
         const int r0 = 4 * ns - h - 1;
-        ring_spectrum<T, NT>(m + rt.start[r0], rt.n[r0], rt.shifted[r0] != 0, p, ft, buf, DS);
+        ring_spectrum<T, NT, MAXV>(m + rt.start[r0], rt.n[r0], rt.shifted[r0] != 0, p, ft, buf, DS);
     }
 #pragma unroll
-    for (int i = 0; i < kRingKPT; ++i) {
+    for (int i = 0; i < ring_kpt(MAXV); ++i) {
         const int k = threadIdx.x + i * NT;
         if (k > p) continue;
         if (equator) store(k, DN[i], C2<T>{T(0), T(0)});
@@ -633,7 +654,7 @@ __device__ __forceinline__ void ring_forward_item(const double* __restrict__ map
 // the next item's first LDS writes behind this item's last LDS reads.  The
 // loop costs registers (256 VGPRs against 192, one wave per SIMD instead of
 // two), so the persistent form is a candidate the autotuner measures.
-template <int NT>
+template <int NT, int MAXV>
 __device__ __forceinline__ void ring_forward_list_item(const double* __restrict__ maps,
                                                        const GroupDesc* __restrict__ gd, const GroupRange& gr,
                                                        char* ws, int reg, int id, C2<double>* buf, int order) {
@@ -655,7 +676,7 @@ __device__ __forceinline__ void ring_forward_list_item(const double* __restrict_
     o.d1 = reinterpret_cast<double*>(ws + uniform(G.reg[reg][1]));
     o.d2 = reinterpret_cast<double*>(ws + uniform(G.reg[reg][2]));
     o.d3 = reinterpret_cast<double*>(ws + uniform(G.reg[reg][3]));
-    ring_forward_item<double, NT>(maps, uniform(G.map_off), uniform(G.rt), uniform(G.ft), o, local, buf, order);
+    ring_forward_item<double, NT, MAXV>(maps, uniform(G.map_off), uniform(G.rt), uniform(G.ft), o, local, buf, order);
 }
 
 // S1 over the work list of every group of the launch (FP64 ring
@@ -663,13 +684,13 @@ __device__ __forceinline__ void ring_forward_list_item(const double* __restrict_
 // form that walks the list does not fit: its loop keeps more values live
 // than the 256 VGPRs of a wave and spills to scratch memory, against 188
 // VGPRs and no scratch for one item per workgroup.)
-template <int NT>
+template <int NT, int MAXV>
 __global__ __launch_bounds__(NT) void k_ring_forward(const double* __restrict__ maps,
                                                      const GroupDesc* __restrict__ gd, GroupRange gr, char* ws,
                                                      int reg, int order) {
     extern __shared__ unsigned char smem_raw[];
     C2<double>* buf = reinterpret_cast<C2<double>*>(smem_raw);
-    ring_forward_list_item<NT>(maps, gd, gr, ws, reg, blockIdx.x, buf, order);
+    ring_forward_list_item<NT, MAXV>(maps, gd, gr, ws, reg, blockIdx.x, buf, order);
 }
 
 // ---------------------------------------------------------------------------
@@ -797,10 +818,12 @@ hipError_t launch_ring_forward(const double* maps, const GroupLaunch& gl, int re
     const size_t shm = ring_lds_bytes(fmax, sizeof(C2<double>));
     const dim3 grid(list_grid(gl, r, false));
     const int order = gl.variant >= 0 && gl.variant <= 2 ? gl.variant : 0;
-    if (ring_threads(fmax) == 256)
-        hipLaunchKernelGGL(k_ring_forward<256>, grid, dim3(256), shm, s, maps, gl.dev, r, gl.ws, reg, order);
+    if (ring_threads(fmax) == 512)
+        hipLaunchKernelGGL((k_ring_forward<512, 16>), grid, dim3(512), shm, s, maps, gl.dev, r, gl.ws, reg, order);
+    else if (gl.threads == 512)
+        hipLaunchKernelGGL((k_ring_forward<512, 8>), grid, dim3(512), shm, s, maps, gl.dev, r, gl.ws, reg, order);
     else
-        hipLaunchKernelGGL(k_ring_forward<512>, grid, dim3(512), shm, s, maps, gl.dev, r, gl.ws, reg, order);
+        hipLaunchKernelGGL((k_ring_forward<256, 16>), grid, dim3(256), shm, s, maps, gl.dev, r, gl.ws, reg, order);
     return hipGetLastError();
 }
 
@@ -2507,8 +2530,9 @@ void* scratch_ptr(int device) {
 hipError_t configure_kernels() {
     const int bytes = 160 * 1024;
     const void* fns[] = {
-        reinterpret_cast<const void*>(&k_ring_forward<256>),
-        reinterpret_cast<const void*>(&k_ring_forward<512>),
+        reinterpret_cast<const void*>(&k_ring_forward<256, 16>),
+        reinterpret_cast<const void*>(&k_ring_forward<512, 16>),
+        reinterpret_cast<const void*>(&k_ring_forward<512, 8>),
         reinterpret_cast<const void*>(&k_ring_inverse<256>),
         reinterpret_cast<const void*>(&k_ring_inverse<512>),
         reinterpret_cast<const void*>(&k_ring_adjoint<256>),

@@ -84,6 +84,23 @@ def test_fullsize_f64_sampled_orders(noise_batch):
     plan.close()
 
 
+def test_fullsize_f64_ring_threads_512(noise_batch):
+    """The ring transform with 512 threads (radix-8 passes, the compiled
+    2048- and 4096-point sequences of the equatorial rings and the largest
+    Bluestein transforms) against the oracle on the sampled orders, and
+    against the 256-thread transform on every coefficient (rounding only)."""
+    maps, dev = noise_batch
+    plan = P.Plan(NSIDE, LMAX, batch=BATCH, mode="f64")
+    plan.set_option("ring_threads", 512)
+    a512 = _sampled_check(plan, maps, dev, SAMPLE_ORDERS, TOL64, "f64 nside 1024 x 64, 512 ring threads")
+    plan.set_option("ring_threads", 256)
+    a256 = plan.analyze(dev).cpu().numpy().reshape(BATCH, -1)
+    plan.close()
+    d = rel_err(a512, a256)
+    print(f"512 vs 256 ring threads: rel diff {d:.3e}")
+    assert d < 1e-13
+
+
 def test_fullsize_f32_single_pass_sampled_orders(noise_batch):
     maps, dev = noise_batch
     plan = P.Plan(NSIDE, LMAX, batch=BATCH, mode="f32")

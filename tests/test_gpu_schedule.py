@@ -127,7 +127,8 @@ def test_work_lists_over_mixed_groups(mode):
     persistent grids only change which workgroup takes which item (items keep
     their XCD), the pack's tile shapes only which workgroup moves which
     a_lm and the ring orders only which workgroup transforms which ring pair,
-    so every option gives the same a_lm bit for bit; and each map
+    so every option gives the same a_lm bit for bit; 512 ring-transform
+    threads (radix-8 passes) change the FFT's rounding only; and each map
     agrees with its own single-map analysis (bitwise for the staged groups,
     whose single-map plans run the same strategy) and with the oracle."""
     nsides = [32] * 9 + [16, 8, 16] + [64] * 8 + [4]
@@ -135,6 +136,7 @@ def test_work_lists_over_mixed_groups(mode):
     maps = torch.from_numpy(np.concatenate(maps_np)).cuda()
     plan = P.Plan(nsides, mode=mode)
     assert plan.option("fold_grid") == 0 and plan.option("pack_maps") == 32 and plan.option("ring_order") == 0
+    assert plan.option("ring_threads") == 256
     ref = _run_clean(plan, maps, False)
     for name, value in [("fold_grid", 8), ("fold_grid", 64), ("fold_grid", 256), ("fold_grid", 2048),
                         ("pack_maps", 16), ("pack_maps", 64), ("fold_grid", 0), ("ring_order", 1),
@@ -144,7 +146,15 @@ def test_work_lists_over_mixed_groups(mode):
         got = _run_clean(plan, maps, False)
         print(f"{mode} {name} {value}: equal={torch.equal(got, ref)}")
         assert torch.equal(got, ref), (name, value)
-    for name, value in [("fold_grid", 3), ("fold_grid", -8), ("pack_maps", 8), ("pack_maps", 48), ("ring_order", 3)]:
+    plan.set_option("ring_threads", 512)
+    got = _run_clean(plan, maps, False)
+    diff = rel_err(got.numpy(), ref.numpy())
+    print(f"{mode} ring_threads 512: rel diff {diff:.3e}")
+    assert diff < (1e-13 if mode == "f64" else 1e-6)
+    plan.set_option("ring_threads", 256)
+    assert torch.equal(_run_clean(plan, maps, False), ref)
+    for name, value in [("fold_grid", 3), ("fold_grid", -8), ("pack_maps", 8), ("pack_maps", 48), ("ring_order", 3),
+                        ("ring_threads", 128), ("ring_threads", 1024)]:
         with pytest.raises(P.HP2SPHError):
             plan.set_option(name, value)
     with pytest.raises(ValueError):
