@@ -1364,15 +1364,38 @@ __device__ __forceinline__ ConstPtr<T> as_const(const T* p) {
     return (ConstPtr<T>)(p);
 }
 
+// The SW angle pairs of sweeps tb .. tb+SW-1 at one position, loaded
+// together (one batch of scalar loads and one wait, instead of a load and a
+// wait in front of every rotation).  The row of the table holds tpad >= the
+// next multiple of SW above the last sweep of any busy wave, so the whole
+// block is in bounds even where its last sweeps are past the group's.
+template <class T>
+struct Angles {
+    T c[SW], s[SW];
+};
+
+template <class T>
+__device__ __forceinline__ Angles<T> load_angles(ConstPtr<T> cs) {
+    Angles<T> a;
+#pragma unroll
+    for (int j = 0; j < SW; ++j) {
+        a.c[j] = cs[2 * j];
+        a.s[j] = cs[2 * j + 1];
+    }
+    return a;
+}
+
 // forward sweeps tb .. tb+SW-1 of one wave at position lp, for MB maps.
 // Sweep t rotates at positions lp >= t and takes its carry at lp = t - 1, so
 // at a given lp the wave applies the first nrot sweeps and then (if it is
 // one of its own) starts the carry of sweep lp + 1.
-template <class T, int MB, bool MASK>
-__device__ __forceinline__ void fwd_position(T (&v)[MB], int lp, int tb, int tg, int kk, T (&carry)[SW][MB],
-                                             ConstPtr<T> cs) {
-    const int nrot = max(0, min(min(lp - tb + 1, tg - tb + 1), SW));   // wave-uniform
-    const int jinit = (lp - tb + 1 < SW && lp + 1 <= tg) ? lp - tb + 1 : -1;
+// ALL: every sweep of the block rotates here and none starts (the interior
+// of the chain), with no per-sweep branch.
+template <class T, int MB, bool MASK, bool ALL>
+__device__ __forceinline__ void fwd_rot(T (&v)[MB], int lp, int tb, int tg, int kk, T (&carry)[SW][MB],
+                                        const Angles<T>& an) {
+    const int nrot = ALL ? SW : max(0, min(min(lp - tb + 1, tg - tb + 1), SW));   // wave-uniform
+    const int jinit = ALL ? -1 : (lp - tb + 1 < SW && lp + 1 <= tg) ? lp - tb + 1 : -1;
     T vf[MB];
 #pragma unroll
     for (int b = 0; b < MB; ++b) vf[b] = v[b];
@@ -1380,7 +1403,7 @@ __device__ __forceinline__ void fwd_position(T (&v)[MB], int lp, int tb, int tg,
     for (int j = 0; j < SW; ++j) {
         if (j < nrot) {
             const int t = tb + j;
-            const T c = cs[2 * j], s = cs[2 * j + 1];
+            const T c = an.c[j], s = an.s[j];
 #pragma unroll
             for (int b = 0; b < MB; ++b) {
                 // explicit fma order: every instantiation rounds identically
@@ -1402,18 +1425,25 @@ __device__ __forceinline__ void fwd_position(T (&v)[MB], int lp, int tb, int tg,
     for (int b = 0; b < MB; ++b) v[b] = vf[b];
 }
 
-// backward (synthesis) sweeps tb+SW-1 down to tb at position lp, for MB maps
 template <class T, int MB, bool MASK>
-__device__ __forceinline__ void bwd_position(T (&v)[MB], int lp, int tb, int tg, int kk, T (&carry)[SW][MB],
-                                             ConstPtr<T> cs) {
+__device__ __forceinline__ void fwd_position(T (&v)[MB], int lp, int tb, int tg, int kk, T (&carry)[SW][MB],
+                                             const Angles<T>& an) {
+    if (lp - tb + 1 >= SW && tg - tb + 1 >= SW) fwd_rot<T, MB, MASK, true>(v, lp, tb, tg, kk, carry, an);
+    else fwd_rot<T, MB, MASK, false>(v, lp, tb, tg, kk, carry, an);
+}
+
+// backward (synthesis) sweeps tb+SW-1 down to tb at position lp, for MB maps
+template <class T, int MB, bool MASK, bool ALL>
+__device__ __forceinline__ void bwd_rot(T (&v)[MB], int lp, int tb, int tg, int kk, T (&carry)[SW][MB],
+                                        const Angles<T>& an) {
 #pragma unroll
     for (int jj = 0; jj < SW; ++jj) {
         const int j = SW - 1 - jj;
         const int t = tb + j;
-        if (t > tg) continue;
+        if (!ALL && t > tg) continue;
         const bool act = MASK ? (t <= kk) : true;
-        if (lp >= t) {
-            const T c = cs[2 * j], s = cs[2 * j + 1];
+        if (ALL || lp >= t) {
+            const T c = an.c[j], s = an.s[j];
 #pragma unroll
             for (int b = 0; b < MB; ++b) {
                 const T nv = fma(s, v[b], c * carry[j][b]);
@@ -1430,6 +1460,13 @@ __device__ __forceinline__ void bwd_position(T (&v)[MB], int lp, int tb, int tg,
             }
         }
     }
+}
+
+template <class T, int MB, bool MASK>
+__device__ __forceinline__ void bwd_position(T (&v)[MB], int lp, int tb, int tg, int kk, T (&carry)[SW][MB],
+                                             const Angles<T>& an) {
+    if (tb + SW - 1 <= tg && lp >= tb + SW - 1) bwd_rot<T, MB, MASK, true>(v, lp, tb, tg, kk, carry, an);
+    else bwd_rot<T, MB, MASK, false>(v, lp, tb, tg, kk, carry, an);
 }
 
 template <class T, int MB, bool FWD>
@@ -1521,13 +1558,13 @@ __global__ __launch_bounds__(64 * SW_WAVES) void k_sweep(Blocks4<T> U, Blocks4<c
                     const int lp = posof(c, i);
                     const bool in = FWD ? (lp < nl) : (lp >= lo);
                     if (busy && in) {
-                        ConstPtr<T> cs = as_const(Gt + (int64_t(lp) * tpad + (tb - 1)) * 2);
+                        const Angles<T> an = load_angles<T>(as_const(Gt + (int64_t(lp) * tpad + (tb - 1)) * 2));
                         if (FWD) {
-                            if (mask) fwd_position<T, MB, true>(v[i], lp, tb, tg, kk, carry, cs);
-                            else fwd_position<T, MB, false>(v[i], lp, tb, tg, kk, carry, cs);
+                            if (mask) fwd_position<T, MB, true>(v[i], lp, tb, tg, kk, carry, an);
+                            else fwd_position<T, MB, false>(v[i], lp, tb, tg, kk, carry, an);
                         } else {
-                            if (mask) bwd_position<T, MB, true>(v[i], lp, tb, tg, kk, carry, cs);
-                            else bwd_position<T, MB, false>(v[i], lp, tb, tg, kk, carry, cs);
+                            if (mask) bwd_position<T, MB, true>(v[i], lp, tb, tg, kk, carry, an);
+                            else bwd_position<T, MB, false>(v[i], lp, tb, tg, kk, carry, an);
                         }
                     }
                     if (wave == SW_WAVES - 1) {
