@@ -1317,15 +1317,17 @@ hipError_t launch_transpose_orders(const double* syn, const int64_t* soff, doubl
 // in chunks of SW_CHUNK positions: wave 0 reads from global memory (one
 // chunk ahead), hands each chunk to wave 1 through LDS, .., the last wave
 // writes back; at step s wave w works on chunk s - w, with a barrier per
-// step.  The carries of a wave's sweeps stay in registers for the pass; the
-// angles come through the scalar cache.  Columns that need fewer sweeps than
+// step (four positions per chunk: a quarter of a barrier per position, at
+// 128 VGPRs for two maps per lane).  The carries of a wave's sweeps stay in
+// registers for the pass; the angles come through the scalar cache, the SW
+// pairs of a position in one batch.  Columns that need fewer sweeps than
 // their neighbours are masked per lane only in the wave blocks that contain
 // their last sweep.
 // ---------------------------------------------------------------------------
 
 constexpr int SW = 8;
 constexpr int SW_WAVES = 8;
-constexpr int SW_CHUNK = 2;
+constexpr int SW_CHUNK = 4;
 constexpr int kSweepCols = 32;
 
 __device__ __forceinline__ void sweep_locate(const GroupDims& g, int nmg, int& blk, int& grp, int& mg) {
