@@ -291,3 +291,30 @@ def test_batch_widths_match_single_maps_bitwise(mode):
         plan.close()
         for v in range(batch):
             assert np.array_equal(a[v * sz:(v + 1) * sz], singles[v]), (batch, v)
+
+
+@pytest.mark.parametrize("mode", ["f64", "f32_refine"])
+def test_staged_sweep_map_groups_match_single_maps_bitwise(mode):
+    """Staged plans of 1, 2, 3, 5 and 7 maps: the Givens sweeps carry one
+    map per lane for a single map and two otherwise (a partial last map
+    group for odd batches), and
+    each map's rotations keep their own fma order, so every map of a batch
+    equals its single-map analysis bit for bit; the single maps agree with
+    the oracle."""
+    nside = 16
+    route = O.analyze if mode == "f64" else O.analyze_refined
+    maps = [white_map(nside, 1600 + v) for v in range(7)]
+    singles = []
+    for v in range(7):
+        plan = P.Plan(nside, batch=1, mode=mode, strategy="staged")
+        singles.append(plan.analyze(_dev(maps[v])).cpu().numpy())
+        plan.close()
+    for v in (0, 6):
+        assert rel_err(singles[v], route(maps[v], nside)) < (TOL64 if mode == "f64" else TOL_REFINE)
+    sz = O.alm_size(2 * nside)
+    for batch in (2, 3, 5, 7):
+        plan = P.Plan(nside, batch=batch, mode=mode, strategy="staged")
+        a = plan.analyze(_dev(np.concatenate(maps[:batch]))).cpu().numpy()
+        plan.close()
+        for v in range(batch):
+            assert np.array_equal(a[v * sz:(v + 1) * sz], singles[v]), (batch, v)
