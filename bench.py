@@ -161,6 +161,26 @@ def roofline(stage, mode, nside, nmaps, ms_total, launches, strategy="staged"):
             "work_per_launch": amount, "work_unit": kind}
 
 
+def uneven_roofline(stage, mode, counts, ms_total, launches, strategy):
+    """roofline() of a stage launched once over several nside groups
+    (counts: nside -> maps): the algorithmic work of a launch is the sum over
+    the groups.  No counter summary covers these launches (traffic null)."""
+    dt = stage_dtype(stage, mode)
+    kind, amount = "byte", 0
+    for ns, nm in counts.items():
+        kind, a = stage_work(stage, ns, nm, 4 if dt == "f32" else 8, strategy, mode)
+        amount += a
+    avg_s = ms_total / launches / 1e3
+    bound = stage_bound(stage)
+    if bound == "hbm":
+        achieved, peak, unit = amount / avg_s / 1e9, PEAK_HBM_GBS, "GB/s"
+    else:
+        achieved, peak, unit = amount / avg_s / 1e12, PEAK_TFLOPS[bound][dt], "TFLOP/s"
+    return {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit, "frac": achieved / peak,
+            "traffic": None, "kernel": stage, "dtype": dt, "strategy": strategy, "avg_launch_ms": avg_s * 1e3,
+            "launches": launches, "work_per_launch": amount, "work_unit": kind}
+
+
 def measured_traffic(stage, dtype, nside, nmaps, strategy):
     """HBM bytes per launch from the committed counter runs (profiles/), scaled
     by the copy-kernel calibration; None if the kernels changed since then or
@@ -346,6 +366,7 @@ def uneven_main(args):
     import paper_1904_10514_amd as P
     nsides = [int(v) for v in W.uneven_nsides(256, 3)]
     lmaxs = [2 * v for v in nsides]
+    counts = {int(n): nsides.count(n) for n in sorted(set(nsides))}
     alm = np.concatenate([W.draw_alm(W.spectrum(3, L), L, W.rng_for(3, i)) for i, L in enumerate(lmaxs)])
     syn = P.Plan(nsides, lmaxs, mode="f64", strategy="staged")
     maps = syn.synthesize(torch.from_numpy(alm).cuda())
@@ -394,18 +415,33 @@ def uneven_main(args):
         torch.cuda.synchronize()
         dtg = time.perf_counter() - t0
         del graph
+        # per-stage times (HIP events) of as many steps again; each stage is one
+        # launch over the four nside groups, so its work is the groups' sum
+        plan.profile(True)
+        for _ in range(args.steps):
+            plan.analyze(maps, out=out)
+        torch.cuda.synchronize()
+        plan.profile(False)
+        prof = plan.profile_read()
+        stages = {st: uneven_roofline(st, mode, counts, ms, n, plan.strategy)
+                  for st, (ms, n) in prof.items() if n}
+        dom = max((st for st in stages if st.startswith("gemm")), key=lambda st: stages[st]["avg_launch_ms"])
         res[mode] = {"maps_per_s": len(nsides) * args.steps / dt, "ms_per_step": 1e3 * dt / args.steps,
                      "graph_maps_per_s": len(nsides) * args.steps / dtg, "graph_ms_per_step": 1e3 * dtg / args.steps,
-                     "setup_s": setup, "strategy": plan.strategy, "autotune": tuned}
+                     "setup_s": setup, "strategy": plan.strategy, "autotune": tuned, "roofline": stages[dom],
+                     "stages": {st: {"ms_per_step": v["avg_launch_ms"] * v["launches"] / args.steps,
+                                     "launches": v["launches"], "achieved": v["achieved"], "unit": v["unit"],
+                                     "frac": v["frac"]} for st, v in stages.items()}}
         print(f"[bench] uneven {mode}: {1e3 * dt / args.steps:.2f} ms/step, as one graph launch "
               f"{1e3 * dtg / args.steps:.2f} ms/step", file=sys.stderr, flush=True)
         plan.close()
         del plan
-    counts = {int(n): nsides.count(n) for n in sorted(set(nsides))}
     head = res.get("f32_refine") or next(iter(res.values()))
     print(json.dumps({"metric": "maps analysed/s, uneven batch (batching form)", "value": head["maps_per_s"],
                       "unit": "maps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-                      "ms_per_step": head["ms_per_step"], "higher_is_better": True, "data": "synthetic",
+                      "ms_per_step": head["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+                      "vs_baseline": None, "dtype": "f32+f64" if "f32_refine" in res else "f64", "data": "synthetic",
+                      "roofline": head["roofline"],
                       "config": {"workload": "uneven_b256_nside64-512", "batch": len(nsides), "nside_counts": counts,
                                  "lmax": "2 nside",
                                  "input": "seeded Gaussian a_lm, C_l=l^-2 exp(-l(l+1)s^2), s=0.005, GPU FP64 synthesis",
