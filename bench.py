@@ -30,7 +30,7 @@ sys.path.insert(0, ROOT)
 METRIC = "maps analysed/s at nside={nside}, L={lmax}: batched FP32+refine vs plain FP64"
 
 # MI355X published peaks.  The VALU figure for FP32 (157.3) counts packed
-# FP32 instructions, which this build never emits (packed-fp32-ops is off):
+# FP32 instructions, which the library is compiled never to emit (packed-fp32-ops off):
 # non-packed FP32 issues at the FP64 VALU rate, 78.6 TFLOP/s.
 PEAK_HBM_GBS = 8000.0
 PEAK_TFLOPS = {"mfma": {"f32": 157.3, "f64": 78.6}, "alu": {"f32": 78.6, "f64": 78.6}}
