@@ -334,9 +334,9 @@ int hp2sph_schedules(hp2sph_plan_t plan, int32_t* out, int32_t cap, int32_t* cou
  * (items grouped by nside, largest first).  Results are bitwise the same
  * under every value of the first three; HP2SPH_OPT_RING_THREADS changes the
  * FFT's pass structure, so its results agree to rounding (a few ulp of the
- * ring coefficients), not bit for bit.  hp2sph_autotune chooses them after the GEMM schedules
- * and remembers its choices per plan shape.  Host state only, like
- * hp2sph_set_schedule.
+ * ring coefficients), not bit for bit.  hp2sph_autotune chooses them after
+ * the GEMM schedules and remembers its choices per plan shape.  Host state
+ * only, like hp2sph_set_schedule.
  *   HP2SPH_OPT_FOLD_GRID  work grid of the refinement's residual fold (an
  *       item is one ring pair of 16 maps, or of one map in the staged
  *       layout): 0 for one workgroup per item (the default), or g >= 8 for a
